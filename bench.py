@@ -1,0 +1,211 @@
+"""Benchmark: SSA events/s of the split multicellular simulation on one MI355X.
+
+Workload (default): the 64x64 hex tissue of 4096 cells, 4x4 voxels per cell,
+the 5-species Notch-Delta network with 9 internal reactions + the trans
+reaction, diffusion 1.0, dt = 0.05, T = 100 (2000 splitting steps), seeded
+synthetic inputs.  One benchmark step = restart the resident tissue from its
+initial counts as a new simulation (sim_id = step index) and advance it over
+the whole horizon T (tissue_step(dt, 2000), replayed from captured HIP
+graphs).  value = (chi + S events) / wall time of the K timed steps.
+
+Also reported: the chi kernel's roofline fraction (HIP events around every
+launch of one extra, eagerly launched step; VALU-bound, see the design
+notes), the CPU FP64 oracle's rate on a bounded sample on the host cores,
+and -- unless --plain-only -- the batched form (many tissues in one graph)
+with per-simulation latency.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SSA events/sec on 1 MI355X (batched vs plain); p50/p99 sim latency"
+
+# Algorithmic VALU work per accepted event, in full-rate lane-operation
+# equivalents (a quarter-rate instruction counts 4), for the 5-species
+# network on 4x4-voxel cells; derivation in the design notes.
+OPS_PER_CHI_EVENT = 480
+OPS_PER_S_EVENT = 260
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pct(a, q):
+    a = sorted(a)
+    if not a:
+        return None
+    k = (len(a) - 1) * q / 100.0
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return a[lo] + (a[hi] - a[lo]) * (k - lo)
+
+
+def run_plain(args, torch, T, W):
+    p = W.config2(n_steps=args.n_steps)
+    stream = torch.cuda.current_stream()
+    t = T.Tissue(p, device="cuda:0", stream=stream)
+    t.set_launch(True, 0)
+    t.set_graph_chunk(args.graph_chunk)
+    dt, n = p["dt"], p["n_steps"]
+
+    def one(k):
+        t.restart(sim_id=k, start_step=0)
+        t.step(dt, n)
+        st = t.stats()  # synchronises the stream
+        return st["chi_events"] + st["s_events"], st
+
+    for w in range(args.warmup):
+        one(1000 + w)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    lat, events, chi_ev, s_ev = [], 0, 0, 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        a = time.perf_counter()
+        ev, st = one(k)
+        lat.append(time.perf_counter() - a)
+        events += ev
+        chi_ev += st["chi_events"]
+        s_ev += st["s_events"]
+        log(f"step {k + 1}/{args.steps}: {ev} events in {lat[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # roofline pass: one more simulation, every kernel bracketed by HIP events
+    t.restart(sim_id=args.steps + 7, start_step=0)
+    tm = t.step_timed(dt, min(n, args.roofline_steps))
+    st = t.stats()
+    chi_per_launch = st["chi_events"] / max(tm["chi_launches"], 1)
+    chi_avg_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
+    s_avg_ms = tm["s_ms"] / max(tm["s_launches"], 1)
+    achieved = chi_per_launch * OPS_PER_CHI_EVENT / (chi_avg_ms * 1e-3)
+    roof = {
+        "bound": "alu", "kernel": "chi_kernel<16>",
+        "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+        "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+        "avg_launch_ms": chi_avg_ms, "events_per_launch": chi_per_launch,
+        "ops_per_event": OPS_PER_CHI_EVENT, "s_kernel_avg_ms": s_avg_ms,
+        "chi_share_of_kernel_time": tm["chi_ms"] / max(tm["chi_ms"] + tm["s_ms"], 1e-12),
+    }
+    res = dict(p=p, value=events / elapsed, elapsed=elapsed, lat=lat, chi=chi_ev, s=s_ev,
+               roofline=roof, timing=tm)
+    t.close()
+    return res
+
+
+def run_batched(args, torch, T, W):
+    """Config-4-shaped sweep: independent tissues in one batch (one graph per
+    chunk of steps); latency = completion of the whole sweep per tissue."""
+    probs = W.config4(n_tissues=args.batch_tissues, n_steps=args.batch_steps)
+    stream = torch.cuda.current_stream()
+    ts = [T.Tissue(p, device="cuda:0", stream=stream) for p in probs]
+    b = T.Batch(ts, device="cuda:0", stream=stream)
+    dt, n = probs[0]["dt"], probs[0]["n_steps"]
+
+    def one(k):
+        for i, t in enumerate(ts):
+            t.restart(sim_id=i + 1000 * k, start_step=0)
+        a = time.perf_counter()
+        b.step(dt, n)
+        b.sync()
+        wall = time.perf_counter() - a
+        ev = 0
+        for t in ts:
+            st = t.stats()
+            ev += st["chi_events"] + st["s_events"]
+        return ev, wall
+
+    one(99)
+    tot_ev, tot_t, walls = 0, 0.0, []
+    for k in range(max(1, args.batch_reps)):
+        ev, wall = one(k)
+        tot_ev += ev
+        tot_t += wall
+        walls.append(wall)
+        log(f"batched rep {k + 1}: {ev} events in {wall * 1e3:.1f} ms")
+    cells = sum(p["nx"] * p["ny"] for p in probs)
+    out = dict(events_per_s=tot_ev / tot_t, tissues=len(probs), cells=cells, steps=n, dt=dt,
+               sweep_ms_p50=pct(walls, 50) * 1e3, sweep_ms_p99=pct(walls, 99) * 1e3)
+    b.close()
+    for t in ts:
+        t.close()
+    return out
+
+
+def cpu_baseline(args, W, p):
+    import oracle
+    oracle.build(force=False)
+    steps = args.cpu_steps
+    a = time.perf_counter()
+    r = oracle.run(p, p["dt"], steps, threads=0)
+    el = time.perf_counter() - a
+    return {"value": (r.chi_events + r.s_events) / el, "unit": "events/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"first {steps} splitting steps of the same 4096-cell tissue "
+                      f"({r.chi_events + r.s_events} events, {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-steps", type=int, default=2000, help="splitting steps per simulation")
+    ap.add_argument("--graph-chunk", type=int, default=50)
+    ap.add_argument("--roofline-steps", type=int, default=200)
+    ap.add_argument("--plain-only", action="store_true")
+    ap.add_argument("--batch-tissues", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-reps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures "
+              "the single-GPU hot path; multi-GPU sharding is a design note, not a run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_10889_amd import tissue as T
+    from paper_1806_10889_amd import workloads as W
+    torch.cuda.set_device(0)
+
+    plain = run_plain(args, torch, T, W)
+    out = {
+        "metric": METRIC, "value": plain["value"], "unit": "events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": plain["elapsed"] / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "hex 64x64 tissue, 4096 cells x 4x4 voxels, 5 species, "
+                               "9+1 reactions, D=1.0, dt=0.05, T=100 (2000 splitting steps)",
+                   "cells": 4096, "voxels_per_cell": 16, "species": 5, "dt": 0.05,
+                   "T": 0.05 * args.n_steps, "splitting_steps": args.n_steps,
+                   "launch": f"persistent, hipGraph chunks of {args.graph_chunk} steps"},
+        "plain": {"events_per_s": plain["value"], "chi_events": plain["chi"], "s_events": plain["s"],
+                  "sim_latency_ms_p50": pct(plain["lat"], 50) * 1e3,
+                  "sim_latency_ms_p99": pct(plain["lat"], 99) * 1e3},
+        "roofline": plain["roofline"],
+    }
+    if not args.plain_only:
+        out["batched"] = run_batched(args, torch, T, W)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, W, plain["p"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * tissue.h -- C-ABI of libtissue.so, the MI355X (gfx950) implementation of the
+ * operator-split multicellular stochastic simulation of Coulier & Hellander,
+ * "Orchestral: a lightweight framework for parallel simulations of cell-cell
+ * communication".
+ *
+ * The problem statement follows the paper's orchestration section: a tissue
+ * is a network of cells with neighbours and per-cell parameters, among them
+ * a seed (Fig. 2, the network file); it is advanced n_steps times by a
+ * splitting interval dt (Fig. 3, the configuration file's n_steps; each
+ * module run with an end time); then its state is read back.  One splitting
+ * step is the internal-dynamics operator chi on every cell independently,
+ * followed by the pairwise signalling operator S (Algorithm section,
+ * splitting assumption; Fig. 1: chi first, then S).
+ *
+ *   chi : per cell, a Gillespie direct-method SSA over the cell's voxels
+ *         (RDME: reactions inside a voxel, diffusion jumps between adjacent
+ *         voxels) on [0, dt)  (Introduction: SSA and RDME as single-cell
+ *         modules; "Internal cell dynamics module").
+ *   S   : per lattice edge, an SSA on [0, dt) of the trans reaction
+ *         N_i + D_j -> I_i between the voxels of the two cells' facing
+ *         membrane groups ("Cell signaling module"; Results, Model: Delta
+ *         near the shared face turns into the neighbour's NICD, each molecule
+ *         handled by a single face's signalling model).
+ *
+ * Numerical contract (identical bits to the CPU FP64 oracle): Philox4x32-10
+ * counter (draw j, global step n, cell or edge id, sim_id << 2 | tag) keyed
+ * by the seed; U1 = (m1 + 1) 2^-53, U2 = m2 2^-53 from the two 53-bit halves;
+ * tau = -plog(U1) / a0; per-voxel propensity = left fold over the channels
+ * (reactions, then one aggregated diffusion channel per diffusing species);
+ * a0 = binary sum tree over the next power of two >= V leaves; the selection
+ * and tie rules are written out in the design notes.
+ *
+ * Conventions for every entry point:
+ *   - all functions return TISSUE_OK (0) or a negative TISSUE_E* code; a
+ *     thread-local detail string is available from tissue_last_error();
+ *   - host arrays passed in are copied; the caller keeps ownership;
+ *   - device memory comes from the caller (dev_buf) and must outlive the
+ *     handle; the library allocates no device memory of its own for a
+ *     tissue (graphs and the launch plan live in host memory);
+ *   - work is enqueued on the tissue's HIP stream; reads synchronise it;
+ *   - handles are not thread-safe; distinct handles are independent;
+ *   - results depend only on the descriptor and the sequence of
+ *     (dt, n_steps) calls -- never on batching, streams or launch shapes.
+ */
+#ifndef TISSUE_H
+#define TISSUE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TISSUE_ABI_VERSION 1u
+
+enum {
+    TISSUE_OK = 0,
+    TISSUE_EINVAL = -1,    /* invalid descriptor or argument; nothing enqueued */
+    TISSUE_ENOMEM = -2,    /* dev_bytes smaller than tissue_required_bytes()   */
+    TISSUE_EOVERFLOW = -3, /* a count left [0, 2^26); state unspecified        */
+    TISSUE_EDEVICE = -4,   /* a HIP call failed (detail in tissue_last_error)  */
+    TISSUE_EBUSY = -5,     /* resource exhausted; retry later                  */
+    TISSUE_ESTATE = -6,    /* call not valid in the handle's state             */
+    TISSUE_ELIMIT = -7     /* a unit-step reached event_cap and was stopped     */
+};
+
+enum { TISSUE_LATTICE_SQUARE = 0, TISSUE_LATTICE_HEX = 1 };
+
+/* descriptor flags */
+#define TISSUE_FLAG_TRACE 1u /* keep per-(unit, step) event counts and clocks */
+
+#define TISSUE_MAX_SPECIES 8
+#define TISSUE_MAX_REACTIONS 16
+#define TISSUE_MAX_MESH 8
+#define TISSUE_COUNT_LIMIT (1 << 26)
+#define TISSUE_DEFAULT_EVENT_CAP (1u << 20)
+
+typedef struct tissue tissue_t;
+typedef struct tissue_batch tissue_batch_t;
+
+/*
+ * Tissue descriptor.  Cells: i = y*nx + x (hex: axial q = x, r = y, rhombus).
+ * Square directions 0 +x, 1 +y, 2 -x, 3 -y; hex 0 E(+1,0), 1 SE(0,+1),
+ * 2 SW(-1,+1), 3 W(-1,0), 4 NW(0,-1), 5 NE(+1,-1); open boundaries.
+ * Cell c has a w x h voxel mesh, voxel v = y*w + x.
+ */
+typedef struct {
+    uint32_t abi_version;     /* = TISSUE_ABI_VERSION                          */
+    uint32_t lattice;         /* TISSUE_LATTICE_SQUARE or TISSUE_LATTICE_HEX   */
+    uint32_t nx, ny;          /* lattice extent, nx*ny >= 1                     */
+    const uint8_t *mesh_w;    /* [nx*ny] per-cell mesh width 1..8, or NULL     */
+    const uint8_t *mesh_h;    /* [nx*ny] per-cell mesh height 1..8, or NULL    */
+    uint32_t mesh_w0, mesh_h0;/* uniform mesh when mesh_w/mesh_h are NULL      */
+    uint32_t n_species;       /* 1..TISSUE_MAX_SPECIES                          */
+    uint32_t n_reactions;     /* 0..TISSUE_MAX_REACTIONS (intracellular)        */
+    const int32_t *reactants; /* [n_reactions][2] species index or -1 (order 0..2) */
+    const int32_t *stoich;    /* [n_reactions][n_species] net change; a species
+                                 may only lose as many as it supplies as reactant */
+    const double *rates;      /* [n_reactions] in [0, 1e12]: propensity constants */
+    const double *diffusion;  /* [n_species] in [0, 1e12]: jump rate per direction */
+    int32_t trans_n, trans_d, trans_i; /* S reaction N_i + D_j -> I_i; trans_n < 0
+                                          disables S; otherwise three distinct species */
+    uint32_t flags;           /* TISSUE_FLAG_*                                  */
+    double trans_rate;        /* in [0, 1e12]                                   */
+    const int32_t *init_counts; /* [sum_c V_c][n_species], each in [0, 2^26)   */
+    uint64_t seed;            /* Philox key                                     */
+    uint32_t sim_id;          /* < 2^30, part of every counter                  */
+    uint32_t start_step;      /* global index of the next step (resume)         */
+    uint32_t event_cap;       /* events per unit-step; 0 = TISSUE_DEFAULT_EVENT_CAP */
+    uint32_t trace_steps;     /* steps of trace kept when TISSUE_FLAG_TRACE     */
+} tissue_desc_t;
+
+typedef struct {
+    uint64_t chi_events;      /* accepted chi events since create/restart       */
+    uint64_t s_events;        /* accepted S events                              */
+    uint64_t draws;           /* Philox blocks drawn (events + overshoots)      */
+    uint32_t steps_done;      /* global index of the next step                  */
+    uint32_t overflow;        /* nonzero: a count left [0, 2^26)                */
+    uint32_t capped;          /* nonzero: a unit-step hit event_cap             */
+    uint32_t n_cells, n_edges, n_voxels;
+} tissue_stats_t;
+
+/* Device bytes a tissue needs in dev_buf (admission by free memory).
+ * Returns 0 for an invalid descriptor. */
+size_t tissue_required_bytes(const tissue_desc_t *d);
+
+/* Validate d, build the lattice, edges, colour classes, meshes and face
+ * groups on the host, lay the state out in dev_buf (>= required bytes,
+ * 256-byte aligned) and upload it on hip_stream (NULL: the null stream). */
+int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes,
+                  void *hip_stream, tissue_t **out);
+
+/* Enqueue n_steps splitting steps of length dt (finite, > 0); n_steps >= 0.
+ * Step indices continue from steps_done.  Asynchronous. */
+int tissue_step(tissue_t *t, double dt, int32_t n_steps);
+
+/* Synchronise and copy the counts out, layout as init_counts.  n_out must be
+ * sum_c V_c * n_species.  Returns TISSUE_EOVERFLOW / TISSUE_ELIMIT if that
+ * condition was flagged (the counts are still copied). */
+int tissue_read_counts(tissue_t *t, int32_t *host_out, size_t n_out);
+
+/* Synchronise and report the running totals. */
+int tissue_read_stats(tissue_t *t, tissue_stats_t *out);
+
+/* Trace of the last trace_steps steps (tissues created with
+ * TISSUE_FLAG_TRACE): for global steps [first_step, first_step + n_steps),
+ * chi_events/chi_t_bits are [n_steps][n_cells] and s_events/s_t_bits
+ * [n_steps][n_edges] (clock after the last accepted event, as bits).  Any
+ * output pointer may be NULL. */
+int tissue_read_trace(tissue_t *t, uint32_t first_step, uint32_t n_steps,
+                      uint32_t *chi_events, uint64_t *chi_t_bits,
+                      uint32_t *s_events, uint64_t *s_t_bits);
+
+/* Restore the counts given at create (kept on the device), zero the
+ * statistics and flags, and continue as simulation sim_id from step
+ * start_step.  Enqueued on the tissue's stream. */
+int tissue_restart(tissue_t *t, uint32_t sim_id, uint32_t start_step);
+
+/* Overwrite the counts from host memory (same layout as init_counts). */
+int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in);
+
+/* Launch shape of the chi operator: 0 = one workgroup per work item,
+ * 1 = persistent workgroups pulling items from a device queue (the
+ * default), with workgroups_per_cu resident workgroups per CU (0 = auto).
+ * Results are bit-identical for every choice. */
+int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu);
+
+/* Steps captured per HIP graph launch (0 disables graphs). */
+int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
+
+/* Per-kernel device time of the last tissue_step_timed call, in ms. */
+typedef struct {
+    double chi_ms, s_ms, total_ms;
+    uint32_t chi_launches, s_launches;
+} tissue_timing_t;
+
+/* tissue_step, launched eagerly with a HIP event pair around every kernel;
+ * synchronises and returns the summed per-kernel device times. */
+int tissue_step_timed(tissue_t *t, double dt, int32_t n_steps, tissue_timing_t *out);
+
+int tissue_destroy(tissue_t *t);
+
+/*
+ * Batches: many tissues advanced together -- every chi launch and every S
+ * launch covers the work items of all member tissues, and n_steps steps are
+ * captured in HIP graphs.  Member tissues keep their own state, stream-free
+ * (the batch's stream is used); each still sees exactly its own sequence of
+ * steps, so its bits equal those of a lone tissue_step.  The batch needs
+ * tissue_batch_required_bytes() of device memory for its work lists.
+ */
+size_t tissue_batch_required_bytes(tissue_t *const *ts, int32_t n);
+int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t dev_bytes,
+                        void *hip_stream, tissue_batch_t **out);
+int tissue_batch_step(tissue_batch_t *b, double dt, int32_t n_steps);
+int tissue_batch_step_timed(tissue_batch_t *b, double dt, int32_t n_steps, tissue_timing_t *out);
+int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workgroups_per_cu);
+int tissue_batch_sync(tissue_batch_t *b);
+int tissue_batch_destroy(tissue_batch_t *b);
+
+const char *tissue_strerror(int code);
+const char *tissue_last_error(void);
+
+/* Number of compute units of the current device (for launch planning). */
+int tissue_device_cus(int32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TISSUE_H */

@@ -1,0 +1,1082 @@
+// host.cpp -- runtime behind the C-ABI of include/tissue.h.
+//
+// tissue_create validates the descriptor, builds the geometry on the host
+// (lattice edges ranked by (colour, i), membrane rings, face groups, the
+// colour-class passes of S), cuts the work into items, lays everything out
+// in the caller's device buffer and uploads it.  tissue_step enqueues the
+// splitting steps -- per step one chi launch per leaf-count class and one S
+// launch per pass -- either eagerly or as replays of a captured HIP graph of
+// a fixed number of steps.  Batches reuse the same kernels over a table of
+// many tissues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/tissue.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace tissue_impl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(TISSUE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr size_t kChiLdsBudget = 40 * 1024;  // per workgroup: >= 4 resident per CU
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+
+// lattice direction offsets (square: +x, +y, -x, -y; hex axial: E, SE, SW,
+// W, NW, NE with y pointing down)
+const int kSquareDir[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+const int kHexDir[6][2] = {{1, 0}, {0, 1}, {-1, 1}, {-1, 0}, {0, -1}, {1, -1}};
+
+// perimeter of a w x h mesh, clockwise from the top-right voxel: down the
+// right column, left along the bottom row, up the left column, right along
+// the top row; a voxel is listed once.
+std::vector<int> membrane_ring(int w, int h)
+{
+    std::vector<int> ring;
+    std::vector<char> on(w * h, 0);
+    auto push = [&](int x, int y) {
+        const int v = y * w + x;
+        if (!on[v]) {
+            on[v] = 1;
+            ring.push_back(v);
+        }
+    };
+    for (int y = 0; y < h; ++y) push(w - 1, y);
+    for (int x = w - 2; x >= 0; --x) push(x, h - 1);
+    for (int y = h - 2; y >= 0; --y) push(0, y);
+    for (int x = 1; x < w - 1; ++x) push(x, 0);
+    return ring;
+}
+
+// voxels of the face toward lattice direction d (of nd): the d-th of nd
+// consecutive slices of the ring (a one-voxel group when the slice is empty)
+std::vector<int> face_voxels(const std::vector<int> &ring, int nd, int d)
+{
+    const int M = (int)ring.size();
+    const int lo = d * M / nd, hi = (d + 1) * M / nd;
+    if (hi <= lo) return {ring[lo % M]};
+    return std::vector<int>(ring.begin() + lo, ring.begin() + hi);
+}
+
+struct Edge {
+    int colour, i, j, d;
+};
+
+std::vector<Edge> lattice_edges(int lattice, int nx, int ny)
+{
+    const int nfwd = lattice == TISSUE_LATTICE_SQUARE ? 2 : 3;
+    std::vector<Edge> out;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int d = 0; d < nfwd; ++d) {
+                const int *off = lattice == TISSUE_LATTICE_SQUARE ? kSquareDir[d] : kHexDir[d];
+                const int X = x + off[0], Y = y + off[1];
+                if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
+                const int parity = (d == 0 ? x : y) & 1;
+                out.push_back(Edge{2 * d + parity, y * nx + x, Y * nx + X, d});
+            }
+    std::sort(out.begin(), out.end(), [](const Edge &a, const Edge &b) {
+        return a.colour != b.colour ? a.colour < b.colour : a.i < b.i;
+    });
+    return out;
+}
+
+// rate constants are bounded so that every propensity (at most 1e12 * 2^52)
+// and every sum of them stays finite
+constexpr double kMaxRate = 1e12;
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0 && x <= kMaxRate; }
+
+// ---------------------------------------------------------------------------
+// plan: everything tissue_create derives from the descriptor on the host
+// ---------------------------------------------------------------------------
+
+struct ChiGroupHost {
+    int P;
+    int cells_per_item;
+    int max_species;
+    std::vector<ChiItem> items;
+};
+
+struct Plan {
+    uint32_t lattice = 0, nx = 0, ny = 0, ncell = 0, S = 0, nvox = 0, nedge = 0;
+    std::vector<uint8_t> wh;
+    std::vector<int32_t> vox_off;
+    std::vector<int32_t> cell_list;
+    std::vector<EdgeRec> edges;
+    std::vector<uint32_t> class_start;  // [n_colours + 1] edge ranges per colour
+    bool disjoint = true;               // every cell's face groups pairwise disjoint
+    bool has_s = false;
+    std::vector<ChiGroupHost> chi;
+    std::vector<std::vector<SItem>> s_passes;
+    DevModel model{};
+    uint32_t trace_steps = 0;
+    // byte offsets inside dev_buf
+    size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
+           off_cells = 0, off_edges = 0, off_chi = 0, off_s = 0, off_ctl = 0, off_trace = 0, bytes = 0;
+    size_t n_chi_items = 0, n_s_items = 0;
+};
+
+int build_plan(const tissue_desc_t *d, Plan &p)
+{
+    if (!d) return fail(TISSUE_EINVAL, "null descriptor");
+    if (d->abi_version != TISSUE_ABI_VERSION) return fail(TISSUE_EINVAL, "abi_version mismatch");
+    if (d->lattice != TISSUE_LATTICE_SQUARE && d->lattice != TISSUE_LATTICE_HEX)
+        return fail(TISSUE_EINVAL, "lattice must be 0 (square) or 1 (hex)");
+    if (d->nx < 1 || d->ny < 1 || (uint64_t)d->nx * d->ny > (1u << 24))
+        return fail(TISSUE_EINVAL, "nx, ny must be >= 1 with nx*ny <= 2^24");
+    if (d->n_species < 1 || d->n_species > TISSUE_MAX_SPECIES)
+        return fail(TISSUE_EINVAL, "n_species must be in 1..8");
+    if (d->n_reactions > TISSUE_MAX_REACTIONS) return fail(TISSUE_EINVAL, "n_reactions must be <= 16");
+    if (d->sim_id >= (1u << 30)) return fail(TISSUE_EINVAL, "sim_id must be < 2^30");
+    if (!d->init_counts) return fail(TISSUE_EINVAL, "init_counts is null");
+    if ((d->mesh_w == nullptr) != (d->mesh_h == nullptr))
+        return fail(TISSUE_EINVAL, "mesh_w and mesh_h must both be given or both be null");
+    if ((d->flags & TISSUE_FLAG_TRACE) && d->trace_steps < 1)
+        return fail(TISSUE_EINVAL, "trace needs trace_steps >= 1");
+    const int S = (int)d->n_species, R = (int)d->n_reactions;
+    if (R > 0 && (!d->reactants || !d->stoich || !d->rates))
+        return fail(TISSUE_EINVAL, "reaction tables are null");
+    if (!d->diffusion) return fail(TISSUE_EINVAL, "diffusion is null");
+
+    p.lattice = d->lattice;
+    p.nx = d->nx;
+    p.ny = d->ny;
+    p.ncell = d->nx * d->ny;
+    p.S = (uint32_t)S;
+
+    // model
+    DevModel &M = p.model;
+    M.n_species = S;
+    M.n_reactions = R;
+    for (int r = 0; r < R; ++r) {
+        const int a = d->reactants[2 * r], b = d->reactants[2 * r + 1];
+        if (a < -1 || a >= S || b < -1 || b >= S) return fail(TISSUE_EINVAL, "reactant index out of range");
+        if (!finite_nonneg(d->rates[r])) return fail(TISSUE_EINVAL, "rates must be finite, >= 0 and <= 1e12");
+        // canonical order: a first reactant, b second or -1
+        int ra = a, rb = b;
+        if (ra < 0) std::swap(ra, rb);
+        M.reac_a[r] = (int8_t)ra;
+        M.reac_b[r] = (int8_t)rb;
+        M.rates[r] = d->rates[r];
+        uint32_t code = 0;
+        int nchg = 0;
+        for (int s = 0; s < S; ++s) {
+            const int delta = d->stoich[r * S + s];
+            if (delta == 0) continue;
+            if (delta < -15 || delta > 15) return fail(TISSUE_EINVAL, "stoich entries must be in -15..15");
+            const int supplied = (a == s) + (b == s);
+            if (delta < -supplied)
+                return fail(TISSUE_EINVAL, "a reaction consumes a species it does not have as reactant");
+            if (nchg == 4) return fail(TISSUE_EINVAL, "a reaction may change at most 4 species");
+            code |= (uint32_t)((s << 5) | (delta + 16)) << (8 * nchg);
+            ++nchg;
+        }
+        for (; nchg < 4; ++nchg) code |= 16u << (8 * nchg);
+        M.change_code[r] = code;
+    }
+    M.n_diff = 0;
+    for (int s = 0; s < S; ++s) {
+        if (!finite_nonneg(d->diffusion[s])) return fail(TISSUE_EINVAL, "diffusion must be finite, >= 0 and <= 1e12");
+        if (d->diffusion[s] > 0.0) {
+            M.diff_species[M.n_diff] = (int8_t)s;
+            M.diff_rate[M.n_diff] = d->diffusion[s];
+            ++M.n_diff;
+        }
+    }
+    p.has_s = d->trans_n >= 0;
+    if (p.has_s) {
+        const int tn = d->trans_n, td = d->trans_d, ti = d->trans_i;
+        if (tn >= S || td < 0 || td >= S || ti < 0 || ti >= S || tn == td || tn == ti || td == ti)
+            return fail(TISSUE_EINVAL, "trans_n, trans_d, trans_i must be distinct species");
+        if (!finite_nonneg(d->trans_rate)) return fail(TISSUE_EINVAL, "trans_rate must be finite, >= 0 and <= 1e12");
+        M.trans_n = tn;
+        M.trans_d = td;
+        M.trans_i = ti;
+        M.trans_rate = d->trans_rate;
+    } else {
+        M.trans_n = M.trans_d = M.trans_i = -1;
+        M.trans_rate = 0.0;
+    }
+
+    // cells and voxels
+    p.wh.resize(2 * (size_t)p.ncell);
+    p.vox_off.resize(p.ncell);
+    uint64_t nvox = 0;
+    for (uint32_t c = 0; c < p.ncell; ++c) {
+        const uint32_t w = d->mesh_w ? d->mesh_w[c] : d->mesh_w0;
+        const uint32_t h = d->mesh_h ? d->mesh_h[c] : d->mesh_h0;
+        if (w < 1 || w > TISSUE_MAX_MESH || h < 1 || h > TISSUE_MAX_MESH)
+            return fail(TISSUE_EINVAL, "mesh sides must be in 1..8");
+        p.wh[2 * c] = (uint8_t)w;
+        p.wh[2 * c + 1] = (uint8_t)h;
+        p.vox_off[c] = (int32_t)nvox;
+        nvox += (uint64_t)w * h;
+    }
+    if (nvox * (uint64_t)S >= (1ull << 31)) return fail(TISSUE_EINVAL, "too many voxels");
+    p.nvox = (uint32_t)nvox;
+    for (uint64_t i = 0; i < nvox * S; ++i)
+        if (d->init_counts[i] < 0 || d->init_counts[i] >= TISSUE_COUNT_LIMIT)
+            return fail(TISSUE_EINVAL, "init_counts must be in [0, 2^26)");
+
+    // chi items: cells grouped by leaf count P, cut into items
+    std::map<int, std::vector<int32_t>> by_p;
+    for (uint32_t c = 0; c < p.ncell; ++c) by_p[pow2_at_least(p.wh[2 * c] * p.wh[2 * c + 1])].push_back((int32_t)c);
+    for (auto it = by_p.rbegin(); it != by_p.rend(); ++it) {  // largest cells first
+        ChiGroupHost g;
+        g.P = it->first;
+        g.max_species = S;
+        const size_t per_cell = chi_lds_bytes(g.P, S, 1);
+        int cpi = 64;
+        while (cpi > 1 && (size_t)cpi * per_cell > kChiLdsBudget) cpi >>= 1;
+        g.cells_per_item = cpi;
+        const uint32_t first = (uint32_t)p.cell_list.size();
+        p.cell_list.insert(p.cell_list.end(), it->second.begin(), it->second.end());
+        const uint32_t n = (uint32_t)it->second.size();
+        for (uint32_t o = 0; o < n; o += cpi)
+            g.items.push_back(ChiItem{0, first + o, std::min<uint32_t>(cpi, n - o), 0});
+        p.n_chi_items += g.items.size();
+        p.chi.push_back(std::move(g));
+    }
+
+    // edges, face groups, S passes
+    const int nd = p.lattice == TISSUE_LATTICE_SQUARE ? 4 : 6;
+    const int ncol = nd;
+    if (p.has_s) {
+        std::map<int, std::vector<std::vector<int>>> faces;  // (w*16+h) -> [nd] groups
+        for (uint32_t c = 0; c < p.ncell; ++c) {
+            const int key = p.wh[2 * c] * 16 + p.wh[2 * c + 1];
+            if (faces.count(key)) continue;
+            const std::vector<int> ring = membrane_ring(p.wh[2 * c], p.wh[2 * c + 1]);
+            std::vector<std::vector<int>> g(nd);
+            for (int dd = 0; dd < nd; ++dd) g[dd] = face_voxels(ring, nd, dd);
+            // disjointness of all face groups of this mesh
+            std::vector<int> seen(64, 0);
+            for (int dd = 0; dd < nd; ++dd)
+                for (int v : g[dd]) {
+                    if (seen[v]) p.disjoint = false;
+                    seen[v] = 1;
+                }
+            faces[key] = std::move(g);
+        }
+        const std::vector<Edge> E = lattice_edges((int)p.lattice, (int)p.nx, (int)p.ny);
+        p.nedge = (uint32_t)E.size();
+        p.edges.resize(E.size());
+        p.class_start.assign(ncol + 1, 0);
+        for (size_t e = 0; e < E.size(); ++e) {
+            const Edge &ed = E[e];
+            EdgeRec r{};
+            r.vox_i = p.vox_off[ed.i];
+            r.vox_j = p.vox_off[ed.j];
+            const auto &gi = faces[p.wh[2 * ed.i] * 16 + p.wh[2 * ed.i + 1]][ed.d];
+            const auto &gj = faces[p.wh[2 * ed.j] * 16 + p.wh[2 * ed.j + 1]][(ed.d + nd / 2) % nd];
+            if (gi.size() > (size_t)kMaxFace || gj.size() > (size_t)kMaxFace)
+                return fail(TISSUE_EINVAL, "face group larger than supported");
+            r.m_a = (uint8_t)gi.size();
+            r.m_b = (uint8_t)gj.size();
+            for (size_t q = 0; q < gi.size(); ++q) r.A[q] = (uint8_t)gi[q];
+            for (size_t q = 0; q < gj.size(); ++q) r.B[q] = (uint8_t)gj[q];
+            p.edges[e] = r;
+            p.class_start[ed.colour + 1]++;
+        }
+        for (int c = 0; c < ncol; ++c) p.class_start[c + 1] += p.class_start[c];
+        auto cut = [](uint32_t lo, uint32_t hi, std::vector<SItem> &out) {
+            for (uint32_t o = lo; o < hi; o += kWave)
+                out.push_back(SItem{0, o, std::min<uint32_t>(kWave, hi - o), 0});
+        };
+        if (p.disjoint) {
+            std::vector<SItem> pass;
+            cut(0, p.nedge, pass);
+            if (!pass.empty()) p.s_passes.push_back(std::move(pass));
+        } else {
+            for (int c = 0; c < ncol; ++c) {
+                std::vector<SItem> pass;
+                cut(p.class_start[c], p.class_start[c + 1], pass);
+                if (!pass.empty()) p.s_passes.push_back(std::move(pass));
+            }
+        }
+        for (auto &ps : p.s_passes) p.n_s_items += ps.size();
+    }
+
+    // device layout
+    if (d->flags & TISSUE_FLAG_TRACE) p.trace_steps = d->trace_steps;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    p.off_tissue = take(sizeof(DevTissue));
+    p.off_tbl = take(sizeof(DevTissue *));
+    p.off_counts = take((size_t)p.nvox * S * 4);
+    p.off_init = take((size_t)p.nvox * S * 4);
+    p.off_voxoff = take((size_t)p.ncell * 4);
+    p.off_wh = take((size_t)p.ncell * 2);
+    p.off_cells = take((size_t)p.ncell * 4);
+    p.off_edges = take((size_t)p.nedge * sizeof(EdgeRec));
+    p.off_chi = take(p.n_chi_items * sizeof(ChiItem));
+    p.off_s = take(p.n_s_items * sizeof(SItem));
+    p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue[2] u32
+    p.off_trace = take((size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12));
+    p.bytes = o;
+    return TISSUE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch plan: what one "step" enqueues, for a tissue or a batch
+// ---------------------------------------------------------------------------
+
+struct ChiLaunch {
+    int P, cells_per_item;
+    size_t lds;
+    const ChiItem *items;
+    uint32_t n_items;
+};
+
+struct SLaunch {
+    const SItem *items;
+    uint32_t n_items;
+};
+
+struct GraphKey {
+    uint64_t dt_bits;
+    int32_t steps;
+    bool operator<(const GraphKey &o) const
+    {
+        return dt_bits != o.dt_bits ? dt_bits < o.dt_bits : steps < o.steps;
+    }
+};
+
+struct LaunchPlan {
+    DevTissue **tbl = nullptr;  // device table of DevTissue pointers
+    uint32_t n_tissues = 0;
+    std::vector<ChiLaunch> chi;
+    std::vector<SLaunch> s;
+    uint32_t *queue = nullptr;  // device: [0] next item, [1] workgroups done
+    hipStream_t stream = nullptr;
+    int persistent = 1;
+    int wpc = 0;                // workgroups per CU in persistent mode (0 auto)
+    int cus = 0;
+    int graph_chunk = 50;
+    hipStream_t capture_stream = nullptr;
+    std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+
+    ~LaunchPlan() { clear_graphs(); if (capture_stream) (void)hipStreamDestroy(capture_stream); }
+
+    void clear_graphs()
+    {
+        for (auto &kv : graphs) {
+            (void)hipGraphExecDestroy(kv.second.second);
+            (void)hipGraphDestroy(kv.second.first);
+        }
+        graphs.clear();
+    }
+
+    uint32_t chi_grid(const ChiLaunch &L) const
+    {
+        if (!persistent) return L.n_items;
+        int per_cu = wpc;
+        if (per_cu <= 0) per_cu = (int)std::min<size_t>(16, std::max<size_t>(1, kLdsPerCu / std::max<size_t>(L.lds, 1)));
+        return std::max<uint32_t>(1, std::min<uint32_t>(L.n_items, (uint32_t)(cus * per_cu)));
+    }
+
+    uint32_t s_grid(const SLaunch &L) const
+    {
+        if (!persistent) return L.n_items;
+        const int per_cu = wpc > 0 ? wpc : 8;
+        return std::max<uint32_t>(1, std::min<uint32_t>(L.n_items, (uint32_t)(cus * per_cu)));
+    }
+
+    // Enqueue n steps (k = 0..n-1) then step_base += n.  With events
+    // (2 per launch, in launch order) each kernel is bracketed.
+    int enqueue(hipStream_t st, double dt, int32_t n, std::vector<hipEvent_t> *ev = nullptr,
+                std::vector<int> *kind = nullptr)
+    {
+        size_t e = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            for (const ChiLaunch &L : chi) {
+                if (L.n_items == 0) continue;
+                if (ev) HIP_TRY(hipEventRecord((*ev)[e++], st));
+                HIP_TRY(launch_chi(L.P, chi_grid(L), L.lds, st, tbl, L.items, L.n_items, queue,
+                                   persistent, L.cells_per_item, dt, (uint32_t)k));
+                if (ev) {
+                    HIP_TRY(hipEventRecord((*ev)[e++], st));
+                    kind->push_back(0);
+                }
+            }
+            for (const SLaunch &L : s) {
+                if (L.n_items == 0) continue;
+                if (ev) HIP_TRY(hipEventRecord((*ev)[e++], st));
+                HIP_TRY(launch_s(s_grid(L), st, tbl, L.items, L.n_items, queue, persistent, dt,
+                                 (uint32_t)k));
+                if (ev) {
+                    HIP_TRY(hipEventRecord((*ev)[e++], st));
+                    kind->push_back(1);
+                }
+            }
+        }
+        HIP_TRY(launch_advance(st, tbl, n_tissues, (uint32_t)n));
+        return TISSUE_OK;
+    }
+
+    int launches_per_step() const
+    {
+        int c = 0;
+        for (const ChiLaunch &L : chi) c += L.n_items > 0;
+        for (const SLaunch &L : s) c += L.n_items > 0;
+        return c;
+    }
+
+    int run(double dt, int32_t n)
+    {
+        int32_t left = n;
+        if (graph_chunk > 0 && n >= graph_chunk) {
+            uint64_t bits;
+            std::memcpy(&bits, &dt, 8);
+            GraphKey key{bits, graph_chunk};
+            auto it = graphs.find(key);
+            if (it == graphs.end()) {
+                if (!capture_stream) HIP_TRY(hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ge = nullptr;
+                HIP_TRY(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal));
+                const int rc = enqueue(capture_stream, dt, graph_chunk);
+                hipGraph_t captured = nullptr;
+                const hipError_t ee = hipStreamEndCapture(capture_stream, &captured);
+                if (rc != TISSUE_OK) {
+                    if (captured) (void)hipGraphDestroy(captured);
+                    return rc;
+                }
+                if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+                g = captured;
+                HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+                it = graphs.emplace(key, std::make_pair(g, ge)).first;
+            }
+            while (left >= graph_chunk) {
+                HIP_TRY(hipGraphLaunch(it->second.second, stream));
+                left -= graph_chunk;
+            }
+        }
+        if (left > 0) return enqueue(stream, dt, left);
+        return TISSUE_OK;
+    }
+
+    int run_timed(double dt, int32_t n, tissue_timing_t *out)
+    {
+        const size_t launches = (size_t)n * launches_per_step();
+        std::vector<hipEvent_t> ev(2 * launches);
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        std::vector<int> kind;
+        hipEvent_t t0, t1;
+        HIP_TRY(hipEventCreate(&t0));
+        HIP_TRY(hipEventCreate(&t1));
+        HIP_TRY(hipEventRecord(t0, stream));
+        int rc = enqueue(stream, dt, n, &ev, &kind);
+        if (rc != TISSUE_OK) return rc;
+        HIP_TRY(hipEventRecord(t1, stream));
+        HIP_TRY(hipEventSynchronize(t1));
+        tissue_timing_t T{};
+        for (size_t q = 0; q < kind.size(); ++q) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
+            if (kind[q] == 0) {
+                T.chi_ms += ms;
+                T.chi_launches++;
+            } else {
+                T.s_ms += ms;
+                T.s_launches++;
+            }
+        }
+        float tot = 0.f;
+        HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
+        T.total_ms = tot;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        if (out) *out = T;
+        return TISSUE_OK;
+    }
+};
+
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+int prepare_lds(const std::vector<ChiLaunch> &chi)
+{
+    for (const ChiLaunch &L : chi) HIP_TRY(set_chi_lds_limit(L.P, L.lds));
+    return TISSUE_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+
+struct tissue {
+    Plan plan;
+    unsigned char *dev = nullptr;
+    hipStream_t stream = nullptr;
+    DevTissue host_rec{};          // last uploaded DevTissue (host copy)
+    uint32_t steps_done = 0;
+    LaunchPlan lp;
+    DevTissue *d_rec() const { return reinterpret_cast<DevTissue *>(dev + plan.off_tissue); }
+    int32_t *d_counts() const { return reinterpret_cast<int32_t *>(dev + plan.off_counts); }
+    unsigned char *d_ctl() const { return dev + plan.off_ctl; }
+};
+
+struct tissue_batch {
+    std::vector<tissue *> members;
+    unsigned char *dev = nullptr;
+    LaunchPlan lp;
+};
+
+extern "C" {
+
+const char *tissue_strerror(int code)
+{
+    switch (code) {
+    case TISSUE_OK: return "ok";
+    case TISSUE_EINVAL: return "invalid argument";
+    case TISSUE_ENOMEM: return "device buffer too small";
+    case TISSUE_EOVERFLOW: return "a species count left [0, 2^26)";
+    case TISSUE_EDEVICE: return "HIP runtime error";
+    case TISSUE_EBUSY: return "busy";
+    case TISSUE_ESTATE: return "invalid state";
+    case TISSUE_ELIMIT: return "a unit-step reached the event cap";
+    default: return "unknown error";
+    }
+}
+
+const char *tissue_last_error(void) { return g_last_error.c_str(); }
+
+int tissue_device_cus(int32_t *out)
+{
+    if (!out) return fail(TISSUE_EINVAL, "null output");
+    const int c = device_cus();
+    if (c <= 0) return fail(TISSUE_EDEVICE, "no HIP device");
+    *out = c;
+    return TISSUE_OK;
+}
+
+size_t tissue_required_bytes(const tissue_desc_t *d)
+{
+    Plan p;
+    if (build_plan(d, p) != TISSUE_OK) return 0;
+    return p.bytes;
+}
+
+int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void *hip_stream,
+                  tissue_t **out)
+{
+    if (!out) return fail(TISSUE_EINVAL, "null output handle");
+    *out = nullptr;
+    std::unique_ptr<tissue> t(new tissue());
+    int rc = build_plan(d, t->plan);
+    if (rc != TISSUE_OK) return rc;
+    Plan &p = t->plan;
+    if (!dev_buf || ((uintptr_t)dev_buf % kAlign) != 0)
+        return fail(TISSUE_EINVAL, "dev_buf must be non-null and 256-byte aligned");
+    if (dev_bytes < p.bytes)
+        return fail(TISSUE_ENOMEM, "dev_bytes " + std::to_string(dev_bytes) + " < required " +
+                                       std::to_string(p.bytes));
+    t->dev = static_cast<unsigned char *>(dev_buf);
+    t->stream = static_cast<hipStream_t>(hip_stream);
+    const int cus = device_cus();
+    if (cus <= 0) return fail(TISSUE_EDEVICE, "no HIP device");
+
+    unsigned char *base = t->dev;
+    DevTissue &R = t->host_rec;
+    R.counts = reinterpret_cast<int32_t *>(base + p.off_counts);
+    R.vox_off = reinterpret_cast<const int32_t *>(base + p.off_voxoff);
+    R.wh = reinterpret_cast<const uint8_t *>(base + p.off_wh);
+    R.cell_list = reinterpret_cast<const int32_t *>(base + p.off_cells);
+    R.edges = reinterpret_cast<const EdgeRec *>(base + p.off_edges);
+    R.stats = reinterpret_cast<unsigned long long *>(base + p.off_ctl);
+    R.flags = reinterpret_cast<uint32_t *>(base + p.off_ctl + 24);
+    if (p.trace_steps) {
+        unsigned char *tr = base + p.off_trace;
+        const size_t nc = (size_t)p.trace_steps * p.ncell, ne = (size_t)p.trace_steps * p.nedge;
+        R.tr_chi_t = reinterpret_cast<unsigned long long *>(tr);
+        R.tr_s_t = reinterpret_cast<unsigned long long *>(tr + nc * 8);
+        R.tr_chi_ev = reinterpret_cast<uint32_t *>(tr + nc * 8 + ne * 8);
+        R.tr_s_ev = reinterpret_cast<uint32_t *>(tr + nc * 8 + ne * 8 + nc * 4);
+    }
+    R.seed = d->seed;
+    R.n_cells = p.ncell;
+    R.n_edges = p.nedge;
+    R.sim_id = d->sim_id;
+    R.step_base = d->start_step;
+    R.event_cap = d->event_cap ? d->event_cap : TISSUE_DEFAULT_EVENT_CAP;
+    R.trace_steps = p.trace_steps ? p.trace_steps : 1;
+    R.model = p.model;
+    t->steps_done = d->start_step;
+
+    // upload (synchronous on the tissue's stream; create is not on the hot path)
+    hipStream_t st = t->stream;
+    const size_t cbytes = (size_t)p.nvox * p.S * 4;
+    DevTissue *d_rec = t->d_rec();
+    HIP_TRY(hipMemcpyAsync(base + p.off_tissue, &R, sizeof(DevTissue), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + p.off_tbl, &d_rec, sizeof(DevTissue *), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + p.off_counts, d->init_counts, cbytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + p.off_init, d->init_counts, cbytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + p.off_voxoff, p.vox_off.data(), p.vox_off.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + p.off_wh, p.wh.data(), p.wh.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + p.off_cells, p.cell_list.data(), p.cell_list.size() * 4, hipMemcpyHostToDevice, st));
+    if (p.nedge)
+        HIP_TRY(hipMemcpyAsync(base + p.off_edges, p.edges.data(), p.edges.size() * sizeof(EdgeRec),
+                               hipMemcpyHostToDevice, st));
+    std::vector<ChiItem> chi_all;
+    for (auto &g : p.chi) chi_all.insert(chi_all.end(), g.items.begin(), g.items.end());
+    std::vector<SItem> s_all;
+    for (auto &ps : p.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
+    if (!chi_all.empty())
+        HIP_TRY(hipMemcpyAsync(base + p.off_chi, chi_all.data(), chi_all.size() * sizeof(ChiItem),
+                               hipMemcpyHostToDevice, st));
+    if (!s_all.empty())
+        HIP_TRY(hipMemcpyAsync(base + p.off_s, s_all.data(), s_all.size() * sizeof(SItem),
+                               hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(base + p.off_ctl, 0, 64, st));
+    if (p.trace_steps)
+        HIP_TRY(hipMemsetAsync(base + p.off_trace, 0,
+                               (size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12), st));
+    HIP_TRY(hipStreamSynchronize(st));
+
+    // launch plan of this tissue alone
+    LaunchPlan &L = t->lp;
+    L.tbl = reinterpret_cast<DevTissue **>(base + p.off_tbl);
+    L.n_tissues = 1;
+    L.queue = reinterpret_cast<uint32_t *>(base + p.off_ctl + 32);
+    L.stream = st;
+    L.cus = cus;
+    size_t off = 0;
+    for (auto &g : p.chi) {
+        ChiLaunch cl;
+        cl.P = g.P;
+        cl.cells_per_item = g.cells_per_item;
+        cl.lds = chi_lds_bytes(g.P, (int)p.S, g.cells_per_item);
+        cl.items = reinterpret_cast<const ChiItem *>(base + p.off_chi) + off;
+        cl.n_items = (uint32_t)g.items.size();
+        off += g.items.size();
+        L.chi.push_back(cl);
+    }
+    off = 0;
+    for (auto &ps : p.s_passes) {
+        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(base + p.off_s) + off, (uint32_t)ps.size()});
+        off += ps.size();
+    }
+    rc = prepare_lds(L.chi);
+    if (rc != TISSUE_OK) return rc;
+    *out = t.release();
+    return TISSUE_OK;
+}
+
+int tissue_step(tissue_t *t, double dt, int32_t n_steps)
+{
+    if (!t) return fail(TISSUE_EINVAL, "null tissue");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(TISSUE_EINVAL, "dt must be finite and > 0");
+    if (n_steps < 0) return fail(TISSUE_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0) return TISSUE_OK;
+    if ((uint64_t)t->steps_done + (uint64_t)n_steps > 0xFFFFFFFFull)
+        return fail(TISSUE_EINVAL, "step index would exceed 2^32");
+    const int rc = t->lp.run(dt, n_steps);
+    if (rc == TISSUE_OK) t->steps_done += (uint32_t)n_steps;
+    return rc;
+}
+
+int tissue_step_timed(tissue_t *t, double dt, int32_t n_steps, tissue_timing_t *out)
+{
+    if (!t) return fail(TISSUE_EINVAL, "null tissue");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(TISSUE_EINVAL, "dt must be finite and > 0");
+    if (n_steps < 0) return fail(TISSUE_EINVAL, "n_steps must be >= 0");
+    const int rc = t->lp.run_timed(dt, n_steps, out);
+    if (rc == TISSUE_OK) t->steps_done += (uint32_t)n_steps;
+    return rc;
+}
+
+static int check_flags(const unsigned char *ctl)
+{
+    uint32_t flags[2];
+    std::memcpy(flags, ctl + 24, 8);
+    if (flags[0]) return fail(TISSUE_EOVERFLOW, "a count left [0, 2^26)");
+    if (flags[1]) return fail(TISSUE_ELIMIT, "a unit-step reached event_cap");
+    return TISSUE_OK;
+}
+
+int tissue_read_counts(tissue_t *t, int32_t *host_out, size_t n_out)
+{
+    if (!t || !host_out) return fail(TISSUE_EINVAL, "null argument");
+    const size_t n = (size_t)t->plan.nvox * t->plan.S;
+    if (n_out != n) return fail(TISSUE_EINVAL, "n_out must equal n_voxels * n_species");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    HIP_TRY(hipMemcpy(host_out, t->d_counts(), n * 4, hipMemcpyDeviceToHost));
+    unsigned char ctl[64];
+    HIP_TRY(hipMemcpy(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost));
+    return check_flags(ctl);
+}
+
+int tissue_read_stats(tissue_t *t, tissue_stats_t *out)
+{
+    if (!t || !out) return fail(TISSUE_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    unsigned char ctl[64];
+    HIP_TRY(hipMemcpy(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost));
+    uint64_t st[3];
+    uint32_t fl[2];
+    std::memcpy(st, ctl, 24);
+    std::memcpy(fl, ctl + 24, 8);
+    out->chi_events = st[0];
+    out->s_events = st[1];
+    out->draws = st[2];
+    out->overflow = fl[0];
+    out->capped = fl[1];
+    out->steps_done = t->steps_done;
+    out->n_cells = t->plan.ncell;
+    out->n_edges = t->plan.nedge;
+    out->n_voxels = t->plan.nvox;
+    return TISSUE_OK;
+}
+
+int tissue_read_trace(tissue_t *t, uint32_t first_step, uint32_t n_steps, uint32_t *chi_events,
+                      uint64_t *chi_t_bits, uint32_t *s_events, uint64_t *s_t_bits)
+{
+    if (!t) return fail(TISSUE_EINVAL, "null tissue");
+    const Plan &p = t->plan;
+    if (!p.trace_steps) return fail(TISSUE_ESTATE, "tissue was created without TISSUE_FLAG_TRACE");
+    const uint64_t end = (uint64_t)first_step + n_steps;
+    if (end > t->steps_done || n_steps > p.trace_steps ||
+        (uint64_t)first_step + p.trace_steps < t->steps_done)
+        return fail(TISSUE_EINVAL, "requested steps are not all in the trace window");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    const DevTissue &R = t->host_rec;
+    for (uint32_t k = 0; k < n_steps; ++k) {
+        const size_t slot = (size_t)((first_step + k) % p.trace_steps);
+        if (chi_events)
+            HIP_TRY(hipMemcpy(chi_events + (size_t)k * p.ncell, R.tr_chi_ev + slot * p.ncell,
+                              (size_t)p.ncell * 4, hipMemcpyDeviceToHost));
+        if (chi_t_bits)
+            HIP_TRY(hipMemcpy(chi_t_bits + (size_t)k * p.ncell, R.tr_chi_t + slot * p.ncell,
+                              (size_t)p.ncell * 8, hipMemcpyDeviceToHost));
+        if (p.nedge && s_events)
+            HIP_TRY(hipMemcpy(s_events + (size_t)k * p.nedge, R.tr_s_ev + slot * p.nedge,
+                              (size_t)p.nedge * 4, hipMemcpyDeviceToHost));
+        if (p.nedge && s_t_bits)
+            HIP_TRY(hipMemcpy(s_t_bits + (size_t)k * p.nedge, R.tr_s_t + slot * p.nedge,
+                              (size_t)p.nedge * 8, hipMemcpyDeviceToHost));
+    }
+    return TISSUE_OK;
+}
+
+int tissue_restart(tissue_t *t, uint32_t sim_id, uint32_t start_step)
+{
+    if (!t) return fail(TISSUE_EINVAL, "null tissue");
+    if (sim_id >= (1u << 30)) return fail(TISSUE_EINVAL, "sim_id must be < 2^30");
+    const Plan &p = t->plan;
+    // wait for earlier work so the host record can be reused as the source
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    t->host_rec.sim_id = sim_id;
+    t->host_rec.step_base = start_step;
+    HIP_TRY(hipMemcpyAsync(t->d_counts(), t->dev + p.off_init, (size_t)p.nvox * p.S * 4,
+                           hipMemcpyDeviceToDevice, t->stream));
+    HIP_TRY(hipMemcpyAsync(t->d_rec(), &t->host_rec, sizeof(DevTissue), hipMemcpyHostToDevice, t->stream));
+    HIP_TRY(hipMemsetAsync(t->d_ctl(), 0, 32, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    t->steps_done = start_step;
+    return TISSUE_OK;
+}
+
+int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in)
+{
+    if (!t || !host_in) return fail(TISSUE_EINVAL, "null argument");
+    const size_t n = (size_t)t->plan.nvox * t->plan.S;
+    if (n_in != n) return fail(TISSUE_EINVAL, "n_in must equal n_voxels * n_species");
+    for (size_t i = 0; i < n; ++i)
+        if (host_in[i] < 0 || host_in[i] >= TISSUE_COUNT_LIMIT)
+            return fail(TISSUE_EINVAL, "counts must be in [0, 2^26)");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    HIP_TRY(hipMemcpy(t->d_counts(), host_in, n * 4, hipMemcpyHostToDevice));
+    return TISSUE_OK;
+}
+
+int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu)
+{
+    if (!t || workgroups_per_cu < 0 || workgroups_per_cu > 64) return fail(TISSUE_EINVAL, "bad launch shape");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    t->lp.persistent = persistent ? 1 : 0;
+    t->lp.wpc = workgroups_per_cu;
+    t->lp.clear_graphs();
+    return TISSUE_OK;
+}
+
+int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph)
+{
+    if (!t || steps_per_graph < 0 || steps_per_graph > 100000) return fail(TISSUE_EINVAL, "bad graph chunk");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    t->lp.graph_chunk = steps_per_graph;
+    t->lp.clear_graphs();
+    return TISSUE_OK;
+}
+
+int tissue_destroy(tissue_t *t)
+{
+    if (!t) return TISSUE_OK;
+    (void)hipStreamSynchronize(t->stream);
+    delete t;
+    return TISSUE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct BatchLayout {
+    size_t off_tbl = 0, off_queue = 0, off_chi = 0, off_s = 0, bytes = 0;
+    std::vector<ChiGroupHost> chi;            // merged per P
+    std::vector<std::vector<SItem>> s_passes;
+};
+
+int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
+{
+    if (!ts || n < 1) return fail(TISSUE_EINVAL, "batch needs >= 1 tissue");
+    for (int32_t i = 0; i < n; ++i)
+        if (!ts[i]) return fail(TISSUE_EINVAL, "null tissue in batch");
+    // chi: per leaf-count class, one launch over all members' items
+    std::map<int, ChiGroupHost> groups;
+    for (int32_t i = 0; i < n; ++i)
+        for (const ChiGroupHost &g : ts[i]->plan.chi) {
+            ChiGroupHost &G = groups[g.P];
+            G.P = g.P;
+            G.max_species = std::max<int>(G.max_species, (int)ts[i]->plan.S);
+        }
+    for (auto &kv : groups) {
+        ChiGroupHost &G = kv.second;
+        const size_t per_cell = chi_lds_bytes(G.P, G.max_species, 1);
+        int cpi = 64;
+        while (cpi > 1 && (size_t)cpi * per_cell > kChiLdsBudget) cpi >>= 1;
+        G.cells_per_item = cpi;
+        for (int32_t i = 0; i < n; ++i)
+            for (const ChiGroupHost &g : ts[i]->plan.chi) {
+                if (g.P != G.P) continue;
+                // this member's cells of the class: re-cut with the batch's items size
+                const uint32_t first = g.items.front().first;
+                uint32_t count = 0;
+                for (const ChiItem &it : g.items) count += it.count;
+                for (uint32_t o = 0; o < count; o += cpi)
+                    G.items.push_back(ChiItem{(uint32_t)i, first + o, std::min<uint32_t>(cpi, count - o), 0});
+            }
+    }
+    for (auto it = groups.rbegin(); it != groups.rend(); ++it) B.chi.push_back(std::move(it->second));
+    // S: pass 0 holds all edges of members with disjoint faces and class 0
+    // of the others; pass c > 0 holds class c of the others
+    int max_pass = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const Plan &p = ts[i]->plan;
+        if (!p.has_s || p.nedge == 0) continue;
+        max_pass = std::max(max_pass, p.disjoint ? 1 : (int)p.class_start.size() - 1);
+    }
+    B.s_passes.assign(max_pass, {});
+    for (int32_t i = 0; i < n; ++i) {
+        const Plan &p = ts[i]->plan;
+        if (!p.has_s || p.nedge == 0) continue;
+        auto cut = [&](uint32_t lo, uint32_t hi, std::vector<SItem> &out) {
+            for (uint32_t o = lo; o < hi; o += kWave)
+                out.push_back(SItem{(uint32_t)i, o, std::min<uint32_t>(kWave, hi - o), 0});
+        };
+        if (p.disjoint) {
+            cut(0, p.nedge, B.s_passes[0]);
+        } else {
+            for (size_t c = 0; c + 1 < p.class_start.size(); ++c)
+                cut(p.class_start[c], p.class_start[c + 1], B.s_passes[c]);
+        }
+    }
+    size_t n_chi = 0, n_s = 0;
+    for (auto &g : B.chi) n_chi += g.items.size();
+    for (auto &ps : B.s_passes) n_s += ps.size();
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    B.off_tbl = take((size_t)n * sizeof(DevTissue *));
+    B.off_queue = take(64);
+    B.off_chi = take(n_chi * sizeof(ChiItem));
+    B.off_s = take(n_s * sizeof(SItem));
+    B.bytes = o;
+    return TISSUE_OK;
+}
+
+}  // namespace
+
+size_t tissue_batch_required_bytes(tissue_t *const *ts, int32_t n)
+{
+    BatchLayout B;
+    if (plan_batch(ts, n, B) != TISSUE_OK) return 0;
+    return B.bytes;
+}
+
+int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t dev_bytes,
+                        void *hip_stream, tissue_batch_t **out)
+{
+    if (!out) return fail(TISSUE_EINVAL, "null output handle");
+    *out = nullptr;
+    BatchLayout B;
+    int rc = plan_batch(ts, n, B);
+    if (rc != TISSUE_OK) return rc;
+    if (!dev_buf || ((uintptr_t)dev_buf % kAlign) != 0)
+        return fail(TISSUE_EINVAL, "dev_buf must be non-null and 256-byte aligned");
+    if (dev_bytes < B.bytes) return fail(TISSUE_ENOMEM, "batch buffer too small");
+    const int cus = device_cus();
+    if (cus <= 0) return fail(TISSUE_EDEVICE, "no HIP device");
+    std::unique_ptr<tissue_batch> b(new tissue_batch());
+    b->members.assign(ts, ts + n);
+    b->dev = static_cast<unsigned char *>(dev_buf);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    for (int32_t i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(ts[i]->stream));
+    std::vector<DevTissue *> tbl(n);
+    for (int32_t i = 0; i < n; ++i) tbl[i] = ts[i]->d_rec();
+    std::vector<ChiItem> chi_all;
+    for (auto &g : B.chi) chi_all.insert(chi_all.end(), g.items.begin(), g.items.end());
+    std::vector<SItem> s_all;
+    for (auto &ps : B.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
+    HIP_TRY(hipMemcpyAsync(b->dev + B.off_tbl, tbl.data(), tbl.size() * sizeof(DevTissue *), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(b->dev + B.off_queue, 0, 64, st));
+    if (!chi_all.empty())
+        HIP_TRY(hipMemcpyAsync(b->dev + B.off_chi, chi_all.data(), chi_all.size() * sizeof(ChiItem), hipMemcpyHostToDevice, st));
+    if (!s_all.empty())
+        HIP_TRY(hipMemcpyAsync(b->dev + B.off_s, s_all.data(), s_all.size() * sizeof(SItem), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    LaunchPlan &L = b->lp;
+    L.tbl = reinterpret_cast<DevTissue **>(b->dev + B.off_tbl);
+    L.n_tissues = (uint32_t)n;
+    L.queue = reinterpret_cast<uint32_t *>(b->dev + B.off_queue);
+    L.stream = st;
+    L.cus = cus;
+    size_t off = 0;
+    for (auto &g : B.chi) {
+        ChiLaunch cl;
+        cl.P = g.P;
+        cl.cells_per_item = g.cells_per_item;
+        cl.lds = chi_lds_bytes(g.P, g.max_species, g.cells_per_item);
+        cl.items = reinterpret_cast<const ChiItem *>(b->dev + B.off_chi) + off;
+        cl.n_items = (uint32_t)g.items.size();
+        off += g.items.size();
+        L.chi.push_back(cl);
+    }
+    off = 0;
+    for (auto &ps : B.s_passes) {
+        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(b->dev + B.off_s) + off, (uint32_t)ps.size()});
+        off += ps.size();
+    }
+    rc = prepare_lds(L.chi);
+    if (rc != TISSUE_OK) return rc;
+    *out = b.release();
+    return TISSUE_OK;
+}
+
+static int batch_check(tissue_batch_t *b, double dt, int32_t n_steps)
+{
+    if (!b) return fail(TISSUE_EINVAL, "null batch");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(TISSUE_EINVAL, "dt must be finite and > 0");
+    if (n_steps < 0) return fail(TISSUE_EINVAL, "n_steps must be >= 0");
+    for (tissue *t : b->members)
+        if ((uint64_t)t->steps_done + (uint64_t)n_steps > 0xFFFFFFFFull)
+            return fail(TISSUE_EINVAL, "step index would exceed 2^32");
+    return TISSUE_OK;
+}
+
+int tissue_batch_step(tissue_batch_t *b, double dt, int32_t n_steps)
+{
+    int rc = batch_check(b, dt, n_steps);
+    if (rc != TISSUE_OK || n_steps == 0) return rc;
+    rc = b->lp.run(dt, n_steps);
+    if (rc == TISSUE_OK)
+        for (tissue *t : b->members) t->steps_done += (uint32_t)n_steps;
+    return rc;
+}
+
+int tissue_batch_step_timed(tissue_batch_t *b, double dt, int32_t n_steps, tissue_timing_t *out)
+{
+    int rc = batch_check(b, dt, n_steps);
+    if (rc != TISSUE_OK) return rc;
+    rc = b->lp.run_timed(dt, n_steps, out);
+    if (rc == TISSUE_OK)
+        for (tissue *t : b->members) t->steps_done += (uint32_t)n_steps;
+    return rc;
+}
+
+int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workgroups_per_cu)
+{
+    if (!b || workgroups_per_cu < 0 || workgroups_per_cu > 64) return fail(TISSUE_EINVAL, "bad launch shape");
+    HIP_TRY(hipStreamSynchronize(b->lp.stream));
+    b->lp.persistent = persistent ? 1 : 0;
+    b->lp.wpc = workgroups_per_cu;
+    b->lp.clear_graphs();
+    return TISSUE_OK;
+}
+
+int tissue_batch_sync(tissue_batch_t *b)
+{
+    if (!b) return fail(TISSUE_EINVAL, "null batch");
+    HIP_TRY(hipStreamSynchronize(b->lp.stream));
+    return TISSUE_OK;
+}
+
+int tissue_batch_destroy(tissue_batch_t *b)
+{
+    if (!b) return TISSUE_OK;
+    (void)hipStreamSynchronize(b->lp.stream);
+    delete b;
+    return TISSUE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// internal.h -- device data layout shared by the host runtime and the kernels.
+//
+// Everything a kernel needs about one tissue is in a DevTissue record that
+// lives in the tissue's own device buffer; launches see tissues through a
+// table of DevTissue pointers, so one launch can cover one tissue (plain) or
+// many (batch, serving).  Work is cut into items of up to 64 cells (chi) or
+// 64 edges (S) of one tissue; one 64-lane wavefront runs one item, one lane
+// per cell or edge.
+#pragma once
+
+#include <stdint.h>
+
+namespace tissue_impl {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxReactions = 16;
+constexpr int kMaxFace = 8;       // voxels in one face group (8x8 square mesh: 7)
+constexpr int kWave = 64;
+constexpr int32_t kCountLimit = 1 << 26;
+
+// Mass-action network of one tissue.  A reaction's net change is packed in
+// change_code[r]: up to four bytes, byte = species << 5 | (delta + 16),
+// byte value 16 (species 0, delta 0) = no change.
+struct DevModel {
+    int32_t n_species;
+    int32_t n_reactions;
+    int32_t n_diff;                      // species with D > 0
+    int32_t trans_n, trans_d, trans_i;   // trans_n < 0: no S operator
+    int8_t reac_a[kMaxReactions];        // first reactant or -1
+    int8_t reac_b[kMaxReactions];        // second reactant or -1
+    int8_t diff_species[kMaxSpecies];    // species of diffusion channel q
+    uint32_t change_code[kMaxReactions];
+    double rates[kMaxReactions];
+    double diff_rate[kMaxSpecies];       // D of diffusion channel q
+    double trans_rate;
+};
+
+// One lattice edge (i < j) and the facing membrane groups A of cell i and
+// B of cell j; the voxel offsets locate the two cells in the counts array.
+struct EdgeRec {
+    int32_t vox_i;         // first voxel of cell i (global voxel index)
+    int32_t vox_j;
+    uint8_t m_a, m_b, pad0, pad1;
+    uint8_t A[kMaxFace];
+    uint8_t B[kMaxFace];
+};
+static_assert(sizeof(EdgeRec) == 28, "EdgeRec layout");
+
+struct DevTissue {
+    int32_t *counts;              // [n_voxels][n_species], cell order, v = y*w + x
+    const int32_t *vox_off;       // [n_cells] first voxel of each cell
+    const uint8_t *wh;            // [n_cells][2] mesh (w, h)
+    const int32_t *cell_list;     // [n_cells] cells grouped by leaf-count class
+    const EdgeRec *edges;         // [n_edges], ranked by (colour, i)
+    unsigned long long *stats;    // [3] chi events, S events, draws
+    uint32_t *flags;              // [2] overflow, capped
+    uint32_t *tr_chi_ev;          // trace ring [trace_steps][n_cells] or null
+    unsigned long long *tr_chi_t;
+    uint32_t *tr_s_ev;            // [trace_steps][n_edges] or null
+    unsigned long long *tr_s_t;
+    uint64_t seed;
+    uint32_t n_cells, n_edges;
+    uint32_t sim_id;
+    uint32_t step_base;           // global index of step k = 0 of the next launch group
+    uint32_t event_cap;
+    uint32_t trace_steps;
+    DevModel model;
+};
+
+// up to 64 cells of one tissue, all with the same leaf count P:
+// cells cell_list[first .. first + count)
+struct ChiItem {
+    uint32_t tissue;
+    uint32_t first;
+    uint32_t count;
+    uint32_t pad;
+};
+
+// up to 64 consecutive edges [first, first + count) of one tissue
+struct SItem {
+    uint32_t tissue;
+    uint32_t first;
+    uint32_t count;
+    uint32_t pad;
+};
+
+}  // namespace tissue_impl

@@ -1,0 +1,302 @@
+"""ctypes binding of libtissue.so (include/tissue.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of the library.  PyTorch provides the device memory (a uint8 tensor
+per tissue or batch) and, optionally, the stream.  Importing this module
+loads the library and raises if it has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtissue.so")
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ESTATE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
+FLAG_TRACE = 1
+ABI_VERSION = 1
+
+
+class TissueError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Desc(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("lattice", C.c_uint32),
+        ("nx", C.c_uint32), ("ny", C.c_uint32),
+        ("mesh_w", C.POINTER(C.c_uint8)), ("mesh_h", C.POINTER(C.c_uint8)),
+        ("mesh_w0", C.c_uint32), ("mesh_h0", C.c_uint32),
+        ("n_species", C.c_uint32), ("n_reactions", C.c_uint32),
+        ("reactants", C.POINTER(C.c_int32)), ("stoich", C.POINTER(C.c_int32)),
+        ("rates", C.POINTER(C.c_double)), ("diffusion", C.POINTER(C.c_double)),
+        ("trans_n", C.c_int32), ("trans_d", C.c_int32), ("trans_i", C.c_int32),
+        ("flags", C.c_uint32), ("trans_rate", C.c_double),
+        ("init_counts", C.POINTER(C.c_int32)),
+        ("seed", C.c_uint64), ("sim_id", C.c_uint32), ("start_step", C.c_uint32),
+        ("event_cap", C.c_uint32), ("trace_steps", C.c_uint32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [("chi_events", C.c_uint64), ("s_events", C.c_uint64), ("draws", C.c_uint64),
+                ("steps_done", C.c_uint32), ("overflow", C.c_uint32), ("capped", C.c_uint32),
+                ("n_cells", C.c_uint32), ("n_edges", C.c_uint32), ("n_voxels", C.c_uint32)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("chi_ms", C.c_double), ("s_ms", C.c_double), ("total_ms", C.c_double),
+                ("chi_launches", C.c_uint32), ("s_launches", C.c_uint32)]
+
+
+EXPORTS = [
+    "tissue_required_bytes", "tissue_create", "tissue_step", "tissue_read_counts",
+    "tissue_read_stats", "tissue_read_trace", "tissue_restart", "tissue_write_counts",
+    "tissue_set_launch", "tissue_set_graph_chunk", "tissue_step_timed", "tissue_destroy",
+    "tissue_batch_required_bytes", "tissue_batch_create", "tissue_batch_step",
+    "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
+    "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1806_10889_amd/build.py "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, u32, sz, dbl = C.c_void_p, C.c_int32, C.c_uint32, C.c_size_t, C.c_double
+    pD = C.POINTER(Desc)
+    sig = {
+        "tissue_required_bytes": (sz, [pD]),
+        "tissue_create": (C.c_int, [pD, vp, sz, vp, C.POINTER(vp)]),
+        "tissue_step": (C.c_int, [vp, dbl, i32]),
+        "tissue_read_counts": (C.c_int, [vp, C.POINTER(C.c_int32), sz]),
+        "tissue_read_stats": (C.c_int, [vp, C.POINTER(Stats)]),
+        "tissue_read_trace": (C.c_int, [vp, u32, u32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]),
+        "tissue_restart": (C.c_int, [vp, u32, u32]),
+        "tissue_write_counts": (C.c_int, [vp, C.POINTER(C.c_int32), sz]),
+        "tissue_set_launch": (C.c_int, [vp, i32, i32]),
+        "tissue_set_graph_chunk": (C.c_int, [vp, i32]),
+        "tissue_step_timed": (C.c_int, [vp, dbl, i32, C.POINTER(Timing)]),
+        "tissue_destroy": (C.c_int, [vp]),
+        "tissue_batch_required_bytes": (sz, [C.POINTER(vp), i32]),
+        "tissue_batch_create": (C.c_int, [C.POINTER(vp), i32, vp, sz, vp, C.POINTER(vp)]),
+        "tissue_batch_step": (C.c_int, [vp, dbl, i32]),
+        "tissue_batch_step_timed": (C.c_int, [vp, dbl, i32, C.POINTER(Timing)]),
+        "tissue_batch_set_launch": (C.c_int, [vp, i32, i32]),
+        "tissue_batch_sync": (C.c_int, [vp]),
+        "tissue_batch_destroy": (C.c_int, [vp]),
+        "tissue_strerror": (C.c_char_p, [C.c_int]),
+        "tissue_last_error": (C.c_char_p, []),
+        "tissue_device_cus": (C.c_int, [C.POINTER(C.c_int32)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int, what: str, allow=()):
+    if rc != OK and rc not in allow:
+        detail = lib.tissue_last_error().decode()
+        raise TissueError(rc, f"{what}: {lib.tissue_strerror(rc).decode()}: {detail}")
+    return rc
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+class _DescHolder:
+    """A filled Desc plus the numpy arrays its pointers refer to."""
+
+    def __init__(self, problem: dict, trace_steps: int = 0):
+        p = problem
+        self.mesh_w = np.ascontiguousarray(p["mesh_w"], dtype=np.uint8)
+        self.mesh_h = np.ascontiguousarray(p["mesh_h"], dtype=np.uint8)
+        self.reactants = np.ascontiguousarray(np.asarray(p["reactants"], np.int32).reshape(-1))
+        self.stoich = np.ascontiguousarray(np.asarray(p["stoich"], np.int32).reshape(-1))
+        self.rates = np.ascontiguousarray(p["rates"], dtype=np.float64)
+        self.diffusion = np.ascontiguousarray(p["diffusion"], dtype=np.float64)
+        self.counts = np.ascontiguousarray(np.asarray(p["init_counts"], np.int32).reshape(-1))
+        d = Desc()
+        d.abi_version = ABI_VERSION
+        d.lattice = int(p["lattice"])
+        d.nx, d.ny = int(p["nx"]), int(p["ny"])
+        d.mesh_w, d.mesh_h = _p(self.mesh_w, C.c_uint8), _p(self.mesh_h, C.c_uint8)
+        d.n_species, d.n_reactions = int(p["n_species"]), int(p["n_reactions"])
+        d.reactants, d.stoich = _p(self.reactants, C.c_int32), _p(self.stoich, C.c_int32)
+        d.rates, d.diffusion = _p(self.rates, C.c_double), _p(self.diffusion, C.c_double)
+        d.trans_n, d.trans_d, d.trans_i = int(p["trans_n"]), int(p["trans_d"]), int(p["trans_i"])
+        d.trans_rate = float(p["trans_rate"])
+        d.init_counts = _p(self.counts, C.c_int32)
+        d.seed = int(p["seed"])
+        d.sim_id = int(p["sim_id"])
+        d.start_step = int(p.get("start_step", 0))
+        d.event_cap = int(p.get("event_cap", 0))
+        d.flags = FLAG_TRACE if trace_steps > 0 else 0
+        d.trace_steps = int(trace_steps)
+        self.desc = d
+
+
+def required_bytes(problem: dict, trace_steps: int = 0) -> int:
+    h = _DescHolder(problem, trace_steps)
+    return int(lib.tissue_required_bytes(C.byref(h.desc)))
+
+
+def device_cus() -> int:
+    n = C.c_int32()
+    _check(lib.tissue_device_cus(C.byref(n)), "tissue_device_cus")
+    return n.value
+
+
+class Tissue:
+    """One tissue resident in a torch-allocated device buffer."""
+
+    def __init__(self, problem: dict, device="cuda:0", stream=None, trace_steps: int = 0,
+                 buffer=None):
+        import torch
+        self.problem = problem
+        self._h = _DescHolder(problem, trace_steps)
+        need = int(lib.tissue_required_bytes(C.byref(self._h.desc)))
+        if need == 0:  # invalid descriptor: tissue_create reports why, before any device work
+            _check(lib.tissue_create(C.byref(self._h.desc), None, 0, None, C.byref(C.c_void_p())),
+                   "tissue_create")
+        self.bytes = need
+        if buffer is None:
+            buffer = torch.empty(need + 256, dtype=torch.uint8, device=device)
+        self.buffer = buffer  # keeps the device memory alive
+        addr = buffer.data_ptr()
+        aligned = (addr + 255) // 256 * 256
+        avail = buffer.numel() - (aligned - addr)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib.tissue_create(C.byref(self._h.desc), C.c_void_p(aligned), avail,
+                                 _stream_handle(stream), C.byref(h)), "tissue_create")
+        self.handle = h
+        self.n_values = int(self._h.counts.size)
+
+    def step(self, dt: float, n_steps: int):
+        _check(lib.tissue_step(self.handle, float(dt), int(n_steps)), "tissue_step")
+
+    def step_timed(self, dt: float, n_steps: int) -> dict:
+        t = Timing()
+        _check(lib.tissue_step_timed(self.handle, float(dt), int(n_steps), C.byref(t)), "tissue_step_timed")
+        return dict(chi_ms=t.chi_ms, s_ms=t.s_ms, total_ms=t.total_ms,
+                    chi_launches=t.chi_launches, s_launches=t.s_launches)
+
+    def read_counts(self, allow_flags: bool = False) -> np.ndarray:
+        out = np.empty(self.n_values, dtype=np.int32)
+        allow = (EOVERFLOW, ELIMIT) if allow_flags else ()
+        _check(lib.tissue_read_counts(self.handle, _p(out, C.c_int32), out.size), "tissue_read_counts", allow)
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib.tissue_read_stats(self.handle, C.byref(s)), "tissue_read_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def trace(self, first_step: int, n_steps: int):
+        st = self.stats()
+        nc, ne = st["n_cells"], st["n_edges"]
+        ce = np.zeros(max(n_steps * nc, 1), np.uint32)
+        ct = np.zeros(max(n_steps * nc, 1), np.uint64)
+        se = np.zeros(max(n_steps * ne, 1), np.uint32)
+        stt = np.zeros(max(n_steps * ne, 1), np.uint64)
+        _check(lib.tissue_read_trace(self.handle, int(first_step), int(n_steps), _p(ce, C.c_uint32),
+                                     _p(ct, C.c_uint64), _p(se, C.c_uint32), _p(stt, C.c_uint64)),
+               "tissue_read_trace")
+        return (ce[: n_steps * nc].reshape(n_steps, nc), ct[: n_steps * nc].reshape(n_steps, nc),
+                se[: n_steps * ne].reshape(n_steps, ne), stt[: n_steps * ne].reshape(n_steps, ne))
+
+    def restart(self, sim_id: int, start_step: int = 0):
+        _check(lib.tissue_restart(self.handle, int(sim_id), int(start_step)), "tissue_restart")
+
+    def write_counts(self, counts):
+        a = np.ascontiguousarray(np.asarray(counts, np.int32).reshape(-1))
+        _check(lib.tissue_write_counts(self.handle, _p(a, C.c_int32), a.size), "tissue_write_counts")
+
+    def set_launch(self, persistent: bool, workgroups_per_cu: int = 0):
+        _check(lib.tissue_set_launch(self.handle, int(bool(persistent)), int(workgroups_per_cu)),
+               "tissue_set_launch")
+
+    def set_graph_chunk(self, steps: int):
+        _check(lib.tissue_set_graph_chunk(self.handle, int(steps)), "tissue_set_graph_chunk")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.tissue_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many tissues advanced by shared launches (one HIP graph per chunk of steps)."""
+
+    def __init__(self, tissues, device="cuda:0", stream=None):
+        import torch
+        self.tissues = list(tissues)
+        arr = (C.c_void_p * len(self.tissues))(*[t.handle.value for t in self.tissues])
+        self._arr = arr
+        need = int(lib.tissue_batch_required_bytes(arr, len(self.tissues)))
+        if need == 0:
+            _check(lib.tissue_batch_create(arr, len(self.tissues), None, 0, None, C.byref(C.c_void_p())),
+                   "tissue_batch_create")
+        self.buffer = torch.empty(need + 256, dtype=torch.uint8, device=device)
+        addr = self.buffer.data_ptr()
+        aligned = (addr + 255) // 256 * 256
+        h = C.c_void_p()
+        _check(lib.tissue_batch_create(arr, len(self.tissues), C.c_void_p(aligned),
+                                       self.buffer.numel() - (aligned - addr),
+                                       _stream_handle(stream), C.byref(h)), "tissue_batch_create")
+        self.handle = h
+
+    def step(self, dt: float, n_steps: int):
+        _check(lib.tissue_batch_step(self.handle, float(dt), int(n_steps)), "tissue_batch_step")
+
+    def step_timed(self, dt: float, n_steps: int) -> dict:
+        t = Timing()
+        _check(lib.tissue_batch_step_timed(self.handle, float(dt), int(n_steps), C.byref(t)),
+               "tissue_batch_step_timed")
+        return dict(chi_ms=t.chi_ms, s_ms=t.s_ms, total_ms=t.total_ms,
+                    chi_launches=t.chi_launches, s_launches=t.s_launches)
+
+    def set_launch(self, persistent: bool, workgroups_per_cu: int = 0):
+        _check(lib.tissue_batch_set_launch(self.handle, int(bool(persistent)), int(workgroups_per_cu)),
+               "tissue_batch_set_launch")
+
+    def sync(self):
+        _check(lib.tissue_batch_sync(self.handle), "tissue_batch_sync")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.tissue_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,35 @@
+"""Shared helpers of the GPU tests: run the HIP path and the oracle on the
+same seeded problem and compare."""
+import numpy as np
+
+
+def gpu_run(problem, n_steps, trace=False, persistent=None, wpc=0, graph_chunk=None, chunks=None,
+            allow_flags=False):
+    from paper_1806_10889_amd import tissue as T
+    t = T.Tissue(problem, trace_steps=n_steps if trace else 0)
+    if persistent is not None:
+        t.set_launch(persistent, wpc)
+    if graph_chunk is not None:
+        t.set_graph_chunk(graph_chunk)
+    for c in (chunks or [n_steps]):
+        t.step(problem["dt"], c)
+    out = dict(counts=t.read_counts(allow_flags=allow_flags), stats=t.stats())
+    if trace:
+        s0 = int(problem.get("start_step", 0))
+        out["trace"] = t.trace(s0, n_steps)
+    t.close()
+    return out
+
+
+def assert_same(g, o, trace=True):
+    assert np.array_equal(g["counts"], o.counts), \
+        f"counts differ at {np.flatnonzero(g['counts'] != o.counts)[:10]}"
+    assert g["stats"]["chi_events"] == o.chi_events
+    assert g["stats"]["s_events"] == o.s_events
+    assert g["stats"]["draws"] == o.draws
+    if trace:
+        ce, ct, se, st = g["trace"]
+        assert np.array_equal(ce, o.chi_trace_events)
+        assert np.array_equal(ct, o.chi_trace_t)
+        assert np.array_equal(se, o.s_trace_events)
+        assert np.array_equal(st, o.s_trace_t)

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every declared entry point, and its
+host-side validation rejects bad descriptors (CPU only: no compute call)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1806_10889_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tissue.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tissue_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1806_10889_amd import tissue as T
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(T.lib, n), n
+    assert sorted(T.EXPORTS) == names
+
+
+def test_required_bytes_and_validation():
+    from paper_1806_10889_amd import tissue as T
+    p = W.config2(side=8)
+    assert T.required_bytes(p) > W.n_voxels(p) * 5 * 4 * 2
+    assert T.required_bytes(W.config1()) > 0
+    assert T.required_bytes(p, trace_steps=5) > T.required_bytes(p)
+
+    def bad(mut):
+        q = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+        mut(q)
+        assert T.required_bytes(q) == 0, T.lib.tissue_last_error()
+        return T.lib.tissue_last_error().decode()
+
+    assert "rates" in bad(lambda q: q["rates"].__setitem__(0, -1.0))
+    assert "rates" in bad(lambda q: q["rates"].__setitem__(0, float("nan")))
+    assert "diffusion" in bad(lambda q: q["diffusion"].__setitem__(0, float("inf")))
+    assert "init_counts" in bad(lambda q: q["init_counts"].__setitem__((0, 0), -1))
+    assert "init_counts" in bad(lambda q: q["init_counts"].__setitem__((0, 0), 1 << 26))
+    assert "mesh" in bad(lambda q: q["mesh_w"].__setitem__(0, 9))
+    assert "mesh" in bad(lambda q: q["mesh_h"].__setitem__(3, 0))
+    assert "sim_id" in bad(lambda q: q.__setitem__("sim_id", 1 << 30))
+    assert "distinct" in bad(lambda q: q.__setitem__("trans_d", q["trans_n"]))
+    assert "lattice" in bad(lambda q: q.__setitem__("lattice", 2))
+
+    def consume_unsupplied(q):
+        q["stoich"] = q["stoich"].copy()
+        q["stoich"][0, 1] = -1  # 0 -> N would also remove a D it does not have
+    assert "consumes" in bad(consume_unsupplied)
+
+    def reactant_range(q):
+        q["reactants"] = q["reactants"].copy()
+        q["reactants"][1, 0] = 7
+    assert "reactant" in bad(reactant_range)
+
+
+def test_error_strings():
+    from paper_1806_10889_amd import tissue as T
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert T.lib.tissue_strerror(code)
+    assert T.lib.tissue_strerror(-99) == b"unknown error"

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU FP64 oracle.
+
+Bit-exact on every integer count, on the per-(cell, step) and per-(edge,
+step) event counts and on the bits of each unit-step's last event time, and
+on the event/draw totals.  Sizes span several work items and ragged tails;
+the last tests run the full-size workloads for a few steps in the launch
+configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import assert_same, gpu_run
+from paper_1806_10889_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(oracle_lib, p, n, trace=True, **kw):
+    return oracle_lib.run(p, p["dt"], n, trace=trace, **kw)
+
+
+def test_config1_full_horizon(oracle_lib):
+    p = W.config1()
+    o = _oracle(oracle_lib, p, p["n_steps"])
+    g = gpu_run(p, p["n_steps"], trace=True)
+    assert o.chi_events > 1000
+    assert_same(g, o)
+
+
+def test_config2_reduced(oracle_lib):
+    p = W.config2(side=9, n_steps=12)  # 81 cells: two chi items, ragged S tail
+    o = _oracle(oracle_lib, p, 12)
+    g = gpu_run(p, 12, trace=True)
+    assert o.chi_events > 10000 and o.s_events > 1000
+    assert_same(g, o)
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_uneven_meshes_overlapping_faces(oracle_lib, lattice):
+    p = W.random_problem(31 + lattice, lattice=lattice, nx=9, ny=7, model="nd5", uneven=True,
+                         dt=0.05, n_steps=6)
+    o = _oracle(oracle_lib, p, 6)
+    g = gpu_run(p, 6, trace=True)
+    assert o.s_events > 0
+    assert_same(g, o)
+
+
+@pytest.mark.parametrize("mesh", [(1, 1), (2, 2), (2, 1), (3, 5), (8, 8), (7, 3), (1, 8)])
+def test_mesh_shapes(oracle_lib, mesh):
+    p = W.random_problem(40 + mesh[0] * 8 + mesh[1], lattice=1, nx=5, ny=4, model="nd5",
+                         mesh=mesh, dt=0.05, n_steps=4)
+    o = _oracle(oracle_lib, p, 4)
+    assert_same(gpu_run(p, 4, trace=True), o)
+
+
+def test_nd4_well_mixed_square(oracle_lib):
+    p = W.random_problem(50, lattice=0, nx=13, ny=11, model="nd4", mesh=(1, 1), dt=0.1,
+                         n_steps=20, rate_lo=-1.0, rate_hi=1.0)
+    o = _oracle(oracle_lib, p, 20)
+    assert_same(gpu_run(p, 20, trace=True), o)
+
+
+@pytest.mark.parametrize("persistent,wpc,chunk", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 3, 2),
+                                                  (0, 0, 3), (1, 8, 5)])
+def test_launch_shapes_do_not_change_bits(oracle_lib, persistent, wpc, chunk):
+    p = W.random_problem(60, lattice=1, nx=11, ny=10, model="nd5", uneven=True, dt=0.05,
+                         n_steps=7)
+    o = _oracle(oracle_lib, p, 7)
+    g = gpu_run(p, 7, trace=True, persistent=persistent, wpc=wpc, graph_chunk=chunk)
+    assert_same(g, o)
+
+
+def test_chunking_restart_and_resume(oracle_lib):
+    from paper_1806_10889_amd import tissue as T
+    p = W.random_problem(70, lattice=1, nx=8, ny=8, model="nd5", mesh=(4, 4), dt=0.05, n_steps=9)
+    o = _oracle(oracle_lib, p, 9, trace=False)
+    g = gpu_run(p, 9, chunks=[2, 3, 4])
+    assert np.array_equal(g["counts"], o.counts)
+    t = T.Tissue(p)
+    t.set_graph_chunk(2)
+    t.step(p["dt"], 9)
+    a = t.read_counts()
+    t.restart(p["sim_id"], 0)
+    t.step(p["dt"], 9)
+    assert np.array_equal(t.read_counts(), a)
+    assert np.array_equal(a, o.counts)
+    # resume from a snapshot: run 4, snapshot, new tissue from step 4
+    t.restart(p["sim_id"], 0)
+    t.step(p["dt"], 4)
+    snap = t.read_counts()
+    q = dict(p, init_counts=snap.reshape(p["init_counts"].shape), start_step=4)
+    t2 = T.Tissue(q)
+    t2.step(p["dt"], 5)
+    assert np.array_equal(t2.read_counts(), o.counts)
+    # another sim_id is another stream
+    t.restart(p["sim_id"] + 1, 0)
+    t.step(p["dt"], 9)
+    other = t.read_counts()
+    o2 = oracle_lib.run(dict(p, sim_id=p["sim_id"] + 1), p["dt"], 9)
+    assert np.array_equal(other, o2.counts) and not np.array_equal(other, a)
+
+
+def test_batch_equals_plain_and_oracle(oracle_lib):
+    from paper_1806_10889_amd import tissue as T
+    probs = [
+        W.random_problem(80, lattice=1, nx=9, ny=9, model="nd5", mesh=(4, 4), dt=0.05, sim_id=3),
+        W.random_problem(81, lattice=1, nx=5, ny=7, model="nd5", uneven=True, dt=0.05, sim_id=4),
+        W.random_problem(82, lattice=0, nx=6, ny=4, model="nd4", mesh=(1, 1), dt=0.05, sim_id=5),
+        W.random_problem(83, lattice=0, nx=3, ny=3, model="nd5", mesh=(2, 3), dt=0.05, sim_id=6),
+        W.random_problem(84, lattice=1, nx=1, ny=1, model="nd5", mesh=(4, 4), dt=0.05, sim_id=7),
+        W.random_problem(85, lattice=1, nx=4, ny=4, model="bd", mesh=(1, 1), dt=0.05, sim_id=8),
+    ]
+    probs[3]["start_step"] = 17
+    n = 6
+    ts = [T.Tissue(p) for p in probs]
+    b = T.Batch(ts)
+    b.step(0.05, 2)
+    b.set_launch(False)
+    b.step(0.05, 4)
+    b.sync()
+    for p, t in zip(probs, ts):
+        o = oracle_lib.run(p, 0.05, n)
+        assert np.array_equal(t.read_counts(), o.counts), p["name"]
+        st = t.stats()
+        assert (st["chi_events"], st["s_events"], st["draws"]) == (o.chi_events, o.s_events, o.draws)
+        assert st["steps_done"] == p["start_step"] + n
+
+
+def test_config4_sampled_tissues(oracle_lib):
+    from paper_1806_10889_amd import tissue as T
+    probs = W.config4(n_tissues=40, side_hi=24, n_steps=5)
+    ts = [T.Tissue(p) for p in probs]
+    b = T.Batch(ts)
+    b.step(probs[0]["dt"], 5)
+    b.sync()
+    sizes = np.array([p["nx"] for p in probs])
+    sample = list(np.argsort(sizes)[:4]) + [5, 17, 29, 39]
+    for i in sample:
+        o = oracle_lib.run(probs[i], probs[i]["dt"], 5)
+        assert np.array_equal(ts[i].read_counts(), o.counts), i
+
+
+def test_edge_cases(oracle_lib):
+    from paper_1806_10889_amd import tissue as T
+    # one cell: no edges
+    p = W.random_problem(90, lattice=1, nx=1, ny=1, model="nd5", mesh=(3, 3), dt=0.05)
+    assert_same(gpu_run(p, 3, trace=True), _oracle(oracle_lib, p, 3))
+    # everything zero: no event, no draw
+    p = W.random_problem(91, lattice=0, nx=3, ny=2, model="nd5", mesh=(2, 2), dt=0.05)
+    p["init_counts"][:] = 0
+    p["rates"][[0, 2]] = 0.0
+    g = gpu_run(p, 3, trace=True)
+    assert g["stats"]["draws"] == 0 and np.all(g["counts"] == 0)
+    assert_same(g, _oracle(oracle_lib, p, 3))
+    # S disabled
+    p = W.random_problem(92, lattice=1, nx=4, ny=3, model="nd5", mesh=(4, 4), dt=0.05)
+    p["trans_n"] = -1
+    g = gpu_run(p, 3, trace=True)
+    assert g["stats"]["s_events"] == 0
+    assert_same(g, _oracle(oracle_lib, p, 3))
+    # event cap: both stop the unit-step at the cap and flag it
+    p = W.birth_death(5e4, 0.0, 0, nx=3, ny=2, dt=1.0)
+    p["event_cap"] = 777
+    o = oracle_lib.run(p, 1.0, 2)
+    assert o.capped
+    t = T.Tissue(p)
+    t.step(1.0, 2)
+    with pytest.raises(T.TissueError) as ei:
+        t.read_counts()
+    assert ei.value.code == T.ELIMIT
+    assert np.array_equal(t.read_counts(allow_flags=True), o.counts)
+    # overflow: a count crosses 2^26
+    p = W.birth_death(50.0, 0.0, (1 << 26) - 5, nx=2, ny=1, dt=1.0)
+    o = oracle_lib.run(p, 1.0, 1)
+    assert o.overflow
+    t = T.Tissue(p)
+    t.step(1.0, 1)
+    with pytest.raises(T.TissueError) as ei:
+        t.read_counts()
+    assert ei.value.code == T.EOVERFLOW
+    assert np.array_equal(t.read_counts(allow_flags=True), o.counts)
+
+
+def test_invalid_calls_enqueue_nothing():
+    from paper_1806_10889_amd import tissue as T
+    p = W.random_problem(93, lattice=1, nx=3, ny=3, model="nd5", mesh=(2, 2), dt=0.05)
+    t = T.Tissue(p)
+    for dt, n in [(0.0, 1), (-1.0, 1), (float("nan"), 1), (float("inf"), 1), (0.1, -1)]:
+        with pytest.raises(T.TissueError) as ei:
+            t.step(dt, n)
+        assert ei.value.code == T.EINVAL
+    assert t.stats()["steps_done"] == 0
+    assert np.array_equal(t.read_counts(), p["init_counts"].ravel())
+    with pytest.raises(T.TissueError):
+        t.trace(0, 1)  # created without trace
+    with pytest.raises(T.TissueError):
+        T.Tissue(dict(p, sim_id=1 << 30))
+
+
+def test_config3_reduced_uneven(oracle_lib):
+    p = W.config3(side=24, n_steps=3)
+    o = _oracle(oracle_lib, p, 3)
+    assert_same(gpu_run(p, 3, trace=True), o)
+
+
+def test_full_size_config2_bench_launch(oracle_lib):
+    """The 64x64 hex, 4x4-voxel workload at full size, persistent launches
+    replayed from a captured graph (as the benchmark runs it), two steps
+    against the oracle on every cell."""
+    p = W.config2()
+    o = _oracle(oracle_lib, p, 2)
+    g = gpu_run(p, 2, trace=True, persistent=1, graph_chunk=1)
+    assert_same(g, o)
+
+
+def test_gpu_birth_death_ensemble_law():
+    """GPU ensemble of 16384 independent well-mixed cells: birth-death
+    transient law (mean, variance within 3 SE; KS after the randomised PIT)."""
+    import math
+
+    from scipy import stats
+
+    import refmath
+    k, gamma, x0, dt, n = 5.0, 0.5, 20, 0.1, 20
+    p = W.birth_death(k, gamma, x0, nx=128, ny=128, dt=dt, n_steps=n, seed=99)
+    x = gpu_run(p, n)["counts"].astype(np.int64)
+    q = math.exp(-gamma * dt * n)
+    mean = x0 * q + (k / gamma) * (1 - q)
+    var = x0 * q * (1 - q) + (k / gamma) * (1 - q)
+    assert abs(x.mean() - mean) < 3 * math.sqrt(var / x.size)
+    pmf = np.convolve(stats.binom.pmf(np.arange(x0 + 1), x0, q),
+                      stats.poisson.pmf(np.arange(120), (k / gamma) * (1 - q)))[:120]
+    m4 = float(np.sum(pmf * (np.arange(120) - mean) ** 4))
+    assert abs(x.var() - var) < 3 * math.sqrt((m4 - var ** 2) / x.size)
+    assert refmath.discrete_ks_pvalue(x, pmf) > 0.01
