@@ -119,7 +119,7 @@ typedef struct {
     uint32_t steps_done;      /* global index of the next step                  */
     uint32_t overflow;        /* nonzero: a count left [0, 2^26)                */
     uint32_t capped;          /* nonzero: a unit-step hit event_cap             */
-    uint32_t n_cells, n_edges, n_voxels;
+    uint32_t n_cells, n_edges, n_voxels; /* n_edges: edges of the S operator (0 without S) */
 } tissue_stats_t;
 
 /* Device bytes a tissue needs in dev_buf (admission by free memory).

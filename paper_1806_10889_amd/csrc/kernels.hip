@@ -63,13 +63,64 @@ __device__ __forceinline__ void leave_queue(uint32_t *queue, bool persistent)
     }
 }
 
+// Wave-uniform copies: the tissue record is reached through a pointer read
+// from memory, so the compiler cannot prove its fields uniform; reading them
+// once per work item and broadcasting lane 0's value keeps them in scalar
+// registers for the whole event loop.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ double uni(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = uni((uint32_t)b), hi = uni((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ uint64_t uni(uint64_t v)
+{
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
+// The network of one tissue, in scalar registers.  Loops over it are
+// fully unrolled to the table sizes with uniform guards, so every index is
+// a compile-time constant.
+struct ModelR {
+    int S, R, ND;
+    int ra[kMaxReactions], rb[kMaxReactions];
+    uint32_t code[kMaxReactions];
+    double rate[kMaxReactions];
+    int dsp[kMaxSpecies];
+    double drate[kMaxSpecies];
+};
+
+__device__ __forceinline__ void load_model(const DevModel &M, ModelR &m)
+{
+    m.S = uni(M.n_species);
+    m.R = uni(M.n_reactions);
+    m.ND = uni(M.n_diff);
+#pragma unroll
+    for (int r = 0; r < kMaxReactions; ++r) {
+        m.ra[r] = uni((int)M.reac_a[r]);
+        m.rb[r] = uni((int)M.reac_b[r]);
+        m.code[r] = uni(M.change_code[r]);
+        m.rate[r] = uni(M.rates[r]);
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxSpecies; ++q) {
+        m.dsp[q] = uni((int)M.diff_species[q]);
+        m.drate[q] = uni(M.diff_rate[q]);
+    }
+}
+
 // Mass-action propensity of reaction r; x points at species 0 of a voxel,
 // species s at x[s * stride].
-__device__ __forceinline__ double reaction_propensity(const DevModel &M, int r,
-                                                      const int32_t *x, int stride)
+__device__ __forceinline__ double reaction_propensity(const ModelR &m, int r, const int32_t *x,
+                                                      int stride)
 {
-    const int a = M.reac_a[r], b = M.reac_b[r];
-    const double c = M.rates[r];
+    const int a = m.ra[r], b = m.rb[r];
+    const double c = m.rate[r];
     if (a < 0) return c;
     const long long xa = x[a * stride];
     if (b < 0) return c * (double)xa;
@@ -77,39 +128,57 @@ __device__ __forceinline__ double reaction_propensity(const DevModel &M, int r,
     return c * (double)(xa * (long long)x[b * stride]);
 }
 
-__device__ __forceinline__ int voxel_degree(int v, int w, int h)
+// Voxel v = y*w + x of a w x h mesh (v < 64, w <= 8): y = (v * inv_w) >> 16
+// with inv_w = 65536 / w + 1, exact on that range.
+struct Mesh {
+    int w, h, inv_w;
+};
+
+__device__ __forceinline__ void voxel_xy(const Mesh &g, int v, int &x, int &y)
 {
-    const int x = v % w, y = v / w;
-    return (x > 0) + (x < w - 1) + (y > 0) + (y < h - 1);
+    y = (v * g.inv_w) >> 16;
+    x = v - y * g.w;
+}
+
+__device__ __forceinline__ int voxel_degree(const Mesh &g, int v)
+{
+    int x, y;
+    voxel_xy(g, v, x, y);
+    return (x > 0) + (x < g.w - 1) + (y > 0) + (y < g.h - 1);
 }
 
 // Propensity of voxel v: left fold over reactions, then diffusion channels.
-__device__ __forceinline__ double voxel_propensity(const DevModel &M, const int32_t *cnt,
-                                                   int stride, int S, int v, int w, int h)
+__device__ __forceinline__ double voxel_propensity(const ModelR &m, const int32_t *cnt, int stride,
+                                                   int v, const Mesh &g)
 {
-    const int32_t *x = cnt + v * S * stride;
+    const int32_t *x = cnt + v * m.S * stride;
     double acc = 0.0;
-    for (int r = 0; r < M.n_reactions; ++r) acc = acc + reaction_propensity(M, r, x, stride);
-    const int deg = voxel_degree(v, w, h);
+#pragma unroll
+    for (int r = 0; r < kMaxReactions; ++r)
+        if (r < m.R) acc = acc + reaction_propensity(m, r, x, stride);
+    const int deg = voxel_degree(g, v);
     if (deg > 0) {
-        for (int q = 0; q < M.n_diff; ++q) {
-            const long long xs = x[M.diff_species[q] * stride];
-            acc = acc + M.diff_rate[q] * (double)(xs * deg);
-        }
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; ++q)
+            if (q < m.ND) {
+                const long long xs = x[m.dsp[q] * stride];
+                acc = acc + m.drate[q] * (double)(xs * deg);
+            }
     }
     return acc;
 }
 
 // Destination of a diffusion jump: the kdir-th present neighbour in the
 // order (-x, +x, -y, +y).
-__device__ __forceinline__ int neighbour_at(int v, int w, int h, int kdir)
+__device__ __forceinline__ int neighbour_at(const Mesh &g, int v, int kdir)
 {
-    const int x = v % w, y = v / w;
+    int x, y;
+    voxel_xy(g, v, x, y);
     int out = v, idx = 0;
     if (x > 0) { if (idx == kdir) out = v - 1; ++idx; }
-    if (x < w - 1) { if (idx == kdir) out = v + 1; ++idx; }
-    if (y > 0) { if (idx == kdir) out = v - w; ++idx; }
-    if (y < h - 1) { if (idx == kdir) out = v + w; }
+    if (x < g.w - 1) { if (idx == kdir) out = v + 1; ++idx; }
+    if (y > 0) { if (idx == kdir) out = v - g.w; ++idx; }
+    if (y < g.h - 1) { if (idx == kdir) out = v + g.w; }
     return out;
 }
 
@@ -145,31 +214,41 @@ __global__ __launch_bounds__(kWave) void chi_kernel(const DevTissue *const *tbl,
         const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const ChiItem item = items[it];
-        const DevTissue *T = tbl[item.tissue];
-        const DevModel &M = T->model;
-        const int S = M.n_species;
-        double *tree = reinterpret_cast<double *>(lds) + lane;                       // [2P][stride]
+        const DevTissue *T = tbl[uni(item.tissue)];
+        ModelR m;
+        load_model(T->model, m);
+        const int S = m.S;
+        const uint32_t first = uni(item.first), count = uni(item.count);
+        const uint32_t step = uni(T->step_base) + kstep;
+        const uint64_t seed = uni((uint64_t)T->seed);
+        const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+        const uint32_t tagword = (uni(T->sim_id) << 2) | 0u;
+        const uint32_t cap = uni(T->event_cap);
+        int32_t *counts = T->counts;
+        double *tree = reinterpret_cast<double *>(lds) + lane;  // [2P][stride]
         int32_t *cnt = reinterpret_cast<int32_t *>(lds + (size_t)2 * P * stride * 8) + lane;
 
-        const bool active = lane < (int)item.count;
+        const bool active = lane < (int)count;
         uint32_t cell = 0;
-        int w = 1, h = 1;
+        Mesh g{1, 1, 65537};
         long long gbase = 0;
         if (active) {
-            cell = (uint32_t)T->cell_list[item.first + lane];
-            w = T->wh[2 * cell];
-            h = T->wh[2 * cell + 1];
+            cell = (uint32_t)T->cell_list[first + lane];
+            g.w = T->wh[2 * cell];
+            g.h = T->wh[2 * cell + 1];
+            g.inv_w = 65536 / g.w + 1;
             gbase = (long long)T->vox_off[cell] * S;
-            const int n = w * h * S;
-            for (int i = 0; i < n; ++i) cnt[i * stride] = T->counts[gbase + i];
+            const int n = g.w * g.h * S;
+            for (int i = 0; i < n; ++i) cnt[i * stride] = counts[gbase + i];
         }
-        const int V = w * h;
-        const uint32_t step = T->step_base + kstep;
+        const int V = g.w * g.h;
 
         // leaves and internal nodes
         if (active) {
+#pragma unroll
             for (int v = 0; v < P; ++v)
-                tree[(P + v) * stride] = v < V ? voxel_propensity(M, cnt, stride, S, v, w, h) : 0.0;
+                tree[(P + v) * stride] = v < V ? voxel_propensity(m, cnt, stride, v, g) : 0.0;
+#pragma unroll
             for (int n = P - 1; n >= 1; --n)
                 tree[n * stride] = tree[(2 * n) * stride] + tree[(2 * n + 1) * stride];
         }
@@ -177,9 +256,6 @@ __global__ __launch_bounds__(kWave) void chi_kernel(const DevTissue *const *tbl,
         double t = 0.0;
         uint32_t j = 0, ev = 0;
         bool overflow = false, capped = false;
-        const uint32_t key0 = (uint32_t)T->seed, key1 = (uint32_t)(T->seed >> 32);
-        const uint32_t tagword = (T->sim_id << 2) | 0u;
-        const uint32_t cap = T->event_cap;
         if (active) {
             for (;;) {
                 const double a0 = tree[1 * stride];
@@ -217,36 +293,42 @@ __global__ __launch_bounds__(kWave) void chi_kernel(const DevTissue *const *tbl,
                 // channel of voxel v: first with a_k > 0 and r < prefix
                 // through k, else the last with a_k > 0
                 int32_t *x = cnt + v * S * stride;
-                const int deg = voxel_degree(v, w, h);
+                const int deg = voxel_degree(g, v);
                 double prefix = 0.0, resid = 0.0, last_prefix = 0.0;
                 int sel = -1, last = -1;
-                for (int k = 0; k < M.n_reactions; ++k) {
-                    const double a = reaction_propensity(M, k, x, stride);
-                    const double next = prefix + a;
-                    if (a > 0.0) {
-                        if (sel < 0 && r < next) {
-                            sel = k;
-                            resid = r - prefix;
-                        }
-                        last = k;
-                        last_prefix = prefix;
-                    }
-                    prefix = next;
-                }
-                if (deg > 0) {
-                    for (int q = 0; q < M.n_diff; ++q) {
-                        const long long xs = x[M.diff_species[q] * stride];
-                        const double a = M.diff_rate[q] * (double)(xs * deg);
+#pragma unroll
+                for (int k = 0; k < kMaxReactions; ++k) {
+                    if (k < m.R) {
+                        const double a = reaction_propensity(m, k, x, stride);
                         const double next = prefix + a;
                         if (a > 0.0) {
                             if (sel < 0 && r < next) {
-                                sel = M.n_reactions + q;
+                                sel = k;
                                 resid = r - prefix;
                             }
-                            last = M.n_reactions + q;
+                            last = k;
                             last_prefix = prefix;
                         }
                         prefix = next;
+                    }
+                }
+                if (deg > 0) {
+#pragma unroll
+                    for (int q = 0; q < kMaxSpecies; ++q) {
+                        if (q < m.ND) {
+                            const long long xs = x[m.dsp[q] * stride];
+                            const double a = m.drate[q] * (double)(xs * deg);
+                            const double next = prefix + a;
+                            if (a > 0.0) {
+                                if (sel < 0 && r < next) {
+                                    sel = kMaxReactions + q;
+                                    resid = r - prefix;
+                                }
+                                last = kMaxReactions + q;
+                                last_prefix = prefix;
+                            }
+                            prefix = next;
+                        }
                     }
                 }
                 if (sel < 0) {
@@ -255,10 +337,11 @@ __global__ __launch_bounds__(kWave) void chi_kernel(const DevTissue *const *tbl,
                 }
 
                 int dst = v;
-                if (sel < M.n_reactions) {
+                if (sel < kMaxReactions) {
                     uint32_t code = 0;
-                    for (int k = 0; k < M.n_reactions; ++k)
-                        if (k == sel) code = M.change_code[k];
+#pragma unroll
+                    for (int k = 0; k < kMaxReactions; ++k)
+                        if (k == sel) code = m.code[k];
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const uint32_t byte = (code >> (8 * b)) & 0xFFu;
@@ -271,19 +354,20 @@ __global__ __launch_bounds__(kWave) void chi_kernel(const DevTissue *const *tbl,
                         }
                     }
                 } else {
-                    const int q = sel - M.n_reactions;
                     int s = 0;
                     double D = 0.0;
-                    for (int qq = 0; qq < M.n_diff; ++qq)
-                        if (qq == q) {
-                            s = M.diff_species[qq];
-                            D = M.diff_rate[qq];
+#pragma unroll
+                    for (int q = 0; q < kMaxSpecies; ++q)
+                        if (kMaxReactions + q == sel) {
+                            s = m.dsp[q];
+                            D = m.drate[q];
                         }
                     const double a1 = D * (double)(long long)x[s * stride];
                     int kdir = 0;
-                    for (int l = 1; l <= deg - 1; ++l)
-                        if (resid >= (double)l * a1) ++kdir;
-                    dst = neighbour_at(v, w, h, kdir);
+#pragma unroll
+                    for (int l = 1; l <= 3; ++l)
+                        if (l <= deg - 1 && resid >= (double)l * a1) ++kdir;
+                    dst = neighbour_at(g, v, kdir);
                     const int32_t nsrc = x[s * stride] - 1;
                     x[s * stride] = nsrc;
                     int32_t *xd = cnt + (dst * S + s) * stride;
@@ -291,17 +375,17 @@ __global__ __launch_bounds__(kWave) void chi_kernel(const DevTissue *const *tbl,
                     *xd = ndst;
                     overflow |= (nsrc < 0) | (ndst >= kCountLimit);
                 }
-                tree[(P + v) * stride] = voxel_propensity(M, cnt, stride, S, v, w, h);
-                if (dst != v)
-                    tree[(P + dst) * stride] = voxel_propensity(M, cnt, stride, S, dst, w, h);
+                tree[(P + v) * stride] = voxel_propensity(m, cnt, stride, v, g);
+                if (dst != v) tree[(P + dst) * stride] = voxel_propensity(m, cnt, stride, dst, g);
                 update_path<P>(tree, stride, v);
                 if (dst != v) update_path<P>(tree, stride, dst);
                 ++ev;
             }
             const int n = V * S;
-            for (int i = 0; i < n; ++i) T->counts[gbase + i] = cnt[i * stride];
+            for (int i = 0; i < n; ++i) counts[gbase + i] = cnt[i * stride];
             if (T->tr_chi_ev) {
-                const size_t slot = (size_t)(step % T->trace_steps) * T->n_cells + cell;
+                const uint32_t ts = uni(T->trace_steps), nc = uni(T->n_cells);
+                const size_t slot = (size_t)(step % ts) * nc + cell;
                 T->tr_chi_ev[slot] = ev;
                 T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
             }
@@ -336,32 +420,48 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
         const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const SItem item = items[it];
-        const DevTissue *T = tbl[item.tissue];
-        const DevModel &M = T->model;
-        const int S = M.n_species;
-        const bool active = lane < (int)item.count;
-        const uint32_t e = item.first + lane;
-        const uint32_t step = T->step_base + kstep;
+        const DevTissue *T = tbl[uni(item.tissue)];
+        const int S = uni(T->model.n_species);
+        const int sp0 = uni(T->model.trans_n), sp1 = uni(T->model.trans_d), sp2 = uni(T->model.trans_i);
+        const double c = uni(T->model.trans_rate);
+        const uint32_t first = uni(item.first), count = uni(item.count);
+        const uint32_t step = uni(T->step_base) + kstep;
+        const uint64_t seed = uni((uint64_t)T->seed);
+        const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+        const uint32_t tagword = (uni(T->sim_id) << 2) | 1u;
+        const uint32_t cap = uni(T->event_cap);
+        int32_t *counts = T->counts;
+        const bool active = lane < (int)count;
+        const uint32_t e = first + lane;
         double t = 0.0;
         uint32_t j = 0, ev = 0;
         bool overflow = false, capped = false;
         if (active) {
-            const EdgeRec &er = T->edges[e];
-            const int mA = er.m_a, mB = er.m_b;
-            const int sp[3] = {M.trans_n, M.trans_d, M.trans_i};
-            for (int a = 0; a < mA; ++a) {
-                const long long g = (long long)(er.vox_i + er.A[a]) * S;
+            const EdgeRec *er = T->edges + e;
+            const int mA = er->m_a, mB = er->m_b;
+            const long long gi = (long long)er->vox_i, gj = (long long)er->vox_j;
+            uint8_t A[kMaxFace], B[kMaxFace];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) fa[q][a][lane] = T->counts[g + sp[q]];
+            for (int a = 0; a < kMaxFace; ++a) {
+                A[a] = er->A[a];
+                B[a] = er->B[a];
             }
-            for (int b = 0; b < mB; ++b) {
-                const long long g = (long long)(er.vox_j + er.B[b]) * S;
 #pragma unroll
-                for (int q = 0; q < 3; ++q) fb[q][b][lane] = T->counts[g + sp[q]];
-            }
-            const double c = M.trans_rate;
-            const uint32_t key0 = (uint32_t)T->seed, key1 = (uint32_t)(T->seed >> 32);
-            const uint32_t tagword = (T->sim_id << 2) | 1u;
+            for (int a = 0; a < kMaxFace; ++a)
+                if (a < mA) {
+                    const long long g = (gi + A[a]) * S;
+                    fa[0][a][lane] = counts[g + sp0];
+                    fa[1][a][lane] = counts[g + sp1];
+                    fa[2][a][lane] = counts[g + sp2];
+                }
+#pragma unroll
+            for (int b = 0; b < kMaxFace; ++b)
+                if (b < mB) {
+                    const long long g = (gj + B[b]) * S;
+                    fb[0][b][lane] = counts[g + sp0];
+                    fb[1][b][lane] = counts[g + sp1];
+                    fb[2][b][lane] = counts[g + sp2];
+                }
             const int half = mA * mB;
             for (;;) {
                 // channels: N_i(a) D_j(b) for a, b; then N_j(b) D_i(a) for b, a
@@ -373,7 +473,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                     for (int a = 0; a < mA; ++a)
                         a0 = a0 + c * (double)((long long)fb[0][b][lane] * fa[1][a][lane]);
                 if (a0 == 0.0) break;
-                if (ev >= T->event_cap) {
+                if (ev >= cap) {
                     capped = true;
                     break;
                 }
@@ -412,13 +512,13 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 if (sel < 0) sel = last;
                 int32_t nN, nD, nI;
                 if (sel < half) {
-                    const int a = sel / mB, b = sel % mB;
+                    const int a = sel / mB, b = sel - (sel / mB) * mB;
                     nN = --fa[0][a][lane];
                     nD = --fb[1][b][lane];
                     nI = ++fa[2][a][lane];
                 } else {
                     const int kk = sel - half;
-                    const int b = kk / mA, a = kk % mA;
+                    const int b = kk / mA, a = kk - (kk / mA) * mA;
                     nN = --fb[0][b][lane];
                     nD = --fa[1][a][lane];
                     nI = ++fb[2][b][lane];
@@ -426,18 +526,25 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 overflow |= (nN < 0) | (nD < 0) | (nI >= kCountLimit);
                 ++ev;
             }
-            for (int a = 0; a < mA; ++a) {
-                const long long g = (long long)(er.vox_i + er.A[a]) * S;
 #pragma unroll
-                for (int q = 0; q < 3; ++q) T->counts[g + sp[q]] = fa[q][a][lane];
-            }
-            for (int b = 0; b < mB; ++b) {
-                const long long g = (long long)(er.vox_j + er.B[b]) * S;
+            for (int a = 0; a < kMaxFace; ++a)
+                if (a < mA) {
+                    const long long g = (gi + A[a]) * S;
+                    counts[g + sp0] = fa[0][a][lane];
+                    counts[g + sp1] = fa[1][a][lane];
+                    counts[g + sp2] = fa[2][a][lane];
+                }
 #pragma unroll
-                for (int q = 0; q < 3; ++q) T->counts[g + sp[q]] = fb[q][b][lane];
-            }
+            for (int b = 0; b < kMaxFace; ++b)
+                if (b < mB) {
+                    const long long g = (gj + B[b]) * S;
+                    counts[g + sp0] = fb[0][b][lane];
+                    counts[g + sp1] = fb[1][b][lane];
+                    counts[g + sp2] = fb[2][b][lane];
+                }
             if (T->tr_s_ev) {
-                const size_t slot = (size_t)(step % T->trace_steps) * T->n_edges + e;
+                const uint32_t ts = uni(T->trace_steps), ne = uni(T->n_edges);
+                const size_t slot = (size_t)(step % ts) * ne + e;
                 T->tr_s_ev[slot] = ev;
                 T->tr_s_t[slot] = (unsigned long long)__double_as_longlong(t);
             }

@@ -12,6 +12,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: its bundled HIP runtime and the system one share a soname, so
+# whichever is loaded first serves the whole process; libtissue must bind to
+# the runtime that owns torch's device memory and streams.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtissue.so")
