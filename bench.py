@@ -171,6 +171,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures "
@@ -179,9 +181,18 @@ def main():
         sys.exit(2)
 
     import torch
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
+        return
     from paper_1806_10889_amd import tissue as T
     from paper_1806_10889_amd import workloads as W
-    torch.cuda.set_device(0)
 
     plain = run_plain(args, torch, T, W)
     out = {

@@ -69,7 +69,8 @@ enum {
 enum { TISSUE_LATTICE_SQUARE = 0, TISSUE_LATTICE_HEX = 1 };
 
 /* descriptor flags */
-#define TISSUE_FLAG_TRACE 1u /* keep per-(unit, step) event counts and clocks */
+#define TISSUE_FLAG_TRACE 1u  /* keep per-(unit, step) event counts and clocks */
+#define TISSUE_FLAG_NO_JIT 2u /* use the ahead-of-time generic chi kernels only  */
 
 #define TISSUE_MAX_SPECIES 8
 #define TISSUE_MAX_REACTIONS 16
@@ -120,7 +121,13 @@ typedef struct {
     uint32_t overflow;        /* nonzero: a count left [0, 2^26)                */
     uint32_t capped;          /* nonzero: a unit-step hit event_cap             */
     uint32_t n_cells, n_edges, n_voxels; /* n_edges: edges of the S operator (0 without S) */
+    uint32_t jit;             /* nonzero: chi runs kernels compiled for this network */
 } tissue_stats_t;
+
+/* Validate d and compile the chi kernels for its network's structure
+ * without loading them (needs no device).  TISSUE_EDEVICE with the compiler
+ * log in tissue_last_error() if the compilation fails. */
+int tissue_network_check(const tissue_desc_t *d);
 
 /* Device bytes a tissue needs in dev_buf (admission by free memory).
  * Returns 0 for an invalid descriptor. */
@@ -128,7 +135,10 @@ size_t tissue_required_bytes(const tissue_desc_t *d);
 
 /* Validate d, build the lattice, edges, colour classes, meshes and face
  * groups on the host, lay the state out in dev_buf (>= required bytes,
- * 256-byte aligned) and upload it on hip_stream (NULL: the null stream). */
+ * 256-byte aligned) and upload it on hip_stream (NULL: the null stream).
+ * Unless TISSUE_FLAG_NO_JIT is set, the chi kernels are compiled for the
+ * network's structure (hipRTC, cached per process by structure, not rates);
+ * if that compilation fails the generic kernels are used (same bits). */
 int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes,
                   void *hip_stream, tissue_t **out);
 
@@ -167,6 +177,13 @@ int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in);
  * Results are bit-identical for every choice. */
 int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu);
 
+/* Kernel of the chi operator: 0 = one lane per cell (all cells), 1 = one
+ * 16-lane row per cell (cells of at most 16 voxels; larger cells keep one
+ * lane each), 2 = automatic (the default: rows for a leaf-count class when
+ * one lane per cell would leave SIMDs without a wavefront).  Results are
+ * bit-identical for every choice. */
+int tissue_set_chi_mode(tissue_t *t, int32_t mode);
+
 /* Steps captured per HIP graph launch (0 disables graphs). */
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
 
@@ -196,6 +213,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
 int tissue_batch_step(tissue_batch_t *b, double dt, int32_t n_steps);
 int tissue_batch_step_timed(tissue_batch_t *b, double dt, int32_t n_steps, tissue_timing_t *out);
 int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workgroups_per_cu);
+int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode);
 int tissue_batch_sync(tissue_batch_t *b);
 int tissue_batch_destroy(tissue_batch_t *b);
 

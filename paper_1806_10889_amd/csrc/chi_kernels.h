@@ -1,0 +1,654 @@
+// chi_kernels.h -- device code of the internal-dynamics operator chi and the
+// helpers shared by the device kernels.  Included by kernels.hip (generic
+// network policy, compiled ahead of time for gfx950) and by the source the
+// runtime compiles per network (compiled network policy).
+//
+// chi (paper: Algorithm section, "Internal cell dynamics module": every cell
+// updated independently over the splitting interval) runs Gillespie's
+// direct method over the voxels of each cell (RDME: reactions in a voxel,
+// diffusion jumps to adjacent voxels).  Two kernels compute identical bits:
+//   - one lane per cell: the lane's counts (int32) and its binary sum tree of
+//     voxel propensities (FP64) live in LDS, field-major with the lane index
+//     fastest, so 64 lanes touching "their" element hit 64 distinct banks;
+//   - one 16-lane row per cell (at most 16 voxels): lane l holds voxel l.
+// Work items (<= 64 cells of one tissue) come one per workgroup or, in
+// persistent mode, from a device queue every workgroup pulls from until it is
+// empty; the last workgroup to leave clears the queue for the next launch.
+#pragma once
+
+#include "device_math.h"
+#include "internal.h"
+
+namespace tissue_impl {
+namespace {
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Next work item for this workgroup (one wavefront).
+__device__ __forceinline__ uint32_t next_item(uint32_t *queue, bool persistent, uint32_t &cursor)
+{
+    if (!persistent) {
+        uint32_t it = cursor;
+        cursor = 0xFFFFFFFFu;
+        return it;
+    }
+    uint32_t it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(queue, 1u);
+    it = __shfl(it, 0, kWave);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)it);
+}
+
+// Called by every workgroup when it has no more items: the last one out
+// resets the queue and the exit counter (queue[0], queue[1]).
+__device__ __forceinline__ void leave_queue(uint32_t *queue, bool persistent)
+{
+    if (!persistent) return;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(queue + 1, 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(queue, 0u);
+            atomicExch(queue + 1, 0u);
+        }
+    }
+}
+
+// Wave-uniform copies: the tissue record is reached through a pointer read
+// from memory, so the compiler cannot prove its fields uniform; reading them
+// once per work item and broadcasting lane 0's value keeps them in scalar
+// registers for the whole event loop.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ double uni(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = uni((uint32_t)b), hi = uni((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ uint64_t uni(uint64_t v)
+{
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
+// A network policy supplies the channel structure of the chi kernels:
+//   SM, RM, NDM   species slots, reaction slots, diffusion slots;
+//   ra(r), rb(r)  reactants of reaction r (-1: none), dsp(q) species of
+//                 diffusion channel q, delta(r, s) net change;
+//   rate[r], drate[q] the tissue's constants (runtime, wave-uniform);
+//   load(M)       fill the runtime part from the tissue record.
+// NetGeneric keeps the whole structure in scalar registers, zero-padded to
+// the slot counts (a padding reaction has no reactants and rate 0, a padding
+// diffusion channel rate 0: each adds exactly 0.0 to every fold and is never
+// selected).  A compiled network (generated per network at tissue creation)
+// makes ra, rb, dsp and delta compile-time constants.
+template <int SM_, int RM_, int NDM_>
+struct NetGeneric {
+    static constexpr int SM = SM_, RM = RM_, NDM = NDM_;
+    int ra_[RM], rb_[RM];
+    uint32_t dlo_[RM], dhi_[RM];
+    int dsp_[NDM > 0 ? NDM : 1];
+    double rate[RM];
+    double drate[NDM > 0 ? NDM : 1];
+    __device__ __forceinline__ int ra(int r) const { return ra_[r]; }
+    __device__ __forceinline__ int rb(int r) const { return rb_[r]; }
+    __device__ __forceinline__ int dsp(int q) const { return dsp_[q]; }
+    __device__ __forceinline__ int delta(int r, int s) const
+    {
+        const uint32_t w = s < 4 ? dlo_[r] : dhi_[r];
+        return (int)(int8_t)((w >> (8 * (s & 3))) & 0xFFu);
+    }
+    __device__ __forceinline__ void load(const DevModel &M)
+    {
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            ra_[r] = uni((int)M.reac_a[r]);
+            rb_[r] = uni((int)M.reac_b[r]);
+            rate[r] = uni(M.rates[r]);
+            dlo_[r] = uni(M.delta_lo[r]);
+            dhi_[r] = uni(M.delta_hi[r]);
+        }
+#pragma unroll
+        for (int q = 0; q < NDM; ++q) {
+            dsp_[q] = uni((int)M.diff_species[q]);
+            drate[q] = uni(M.diff_rate[q]);
+        }
+    }
+};
+
+// Mass-action propensity of reaction r from the voxel's counts held as
+// doubles.  Counts are below 2^26, so every product of two counts is an
+// exact integer below 2^52 and equals the integer product converted.
+template <class NET>
+__device__ __forceinline__ double reaction_prop(const NET &n, int r, const double *xd)
+{
+    const int a = n.ra(r), b = n.rb(r);
+    if (a < 0) return n.rate[r];
+    const double xa = xd[a];
+    if (b < 0) return n.rate[r] * xa;
+    if (a == b) return n.rate[r] * ((xa * (xa - 1.0)) * 0.5);
+    return n.rate[r] * (xa * xd[b]);
+}
+
+// Fold of the voxel's channels (reactions, then diffusion D_s (x_s deg)).
+template <class NET>
+__device__ __forceinline__ double voxel_fold(const NET &n, const double *xd, double degd)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < NET::RM; ++r) acc = acc + reaction_prop(n, r, xd);
+#pragma unroll
+    for (int q = 0; q < NET::NDM; ++q) acc = acc + n.drate[q] * (xd[n.dsp(q)] * degd);
+    return acc;
+}
+
+// The selection scan over the same fold: the first channel with a_k > 0
+// and r < prefix through k, else the last channel with a_k > 0.  Returns the
+// channel slot (reactions 0..RM-1, diffusion RM + q), the residual r minus
+// the prefix before it, and for diffusion D_s x_s and s.
+template <class NET>
+__device__ __forceinline__ int voxel_select(const NET &n, const double *xd, double degd, double r,
+                                            double &resid, double &a1, int &spec)
+{
+    constexpr int RM = NET::RM, NDM = NET::NDM;
+    double acc = 0.0, before = 0.0, last_before = 0.0, a1_sel = 0.0, a1_last = 0.0;
+    int sel = -1, last = -1, s_sel = 0, s_last = 0;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+        const double a = reaction_prop(n, k, xd);
+        const double next = acc + a;
+        if (a > 0.0) {
+            if (sel < 0 && r < next) {
+                sel = k;
+                before = acc;
+            }
+            last = k;
+            last_before = acc;
+        }
+        acc = next;
+    }
+#pragma unroll
+    for (int q = 0; q < NDM; ++q) {
+        const double xs = xd[n.dsp(q)];
+        const double a = n.drate[q] * (xs * degd);
+        const double next = acc + a;
+        if (a > 0.0) {
+            const double one = n.drate[q] * xs;
+            if (sel < 0 && r < next) {
+                sel = RM + q;
+                before = acc;
+                a1_sel = one;
+                s_sel = n.dsp(q);
+            }
+            last = RM + q;
+            last_before = acc;
+            a1_last = one;
+            s_last = n.dsp(q);
+        }
+        acc = next;
+    }
+    if (sel < 0) {
+        sel = last;
+        before = last_before;
+        a1_sel = a1_last;
+        s_sel = s_last;
+    }
+    resid = r - before;
+    a1 = a1_sel;
+    spec = s_sel;
+    return sel;
+}
+
+// Net change of species s by reaction slot sel (a per-lane index).
+template <class NET>
+__device__ __forceinline__ int reaction_delta(const NET &n, int sel, int s)
+{
+    int d = 0;
+#pragma unroll
+    for (int k = 0; k < NET::RM; ++k) d += (k == sel) ? n.delta(k, s) : 0;
+    return d;
+}
+
+// Voxel v = y*w + x of a w x h mesh (v < 64, w <= 8): y = (v * inv_w) >> 16
+// with inv_w = 65536 / w + 1, exact on that range.
+struct Mesh {
+    int w, h, inv_w;
+};
+
+__device__ __forceinline__ void voxel_xy(const Mesh &g, int v, int &x, int &y)
+{
+    y = (v * g.inv_w) >> 16;
+    x = v - y * g.w;
+}
+
+__device__ __forceinline__ int voxel_degree(const Mesh &g, int v)
+{
+    int x, y;
+    voxel_xy(g, v, x, y);
+    return (x > 0) + (x < g.w - 1) + (y > 0) + (y < g.h - 1);
+}
+
+// Destination of a diffusion jump: the kdir-th present neighbour in the
+// order (-x, +x, -y, +y).
+__device__ __forceinline__ int neighbour_at(const Mesh &g, int v, int kdir)
+{
+    int x, y;
+    voxel_xy(g, v, x, y);
+    int out = v, idx = 0;
+    if (x > 0) { if (idx == kdir) out = v - 1; ++idx; }
+    if (x < g.w - 1) { if (idx == kdir) out = v + 1; ++idx; }
+    if (y > 0) { if (idx == kdir) out = v - g.w; ++idx; }
+    if (y < g.h - 1) { if (idx == kdir) out = v + g.w; }
+    return out;
+}
+
+// Index of the diffusion direction: #{l in 1..deg-1 : resid >= l * a1}.
+__device__ __forceinline__ int jump_direction(double resid, double a1, int deg)
+{
+    int kdir = 0;
+#pragma unroll
+    for (int l = 1; l <= 3; ++l)
+        if (l <= deg - 1 && resid >= (double)l * a1) ++kdir;
+    return kdir;
+}
+
+// Per-item uniform data of a tissue.
+struct ItemCtx {
+    const DevTissue *T;
+    int32_t *counts;
+    int S;
+    uint32_t first, count, step, key0, key1, tagword, cap;
+};
+
+__device__ __forceinline__ ItemCtx item_ctx(const DevTissue *const *tbl, const ChiItem &item,
+                                            uint32_t kstep)
+{
+    ItemCtx c;
+    c.T = tbl[uni(item.tissue)];
+    c.counts = c.T->counts;
+    c.S = uni(c.T->model.n_species);
+    c.first = uni(item.first);
+    c.count = uni(item.count);
+    c.step = uni(c.T->step_base) + kstep;
+    const uint64_t seed = uni((uint64_t)c.T->seed);
+    c.key0 = (uint32_t)seed;
+    c.key1 = (uint32_t)(seed >> 32);
+    c.tagword = (uni(c.T->sim_id) << 2) | 0u;
+    c.cap = uni(c.T->event_cap);
+    return c;
+}
+
+__device__ __forceinline__ void item_stats(const ItemCtx &c, uint32_t ev, uint32_t draws,
+                                           bool overflow, bool capped, int stat_slot)
+{
+    const uint32_t ev_sum = wave_sum_u32(ev);
+    const uint32_t dr_sum = wave_sum_u32(draws);
+    const bool any_over = __any(overflow);
+    const bool any_cap = __any(capped);
+    if (threadIdx.x == 0) {
+        if (ev_sum) atomicAdd(c.T->stats + stat_slot, (unsigned long long)ev_sum);
+        if (dr_sum) atomicAdd(c.T->stats + 2, (unsigned long long)dr_sum);
+        if (any_over) atomicOr(c.T->flags + 0, 1u);
+        if (any_cap) atomicOr(c.T->flags + 1, 1u);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// chi, one lane per cell.  LDS per lane: the sum tree (2P doubles) and the
+// cell's counts (P*S int32, voxel-major), field-major across lanes.
+// ---------------------------------------------------------------------------
+template <class NET>
+__device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissue *const *tbl,
+                                              const ChiItem *items, uint32_t n_items, uint32_t *queue,
+                                              int persistent, int cells_per_item, int log2p, double dt,
+                                              uint32_t kstep)
+{
+    constexpr int SM = NET::SM, RM = NET::RM;
+    const int lane = threadIdx.x;
+    const int stride = cells_per_item;
+    const int P = 1 << log2p;
+    uint32_t cursor = blockIdx.x;
+    for (;;) {
+        const uint32_t it = next_item(queue, persistent != 0, cursor);
+        if (it >= n_items) break;
+        const ChiItem item = items[it];
+        const ItemCtx c = item_ctx(tbl, item, kstep);
+        NET net;
+        net.load(c.T->model);
+        const int S = c.S;
+        double *tree = reinterpret_cast<double *>(lds) + lane;  // [2P][stride]
+        int32_t *cnt = reinterpret_cast<int32_t *>(lds + (size_t)2 * P * stride * 8) + lane;
+
+        const bool active = lane < (int)c.count;
+        uint32_t cell = 0;
+        Mesh g{1, 1, 65537};
+        long long gbase = 0;
+        if (active) {
+            cell = (uint32_t)c.T->cell_list[c.first + lane];
+            g.w = c.T->wh[2 * cell];
+            g.h = c.T->wh[2 * cell + 1];
+            g.inv_w = 65536 / g.w + 1;
+            gbase = (long long)c.T->vox_off[cell] * S;
+            const int n = g.w * g.h * S;
+            for (int i = 0; i < n; ++i) cnt[i * stride] = c.counts[gbase + i];
+        }
+        const int V = g.w * g.h;
+        double xd[SM];
+
+        if (active) {
+            for (int v = 0; v < P; ++v) {
+                double leaf = 0.0;
+                if (v < V) {
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(v * S + q) * stride];
+                    leaf = voxel_fold(net, xd, (double)voxel_degree(g, v));
+                }
+                tree[(P + v) * stride] = leaf;
+            }
+            for (int n = P - 1; n >= 1; --n)
+                tree[n * stride] = tree[(2 * n) * stride] + tree[(2 * n + 1) * stride];
+        }
+
+        double t = 0.0;
+        uint32_t j = 0, ev = 0;
+        bool overflow = false, capped = false;
+        if (active) {
+            for (;;) {
+                const double a0 = tree[1 * stride];
+                if (a0 == 0.0) break;
+                if (ev >= c.cap) {
+                    capped = true;
+                    break;
+                }
+                const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
+                ++j;
+                double u1, u2;
+                tdev::two_uniforms(wds, u1, u2);
+                const double tau = (-tdev::plog(u1)) / a0;
+                const double tn = t + tau;
+                if (tn >= dt) break;
+                t = tn;
+                double r = u2 * a0;
+
+                // descend the sum tree
+                int n = 1;
+                for (int lvl = 0; lvl < log2p; ++lvl) {
+                    const double L = tree[(2 * n) * stride];
+                    const double R = tree[(2 * n + 1) * stride];
+                    if (r < L || R == 0.0) {
+                        n = 2 * n;
+                    } else {
+                        r = r - L;
+                        n = 2 * n + 1;
+                    }
+                }
+                const int v = n - P;
+
+                // the voxel's counts, the channel, the change
+                int32_t *x = cnt + v * S * stride;
+#pragma unroll
+                for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
+                const int deg = voxel_degree(g, v);
+                double resid, a1;
+                int spec;
+                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1, spec);
+                int dst = v;
+                if (sel < RM) {
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) {
+                        const int d = reaction_delta(net, sel, q);
+                        if (q < S && d != 0) {
+                            xd[q] += (double)d;
+                            x[q * stride] = (int32_t)xd[q];
+                            overflow |= (xd[q] < 0.0) | (xd[q] >= (double)kCountLimit);
+                        }
+                    }
+                } else {
+                    dst = neighbour_at(g, v, jump_direction(resid, a1, deg));
+#pragma unroll
+                    for (int q = 0; q < SM; ++q)
+                        if (q == spec) xd[q] -= 1.0;
+                    x[spec * stride] -= 1;
+                    int32_t *xdst = cnt + (dst * S + spec) * stride;
+                    const int32_t nd = *xdst + 1;
+                    *xdst = nd;
+                    overflow |= nd >= kCountLimit;
+                }
+                tree[(P + v) * stride] = voxel_fold(net, xd, (double)deg);
+                if (dst != v) {
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(dst * S + q) * stride];
+                    tree[(P + dst) * stride] = voxel_fold(net, xd, (double)voxel_degree(g, dst));
+                }
+                // ancestors of the changed leaves
+                int na = (P + v) >> 1, nb = (P + dst) >> 1;
+                for (int lvl = 0; lvl < log2p; ++lvl) {
+                    tree[na * stride] = tree[(2 * na) * stride] + tree[(2 * na + 1) * stride];
+                    na >>= 1;
+                }
+                if (dst != v) {
+                    for (int lvl = 0; lvl < log2p; ++lvl) {
+                        tree[nb * stride] = tree[(2 * nb) * stride] + tree[(2 * nb + 1) * stride];
+                        nb >>= 1;
+                    }
+                }
+                ++ev;
+            }
+            const int n = V * S;
+            for (int i = 0; i < n; ++i) c.counts[gbase + i] = cnt[i * stride];
+            if (c.T->tr_chi_ev) {
+                const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
+                const size_t slot = (size_t)(c.step % ts) * nc + cell;
+                c.T->tr_chi_ev[slot] = ev;
+                c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
+            }
+        }
+        item_stats(c, ev, j, overflow, capped, 0);
+    }
+    leave_queue(queue, persistent != 0);
+}
+
+// ---------------------------------------------------------------------------
+// chi, one 16-lane row per cell (cells of at most 16 voxels): lane l of the
+// row holds voxel l's counts (as exact doubles) and leaf propensity.  The
+// sum tree is rebuilt in registers after every event by four in-row DPP
+// exchanges (pair, quad, half-row, row); the descent is evaluated by every
+// lane along the path to its own leaf, and exactly one lane finds all its
+// decisions consistent.  Draws are made 16 at a time, one per lane.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int plo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    const int phi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(phi, plo);
+}
+
+constexpr int kDppPairSwap = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+// One descent level: children L (left) and R of the lane's ancestor, given
+// the lane's own subtree sum and its sibling's; bit = lane's side.
+__device__ __forceinline__ void descent_level(double own, double sib, int bit, double &r, bool &on)
+{
+    const double L = bit ? sib : own;
+    const double R = bit ? own : sib;
+    const bool left = (r < L) || (R == 0.0);
+    on = on && (left == (bit == 0));
+    r = left ? r : r - L;
+}
+
+}  // namespace
+
+// LDS of the row kernel: per lane one pre-drawn (-plog(U1), U2) pair, per
+// row the broadcast word of a diffusion event (1 | spec << 4 | dst << 8).
+struct RowShared {
+    double rng_e[kWave];
+    double rng_u[kWave];
+    uint32_t row_event[4];
+};
+
+template <class NET>
+__device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *const *tbl,
+                                             const ChiItem *items, uint32_t n_items, uint32_t *queue,
+                                             int persistent, double dt, uint32_t kstep)
+{
+    constexpr int SM = NET::SM, RM = NET::RM;
+    double *rng_e = sh.rng_e;
+    double *rng_u = sh.rng_u;
+    uint32_t *row_event = sh.row_event;
+    const int lane = threadIdx.x, row = lane >> 4, lv = lane & 15;
+    uint32_t cursor = blockIdx.x;
+    for (;;) {
+        const uint32_t it = next_item(queue, persistent != 0, cursor);
+        if (it >= n_items) break;
+        const ChiItem item = items[it];
+        const ItemCtx c = item_ctx(tbl, item, kstep);
+        NET net;
+        net.load(c.T->model);
+        const int S = c.S;
+
+        const bool has_cell = row < (int)c.count;
+        uint32_t cell = 0;
+        Mesh g{1, 1, 65537};
+        long long vbase = 0;
+        if (has_cell) {
+            cell = (uint32_t)c.T->cell_list[c.first + row];
+            g.w = c.T->wh[2 * cell];
+            g.h = c.T->wh[2 * cell + 1];
+            g.inv_w = 65536 / g.w + 1;
+            vbase = (long long)(c.T->vox_off[cell] + lv) * S;
+        }
+        const bool vox = has_cell && lv < g.w * g.h;
+        double xd[SM];
+#pragma unroll
+        for (int q = 0; q < SM; ++q) xd[q] = (vox && q < S) ? (double)c.counts[vbase + q] : 0.0;
+        const int deg = vox ? voxel_degree(g, lv) : 0;
+        const double degd = (double)deg;
+        double leaf = vox ? voxel_fold(net, xd, degd) : 0.0;
+
+        double t = 0.0;
+        uint32_t j = 0, ev = 0;
+        bool run = has_cell, overflow = false, capped = false;
+        for (;;) {
+            // the sum tree of the row, rebuilt from the leaves (full wave)
+            const double p0 = dpp_f64<kDppPairSwap>(leaf);
+            const double s1 = leaf + p0;
+            const double p1 = dpp_f64<kDppQuadSwap>(s1);
+            const double s2 = s1 + p1;
+            const double p2 = dpp_f64<kDppHalfMirror>(s2);
+            const double s3 = s2 + p2;
+            const double p3 = dpp_f64<kDppRowMirror>(s3);
+            const double a0 = s3 + p3;
+            if (run) {
+                if (a0 == 0.0) {
+                    run = false;
+                } else if (ev >= c.cap) {
+                    run = false;
+                    capped = true;
+                }
+            }
+            if (!__any(run)) break;
+            // draws j0 .. j0+15 of the row, one per lane (j is equal in all running rows)
+            if (run && (j & 15u) == 0u) {
+                const tdev::Words4 wds =
+                    tdev::philox4x32_10(j + (uint32_t)lv, c.step, cell, c.tagword, c.key0, c.key1);
+                double u1, u2;
+                tdev::two_uniforms(wds, u1, u2);
+                rng_e[lane] = -tdev::plog(u1);
+                rng_u[lane] = u2;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const double e1 = rng_e[(row << 4) | (int)(j & 15u)];
+            const double u2 = rng_u[(row << 4) | (int)(j & 15u)];
+            bool event = false;
+            if (run) {
+                ++j;
+                const double tn = t + e1 / a0;
+                if (tn >= dt) {
+                    run = false;
+                } else {
+                    t = tn;
+                    event = true;
+                }
+            }
+            // which lane's leaf the descent reaches
+            double rr = u2 * a0;
+            bool on = true;
+            descent_level(s3, p3, (lv >> 3) & 1, rr, on);
+            descent_level(s2, p2, (lv >> 2) & 1, rr, on);
+            descent_level(s1, p1, (lv >> 1) & 1, rr, on);
+            descent_level(leaf, p0, lv & 1, rr, on);
+            on = on && event;
+
+            bool changed = false;
+            uint32_t word = 0;
+            if (on) {
+                double resid, a1;
+                int spec;
+                const int sel = voxel_select(net, xd, degd, rr, resid, a1, spec);
+                if (sel < RM) {
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) {
+                        xd[q] += (double)reaction_delta(net, sel, q);
+                        overflow |= (xd[q] < 0.0) | (xd[q] >= (double)kCountLimit);
+                    }
+                } else {
+                    const int dst = neighbour_at(g, lv, jump_direction(resid, a1, deg));
+#pragma unroll
+                    for (int q = 0; q < SM; ++q)
+                        if (q == spec) xd[q] -= 1.0;
+                    word = 1u | ((uint32_t)spec << 4) | ((uint32_t)dst << 8);
+                }
+                row_event[row] = word;
+                changed = true;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (event) {
+                const uint32_t w = row_event[row];
+                if ((w & 1u) && (int)(w >> 8) == lv) {
+                    const int spec = (int)((w >> 4) & 15u);
+#pragma unroll
+                    for (int q = 0; q < SM; ++q)
+                        if (q == spec) {
+                            xd[q] += 1.0;
+                            overflow |= xd[q] >= (double)kCountLimit;
+                        }
+                    changed = true;
+                }
+                ++ev;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (changed) leaf = voxel_fold(net, xd, degd);
+        }
+        if (vox) {
+#pragma unroll
+            for (int q = 0; q < SM; ++q)
+                if (q < S) c.counts[vbase + q] = (int32_t)xd[q];
+        }
+        if (has_cell && lv == 0 && c.T->tr_chi_ev) {
+            const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
+            const size_t slot = (size_t)(c.step % ts) * nc + cell;
+            c.T->tr_chi_ev[slot] = ev;
+            c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
+        }
+        item_stats(c, lv == 0 ? ev : 0u, lv == 0 ? j : 0u, overflow, capped, 0);
+    }
+    leave_queue(queue, persistent != 0);
+}
+
+}  // namespace tissue_impl

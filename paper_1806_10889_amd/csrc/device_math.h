@@ -14,8 +14,18 @@
 // binary64 operation in a fixed order; fma only where written.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else
+// runtime compilation: the fixed-width integer types live in __hip_internal
+using __hip_internal::int8_t;
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint8_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#endif
 
 namespace tdev {
 

@@ -22,6 +22,7 @@
 
 #include "../../include/tissue.h"
 #include "internal.h"
+#include "jit.h"
 #include "kernels.h"
 
 using namespace tissue_impl;
@@ -133,12 +134,27 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0 && x <= kMaxR
 // plan: everything tissue_create derives from the descriptor on the host
 // ---------------------------------------------------------------------------
 
+// cells of one leaf-count class P: cell_list[first, first + count)
 struct ChiGroupHost {
     int P;
-    int cells_per_item;
-    int max_species;
-    std::vector<ChiItem> items;
+    uint32_t first, count;
 };
+
+// cells per lane-mode item: as many as fit the LDS budget (a power of two <= 64)
+int lane_cells_per_item(int P, int S)
+{
+    const size_t per_cell = chi_lds_bytes(kChiLane, P, S, 1);
+    int cpi = 64;
+    while (cpi > 1 && (size_t)cpi * per_cell > kChiLdsBudget) cpi >>= 1;
+    return cpi;
+}
+
+// items of a class: up to cpi cells each, tagged with the tissue index
+void cut_items(uint32_t tissue, uint32_t first, uint32_t count, int cpi, std::vector<ChiItem> &out)
+{
+    for (uint32_t o = 0; o < count; o += (uint32_t)cpi)
+        out.push_back(ChiItem{tissue, first + o, std::min<uint32_t>((uint32_t)cpi, count - o), 0});
+}
 
 struct Plan {
     uint32_t lattice = 0, nx = 0, ny = 0, ncell = 0, S = 0, nvox = 0, nedge = 0;
@@ -152,6 +168,8 @@ struct Plan {
     std::vector<ChiGroupHost> chi;
     std::vector<std::vector<SItem>> s_passes;
     DevModel model{};
+    std::string net_key;                // structure of the network (cache key)
+    const JitKernels *jit = nullptr;    // compiled-network chi kernels, if any
     uint32_t trace_steps = 0;
     // byte offsets inside dev_buf
     size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
@@ -201,7 +219,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         M.reac_a[r] = (int8_t)ra;
         M.reac_b[r] = (int8_t)rb;
         M.rates[r] = d->rates[r];
-        uint32_t code = 0;
+        uint32_t lo = 0, hi = 0;
         int nchg = 0;
         for (int s = 0; s < S; ++s) {
             const int delta = d->stoich[r * S + s];
@@ -210,12 +228,20 @@ int build_plan(const tissue_desc_t *d, Plan &p)
             const int supplied = (a == s) + (b == s);
             if (delta < -supplied)
                 return fail(TISSUE_EINVAL, "a reaction consumes a species it does not have as reactant");
-            if (nchg == 4) return fail(TISSUE_EINVAL, "a reaction may change at most 4 species");
-            code |= (uint32_t)((s << 5) | (delta + 16)) << (8 * nchg);
-            ++nchg;
+            if (++nchg > 4) return fail(TISSUE_EINVAL, "a reaction may change at most 4 species");
+            const uint32_t byte = (uint32_t)(uint8_t)(int8_t)delta;
+            if (s < 4) lo |= byte << (8 * s);
+            else hi |= byte << (8 * (s - 4));
         }
-        for (; nchg < 4; ++nchg) code |= 16u << (8 * nchg);
-        M.change_code[r] = code;
+        M.delta_lo[r] = lo;
+        M.delta_hi[r] = hi;
+    }
+    for (int r = R; r < kMaxReactions; ++r) {  // padding: no reactants, rate 0, no change
+        M.reac_a[r] = -1;
+        M.reac_b[r] = -1;
+        M.rates[r] = 0.0;
+        M.delta_lo[r] = 0;
+        M.delta_hi[r] = 0;
     }
     M.n_diff = 0;
     for (int s = 0; s < S; ++s) {
@@ -225,6 +251,10 @@ int build_plan(const tissue_desc_t *d, Plan &p)
             M.diff_rate[M.n_diff] = d->diffusion[s];
             ++M.n_diff;
         }
+    }
+    for (int q = M.n_diff; q < kMaxSpecies; ++q) {  // padding: rate 0
+        M.diff_species[q] = 0;
+        M.diff_rate[q] = 0.0;
     }
     p.has_s = d->trans_n >= 0;
     if (p.has_s) {
@@ -240,6 +270,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         M.trans_n = M.trans_d = M.trans_i = -1;
         M.trans_rate = 0.0;
     }
+
+    p.net_key = network_key(M);
 
     // cells and voxels
     p.wh.resize(2 * (size_t)p.ncell);
@@ -261,24 +293,20 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         if (d->init_counts[i] < 0 || d->init_counts[i] >= TISSUE_COUNT_LIMIT)
             return fail(TISSUE_EINVAL, "init_counts must be in [0, 2^26)");
 
-    // chi items: cells grouped by leaf count P, cut into items
+    // chi: cells grouped by leaf count P (largest cells first); work items
+    // are cut per launch mode when a launch plan is made
     std::map<int, std::vector<int32_t>> by_p;
     for (uint32_t c = 0; c < p.ncell; ++c) by_p[pow2_at_least(p.wh[2 * c] * p.wh[2 * c + 1])].push_back((int32_t)c);
-    for (auto it = by_p.rbegin(); it != by_p.rend(); ++it) {  // largest cells first
+    for (auto it = by_p.rbegin(); it != by_p.rend(); ++it) {
         ChiGroupHost g;
         g.P = it->first;
-        g.max_species = S;
-        const size_t per_cell = chi_lds_bytes(g.P, S, 1);
-        int cpi = 64;
-        while (cpi > 1 && (size_t)cpi * per_cell > kChiLdsBudget) cpi >>= 1;
-        g.cells_per_item = cpi;
-        const uint32_t first = (uint32_t)p.cell_list.size();
+        g.first = (uint32_t)p.cell_list.size();
+        g.count = (uint32_t)it->second.size();
         p.cell_list.insert(p.cell_list.end(), it->second.begin(), it->second.end());
-        const uint32_t n = (uint32_t)it->second.size();
-        for (uint32_t o = 0; o < n; o += cpi)
-            g.items.push_back(ChiItem{0, first + o, std::min<uint32_t>(cpi, n - o), 0});
-        p.n_chi_items += g.items.size();
-        p.chi.push_back(std::move(g));
+        p.chi.push_back(g);
+        // room for both cuts of the class
+        p.n_chi_items += (g.count + lane_cells_per_item(g.P, S) - 1) / lane_cells_per_item(g.P, S);
+        p.n_chi_items += (g.count + 3) / 4;
     }
 
     // edges, face groups, S passes
@@ -369,11 +397,86 @@ int build_plan(const tissue_desc_t *d, Plan &p)
 // ---------------------------------------------------------------------------
 
 struct ChiLaunch {
+    int mode;                // kChiLane or kChiRow
+    const JitKernels *jit;   // compiled-network kernels, or null: generic ones
+    int SM, RM, NDM;         // generic kernel instantiation (table sizes)
     int P, cells_per_item;
     size_t lds;
     const ChiItem *items;
     uint32_t n_items;
 };
+
+// chi mode request: lane, row, or automatic (row mode for classes of at
+// most 16 voxels when one lane per cell would not give every SIMD a wave)
+enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2 };
+
+// Work items and launches of the chi operator over a set of tissues: one
+// launch per (leaf class, kernel instantiation).  Items are written to
+// items_out in launch order; ChiLaunch.items holds offsets until rebased.
+void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd,
+              std::vector<ChiItem> &items_out, std::vector<ChiLaunch> &launches)
+{
+    struct Key {
+        int P;
+        std::string net;  // compiled network key, or the generic table sizes
+        bool operator<(const Key &o) const
+        {
+            if (P != o.P) return P > o.P;  // largest cells first
+            return net < o.net;
+        }
+    };
+    struct Group {
+        const JitKernels *jit = nullptr;
+        int SM = 0, RM = 0, NDM = 0, max_s = 0;
+        std::vector<std::pair<uint32_t, const ChiGroupHost *>> cells;
+    };
+    std::map<Key, Group> groups;
+    for (size_t i = 0; i < members.size(); ++i) {
+        const Plan &p = *members[i];
+        int SM, RM, NDM;
+        chi_variant((int)p.S, p.model.n_reactions, p.model.n_diff, SM, RM, NDM);
+        const std::string net = p.jit ? "J" + p.net_key
+                                      : "G" + std::to_string(SM) + "," + std::to_string(RM) + "," +
+                                            std::to_string(NDM);
+        for (const ChiGroupHost &g : p.chi) {
+            Group &G = groups[Key{g.P, net}];
+            G.jit = p.jit;
+            G.SM = SM;
+            G.RM = RM;
+            G.NDM = NDM;
+            G.max_s = std::max(G.max_s, (int)p.S);
+            G.cells.push_back({(uint32_t)i, &g});
+        }
+    }
+    items_out.clear();
+    launches.clear();
+    for (auto &kv : groups) {
+        const Key &k = kv.first;
+        const Group &G = kv.second;
+        uint64_t cells = 0;
+        for (auto &m : G.cells) cells += m.second->count;
+        int mode = kChiLane;
+        if (k.P <= 16) {
+            if (mode_req == kModeRow) mode = kChiRow;
+            if (mode_req == kModeAuto && cells < (uint64_t)kWave * (uint64_t)std::max(n_simd, 1))
+                mode = kChiRow;
+        }
+        ChiLaunch L;
+        L.mode = mode;
+        L.jit = G.jit;
+        L.SM = G.SM;
+        L.RM = G.RM;
+        L.NDM = G.NDM;
+        L.P = k.P;
+        L.cells_per_item = mode == kChiRow ? 4 : lane_cells_per_item(k.P, G.max_s);
+        L.lds = chi_lds_bytes(mode, k.P, G.max_s, L.cells_per_item);
+        const size_t off = items_out.size();
+        for (auto &m : G.cells) cut_items(m.first, m.second->first, m.second->count, L.cells_per_item, items_out);
+        L.items = reinterpret_cast<const ChiItem *>(off);
+        L.n_items = (uint32_t)(items_out.size() - off);
+        launches.push_back(L);
+    }
+}
 
 struct SLaunch {
     const SItem *items;
@@ -392,6 +495,10 @@ struct GraphKey {
 struct LaunchPlan {
     DevTissue **tbl = nullptr;  // device table of DevTissue pointers
     uint32_t n_tissues = 0;
+    std::vector<const Plan *> members;
+    ChiItem *chi_items = nullptr;  // device region for chi work items
+    size_t chi_items_cap = 0;
+    int chi_mode = kModeAuto;
     std::vector<ChiLaunch> chi;
     std::vector<SLaunch> s;
     uint32_t *queue = nullptr;  // device: [0] next item, [1] workgroups done
@@ -412,6 +519,28 @@ struct LaunchPlan {
             (void)hipGraphDestroy(kv.second.first);
         }
         graphs.clear();
+    }
+
+    hipError_t launch_chi_any(const ChiLaunch &L, uint32_t grid, hipStream_t st, double dt,
+                              uint32_t kstep)
+    {
+        if (!L.jit)
+            return launch_chi(L.mode, L.SM, L.RM, L.NDM, L.P, grid, L.lds, st, tbl, L.items,
+                              L.n_items, queue, persistent, L.cells_per_item, dt, kstep);
+        const DevTissue *const *tb = tbl;
+        const ChiItem *it = L.items;
+        uint32_t ni = L.n_items;
+        uint32_t *qu = queue;
+        int pe = persistent, cpi = L.cells_per_item;
+        int log2p = 0;
+        while ((1 << log2p) < L.P) ++log2p;
+        if (L.mode == kChiRow) {
+            void *args[] = {&tb, &it, &ni, &qu, &pe, &dt, &kstep};
+            return hipModuleLaunchKernel(L.jit->row, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
+        }
+        void *args[] = {&tb, &it, &ni, &qu, &pe, &cpi, &log2p, &dt, &kstep};
+        return hipModuleLaunchKernel(L.jit->lane, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st, args,
+                                     nullptr);
     }
 
     uint32_t chi_grid(const ChiLaunch &L) const
@@ -439,8 +568,7 @@ struct LaunchPlan {
             for (const ChiLaunch &L : chi) {
                 if (L.n_items == 0) continue;
                 if (ev) HIP_TRY(hipEventRecord((*ev)[e++], st));
-                HIP_TRY(launch_chi(L.P, chi_grid(L), L.lds, st, tbl, L.items, L.n_items, queue,
-                                   persistent, L.cells_per_item, dt, (uint32_t)k));
+                HIP_TRY(launch_chi_any(L, chi_grid(L), st, dt, (uint32_t)k));
                 if (ev) {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
                     kind->push_back(0);
@@ -458,6 +586,23 @@ struct LaunchPlan {
             }
         }
         HIP_TRY(launch_advance(st, tbl, n_tissues, (uint32_t)n));
+        return TISSUE_OK;
+    }
+
+    // (Re)plan the chi launches for a mode request and upload their items.
+    int set_chi_mode(int mode)
+    {
+        std::vector<ChiItem> items;
+        std::vector<ChiLaunch> launches;
+        plan_chi(members, mode, cus * 4, items, launches);
+        if (items.size() > chi_items_cap) return fail(TISSUE_EINVAL, "chi item region too small");
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (!items.empty())
+            HIP_TRY(hipMemcpy(chi_items, items.data(), items.size() * sizeof(ChiItem), hipMemcpyHostToDevice));
+        for (ChiLaunch &L : launches) L.items = chi_items + reinterpret_cast<uintptr_t>(L.items);
+        chi = std::move(launches);
+        chi_mode = mode;
+        clear_graphs();
         return TISSUE_OK;
     }
 
@@ -548,12 +693,6 @@ int device_cus()
     return cus;
 }
 
-int prepare_lds(const std::vector<ChiLaunch> &chi)
-{
-    for (const ChiLaunch &L : chi) HIP_TRY(set_chi_lds_limit(L.P, L.lds));
-    return TISSUE_OK;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -606,6 +745,16 @@ int tissue_device_cus(int32_t *out)
     return TISSUE_OK;
 }
 
+int tissue_network_check(const tissue_desc_t *d)
+{
+    Plan p;
+    const int rc = build_plan(d, p);
+    if (rc != TISSUE_OK) return rc;
+    std::string err;
+    if (jit_compile_check(p.model, err) != 0) return fail(TISSUE_EDEVICE, err);
+    return TISSUE_OK;
+}
+
 size_t tissue_required_bytes(const tissue_desc_t *d)
 {
     Plan p;
@@ -631,6 +780,11 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     t->stream = static_cast<hipStream_t>(hip_stream);
     const int cus = device_cus();
     if (cus <= 0) return fail(TISSUE_EDEVICE, "no HIP device");
+    if (!(d->flags & TISSUE_FLAG_NO_JIT)) {
+        // the network's own chi kernels; the generic ones serve if that fails
+        std::string err;
+        if (jit_kernels(p.model, &p.jit, err) != 0) p.jit = nullptr;
+    }
 
     unsigned char *base = t->dev;
     DevTissue &R = t->host_rec;
@@ -673,13 +827,8 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     if (p.nedge)
         HIP_TRY(hipMemcpyAsync(base + p.off_edges, p.edges.data(), p.edges.size() * sizeof(EdgeRec),
                                hipMemcpyHostToDevice, st));
-    std::vector<ChiItem> chi_all;
-    for (auto &g : p.chi) chi_all.insert(chi_all.end(), g.items.begin(), g.items.end());
     std::vector<SItem> s_all;
     for (auto &ps : p.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
-    if (!chi_all.empty())
-        HIP_TRY(hipMemcpyAsync(base + p.off_chi, chi_all.data(), chi_all.size() * sizeof(ChiItem),
-                               hipMemcpyHostToDevice, st));
     if (!s_all.empty())
         HIP_TRY(hipMemcpyAsync(base + p.off_s, s_all.data(), s_all.size() * sizeof(SItem),
                                hipMemcpyHostToDevice, st));
@@ -696,23 +845,15 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     L.queue = reinterpret_cast<uint32_t *>(base + p.off_ctl + 32);
     L.stream = st;
     L.cus = cus;
+    L.members = {&t->plan};
+    L.chi_items = reinterpret_cast<ChiItem *>(base + p.off_chi);
+    L.chi_items_cap = p.n_chi_items;
     size_t off = 0;
-    for (auto &g : p.chi) {
-        ChiLaunch cl;
-        cl.P = g.P;
-        cl.cells_per_item = g.cells_per_item;
-        cl.lds = chi_lds_bytes(g.P, (int)p.S, g.cells_per_item);
-        cl.items = reinterpret_cast<const ChiItem *>(base + p.off_chi) + off;
-        cl.n_items = (uint32_t)g.items.size();
-        off += g.items.size();
-        L.chi.push_back(cl);
-    }
-    off = 0;
     for (auto &ps : p.s_passes) {
         L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(base + p.off_s) + off, (uint32_t)ps.size()});
         off += ps.size();
     }
-    rc = prepare_lds(L.chi);
+    rc = L.set_chi_mode(kModeAuto);
     if (rc != TISSUE_OK) return rc;
     *out = t.release();
     return TISSUE_OK;
@@ -781,6 +922,7 @@ int tissue_read_stats(tissue_t *t, tissue_stats_t *out)
     out->n_cells = t->plan.ncell;
     out->n_edges = t->plan.nedge;
     out->n_voxels = t->plan.nvox;
+    out->jit = t->plan.jit != nullptr;
     return TISSUE_OK;
 }
 
@@ -855,6 +997,12 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
     return TISSUE_OK;
 }
 
+int tissue_set_chi_mode(tissue_t *t, int32_t mode)
+{
+    if (!t || mode < kModeLane || mode > kModeAuto) return fail(TISSUE_EINVAL, "chi mode must be 0, 1 or 2");
+    return t->lp.set_chi_mode(mode);
+}
+
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph)
 {
     if (!t || steps_per_graph < 0 || steps_per_graph > 100000) return fail(TISSUE_EINVAL, "bad graph chunk");
@@ -880,7 +1028,7 @@ namespace {
 
 struct BatchLayout {
     size_t off_tbl = 0, off_queue = 0, off_chi = 0, off_s = 0, bytes = 0;
-    std::vector<ChiGroupHost> chi;            // merged per P
+    size_t chi_cap = 0;
     std::vector<std::vector<SItem>> s_passes;
 };
 
@@ -889,32 +1037,8 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
     if (!ts || n < 1) return fail(TISSUE_EINVAL, "batch needs >= 1 tissue");
     for (int32_t i = 0; i < n; ++i)
         if (!ts[i]) return fail(TISSUE_EINVAL, "null tissue in batch");
-    // chi: per leaf-count class, one launch over all members' items
-    std::map<int, ChiGroupHost> groups;
-    for (int32_t i = 0; i < n; ++i)
-        for (const ChiGroupHost &g : ts[i]->plan.chi) {
-            ChiGroupHost &G = groups[g.P];
-            G.P = g.P;
-            G.max_species = std::max<int>(G.max_species, (int)ts[i]->plan.S);
-        }
-    for (auto &kv : groups) {
-        ChiGroupHost &G = kv.second;
-        const size_t per_cell = chi_lds_bytes(G.P, G.max_species, 1);
-        int cpi = 64;
-        while (cpi > 1 && (size_t)cpi * per_cell > kChiLdsBudget) cpi >>= 1;
-        G.cells_per_item = cpi;
-        for (int32_t i = 0; i < n; ++i)
-            for (const ChiGroupHost &g : ts[i]->plan.chi) {
-                if (g.P != G.P) continue;
-                // this member's cells of the class: re-cut with the batch's items size
-                const uint32_t first = g.items.front().first;
-                uint32_t count = 0;
-                for (const ChiItem &it : g.items) count += it.count;
-                for (uint32_t o = 0; o < count; o += cpi)
-                    G.items.push_back(ChiItem{(uint32_t)i, first + o, std::min<uint32_t>(cpi, count - o), 0});
-            }
-    }
-    for (auto it = groups.rbegin(); it != groups.rend(); ++it) B.chi.push_back(std::move(it->second));
+    // chi items: room for both cuts of every member's classes
+    for (int32_t i = 0; i < n; ++i) B.chi_cap += ts[i]->plan.n_chi_items;
     // S: pass 0 holds all edges of members with disjoint faces and class 0
     // of the others; pass c > 0 holds class c of the others
     int max_pass = 0;
@@ -938,8 +1062,7 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
                 cut(p.class_start[c], p.class_start[c + 1], B.s_passes[c]);
         }
     }
-    size_t n_chi = 0, n_s = 0;
-    for (auto &g : B.chi) n_chi += g.items.size();
+    size_t n_s = 0;
     for (auto &ps : B.s_passes) n_s += ps.size();
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -949,7 +1072,7 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
     };
     B.off_tbl = take((size_t)n * sizeof(DevTissue *));
     B.off_queue = take(64);
-    B.off_chi = take(n_chi * sizeof(ChiItem));
+    B.off_chi = take(B.chi_cap * sizeof(ChiItem));
     B.off_s = take(n_s * sizeof(SItem));
     B.bytes = o;
     return TISSUE_OK;
@@ -984,14 +1107,10 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     for (int32_t i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(ts[i]->stream));
     std::vector<DevTissue *> tbl(n);
     for (int32_t i = 0; i < n; ++i) tbl[i] = ts[i]->d_rec();
-    std::vector<ChiItem> chi_all;
-    for (auto &g : B.chi) chi_all.insert(chi_all.end(), g.items.begin(), g.items.end());
     std::vector<SItem> s_all;
     for (auto &ps : B.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
     HIP_TRY(hipMemcpyAsync(b->dev + B.off_tbl, tbl.data(), tbl.size() * sizeof(DevTissue *), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(b->dev + B.off_queue, 0, 64, st));
-    if (!chi_all.empty())
-        HIP_TRY(hipMemcpyAsync(b->dev + B.off_chi, chi_all.data(), chi_all.size() * sizeof(ChiItem), hipMemcpyHostToDevice, st));
     if (!s_all.empty())
         HIP_TRY(hipMemcpyAsync(b->dev + B.off_s, s_all.data(), s_all.size() * sizeof(SItem), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1001,23 +1120,15 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     L.queue = reinterpret_cast<uint32_t *>(b->dev + B.off_queue);
     L.stream = st;
     L.cus = cus;
+    for (int32_t i = 0; i < n; ++i) L.members.push_back(&ts[i]->plan);
+    L.chi_items = reinterpret_cast<ChiItem *>(b->dev + B.off_chi);
+    L.chi_items_cap = B.chi_cap;
     size_t off = 0;
-    for (auto &g : B.chi) {
-        ChiLaunch cl;
-        cl.P = g.P;
-        cl.cells_per_item = g.cells_per_item;
-        cl.lds = chi_lds_bytes(g.P, g.max_species, g.cells_per_item);
-        cl.items = reinterpret_cast<const ChiItem *>(b->dev + B.off_chi) + off;
-        cl.n_items = (uint32_t)g.items.size();
-        off += g.items.size();
-        L.chi.push_back(cl);
-    }
-    off = 0;
     for (auto &ps : B.s_passes) {
         L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(b->dev + B.off_s) + off, (uint32_t)ps.size()});
         off += ps.size();
     }
-    rc = prepare_lds(L.chi);
+    rc = L.set_chi_mode(kModeAuto);
     if (rc != TISSUE_OK) return rc;
     *out = b.release();
     return TISSUE_OK;
@@ -1062,6 +1173,12 @@ int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workg
     b->lp.wpc = workgroups_per_cu;
     b->lp.clear_graphs();
     return TISSUE_OK;
+}
+
+int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode)
+{
+    if (!b || mode < kModeLane || mode > kModeAuto) return fail(TISSUE_EINVAL, "chi mode must be 0, 1 or 2");
+    return b->lp.set_chi_mode(mode);
 }
 
 int tissue_batch_sync(tissue_batch_t *b)

@@ -8,7 +8,9 @@
 // per cell or edge.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#endif
 
 namespace tissue_impl {
 
@@ -18,9 +20,11 @@ constexpr int kMaxFace = 8;       // voxels in one face group (8x8 square mesh: 
 constexpr int kWave = 64;
 constexpr int32_t kCountLimit = 1 << 26;
 
-// Mass-action network of one tissue.  A reaction's net change is packed in
-// change_code[r]: up to four bytes, byte = species << 5 | (delta + 16),
-// byte value 16 (species 0, delta 0) = no change.
+// Mass-action network of one tissue, zero-padded to the table sizes: a
+// padding reaction has no reactants and rate 0, a padding diffusion channel
+// rate 0, so it adds exactly 0.0 to every fold and is never selected.  A
+// reaction's net change is packed in delta_lo/delta_hi: one signed byte per
+// species (species 0..3 in delta_lo, 4..7 in delta_hi).
 struct DevModel {
     int32_t n_species;
     int32_t n_reactions;
@@ -29,7 +33,8 @@ struct DevModel {
     int8_t reac_a[kMaxReactions];        // first reactant or -1
     int8_t reac_b[kMaxReactions];        // second reactant or -1
     int8_t diff_species[kMaxSpecies];    // species of diffusion channel q
-    uint32_t change_code[kMaxReactions];
+    uint32_t delta_lo[kMaxReactions];
+    uint32_t delta_hi[kMaxReactions];
     double rates[kMaxReactions];
     double diff_rate[kMaxSpecies];       // D of diffusion channel q
     double trans_rate;
@@ -75,6 +80,10 @@ struct ChiItem {
     uint32_t count;
     uint32_t pad;
 };
+
+// chi kernel variants: one lane per cell (any P), or one 16-lane row per cell
+// (P <= 16, four cells per wavefront)
+enum ChiMode { kChiLane = 0, kChiRow = 1 };
 
 // up to 64 consecutive edges [first, first + count) of one tissue
 struct SItem {

@@ -7,13 +7,17 @@
 
 namespace tissue_impl {
 
-// LDS bytes of one chi workgroup: per cell 2P FP64 tree nodes + P*S counts.
-size_t chi_lds_bytes(int P, int S, int cells_per_item);
-hipError_t set_chi_lds_limit(int P, size_t lds);
-hipError_t launch_chi(int P, uint32_t grid, size_t lds, hipStream_t stream,
-                      const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items,
-                      uint32_t *queue, int persistent, int cells_per_item, double dt,
-                      uint32_t kstep);
+// Dynamic LDS bytes of one chi workgroup (lane mode: per cell 2P FP64 tree
+// nodes and P*S counts; row mode: none).
+size_t chi_lds_bytes(int mode, int P, int S, int cells_per_item);
+// Table sizes (species slots, reaction slots, diffusion slots) the kernels
+// are instantiated for, for a network of S species, R reactions and ND
+// diffusing species.
+void chi_variant(int S, int R, int ND, int &SM, int &RM, int &NDM);
+hipError_t launch_chi(int mode, int SM, int RM, int NDM, int P, uint32_t grid, size_t lds,
+                      hipStream_t stream, const DevTissue *const *tbl, const ChiItem *items,
+                      uint32_t n_items, uint32_t *queue, int persistent, int cells_per_item,
+                      double dt, uint32_t kstep);
 hipError_t launch_s(uint32_t grid, hipStream_t stream, const DevTissue *const *tbl,
                     const SItem *items, uint32_t n_items, uint32_t *queue, int persistent,
                     double dt, uint32_t kstep);

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtissue.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ESTATE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 FLAG_TRACE = 1
+FLAG_NO_JIT = 2
 ABI_VERSION = 1
 
 
@@ -51,7 +52,8 @@ class Desc(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("chi_events", C.c_uint64), ("s_events", C.c_uint64), ("draws", C.c_uint64),
                 ("steps_done", C.c_uint32), ("overflow", C.c_uint32), ("capped", C.c_uint32),
-                ("n_cells", C.c_uint32), ("n_edges", C.c_uint32), ("n_voxels", C.c_uint32)]
+                ("n_cells", C.c_uint32), ("n_edges", C.c_uint32), ("n_voxels", C.c_uint32),
+                ("jit", C.c_uint32)]
 
 
 class Timing(C.Structure):
@@ -62,7 +64,8 @@ class Timing(C.Structure):
 EXPORTS = [
     "tissue_required_bytes", "tissue_create", "tissue_step", "tissue_read_counts",
     "tissue_read_stats", "tissue_read_trace", "tissue_restart", "tissue_write_counts",
-    "tissue_set_launch", "tissue_set_graph_chunk", "tissue_step_timed", "tissue_destroy",
+    "tissue_set_launch", "tissue_set_chi_mode", "tissue_set_graph_chunk", "tissue_step_timed",
+    "tissue_destroy", "tissue_batch_set_chi_mode", "tissue_network_check",
     "tissue_batch_required_bytes", "tissue_batch_create", "tissue_batch_step",
     "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
     "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
@@ -78,6 +81,7 @@ def _load():
     pD = C.POINTER(Desc)
     sig = {
         "tissue_required_bytes": (sz, [pD]),
+        "tissue_network_check": (C.c_int, [pD]),
         "tissue_create": (C.c_int, [pD, vp, sz, vp, C.POINTER(vp)]),
         "tissue_step": (C.c_int, [vp, dbl, i32]),
         "tissue_read_counts": (C.c_int, [vp, C.POINTER(C.c_int32), sz]),
@@ -88,6 +92,8 @@ def _load():
         "tissue_write_counts": (C.c_int, [vp, C.POINTER(C.c_int32), sz]),
         "tissue_set_launch": (C.c_int, [vp, i32, i32]),
         "tissue_set_graph_chunk": (C.c_int, [vp, i32]),
+        "tissue_set_chi_mode": (C.c_int, [vp, i32]),
+        "tissue_batch_set_chi_mode": (C.c_int, [vp, i32]),
         "tissue_step_timed": (C.c_int, [vp, dbl, i32, C.POINTER(Timing)]),
         "tissue_destroy": (C.c_int, [vp]),
         "tissue_batch_required_bytes": (sz, [C.POINTER(vp), i32]),
@@ -131,7 +137,7 @@ def _stream_handle(stream):
 class _DescHolder:
     """A filled Desc plus the numpy arrays its pointers refer to."""
 
-    def __init__(self, problem: dict, trace_steps: int = 0):
+    def __init__(self, problem: dict, trace_steps: int = 0, jit: bool = True):
         p = problem
         self.mesh_w = np.ascontiguousarray(p["mesh_w"], dtype=np.uint8)
         self.mesh_h = np.ascontiguousarray(p["mesh_h"], dtype=np.uint8)
@@ -155,7 +161,7 @@ class _DescHolder:
         d.sim_id = int(p["sim_id"])
         d.start_step = int(p.get("start_step", 0))
         d.event_cap = int(p.get("event_cap", 0))
-        d.flags = FLAG_TRACE if trace_steps > 0 else 0
+        d.flags = (FLAG_TRACE if trace_steps > 0 else 0) | (0 if jit else FLAG_NO_JIT)
         d.trace_steps = int(trace_steps)
         self.desc = d
 
@@ -163,6 +169,12 @@ class _DescHolder:
 def required_bytes(problem: dict, trace_steps: int = 0) -> int:
     h = _DescHolder(problem, trace_steps)
     return int(lib.tissue_required_bytes(C.byref(h.desc)))
+
+
+def network_check(problem: dict) -> None:
+    """Compile the chi kernels for the problem's network (no device needed)."""
+    h = _DescHolder(problem)
+    _check(lib.tissue_network_check(C.byref(h.desc)), "tissue_network_check")
 
 
 def device_cus() -> int:
@@ -175,10 +187,10 @@ class Tissue:
     """One tissue resident in a torch-allocated device buffer."""
 
     def __init__(self, problem: dict, device="cuda:0", stream=None, trace_steps: int = 0,
-                 buffer=None):
+                 buffer=None, jit: bool = True):
         import torch
         self.problem = problem
-        self._h = _DescHolder(problem, trace_steps)
+        self._h = _DescHolder(problem, trace_steps, jit)
         need = int(lib.tissue_required_bytes(C.byref(self._h.desc)))
         if need == 0:  # invalid descriptor: tissue_create reports why, before any device work
             _check(lib.tissue_create(C.byref(self._h.desc), None, 0, None, C.byref(C.c_void_p())),
@@ -241,6 +253,10 @@ class Tissue:
         _check(lib.tissue_set_launch(self.handle, int(bool(persistent)), int(workgroups_per_cu)),
                "tissue_set_launch")
 
+    def set_chi_mode(self, mode: int):
+        """0 = one lane per cell, 1 = one 16-lane row per cell (<= 16 voxels), 2 = auto."""
+        _check(lib.tissue_set_chi_mode(self.handle, int(mode)), "tissue_set_chi_mode")
+
     def set_graph_chunk(self, steps: int):
         _check(lib.tissue_set_graph_chunk(self.handle, int(steps)), "tissue_set_graph_chunk")
 
@@ -290,6 +306,9 @@ class Batch:
     def set_launch(self, persistent: bool, workgroups_per_cu: int = 0):
         _check(lib.tissue_batch_set_launch(self.handle, int(bool(persistent)), int(workgroups_per_cu)),
                "tissue_batch_set_launch")
+
+    def set_chi_mode(self, mode: int):
+        _check(lib.tissue_batch_set_chi_mode(self.handle, int(mode)), "tissue_batch_set_chi_mode")
 
     def sync(self):
         _check(lib.tissue_batch_sync(self.handle), "tissue_batch_sync")

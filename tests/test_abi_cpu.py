@@ -66,3 +66,12 @@ def test_error_strings():
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert T.lib.tissue_strerror(code)
     assert T.lib.tissue_strerror(-99) == b"unknown error"
+
+
+@pytest.mark.parametrize("model", ["nd5", "nd4", "bd", "dimer", "diff", "tr"])
+def test_network_kernels_compile(model):
+    """The chi kernels compiled per network (hipRTC, gfx950) build for every
+    test network; no device needed."""
+    from paper_1806_10889_amd import tissue as T
+    p = W.random_problem(1, lattice=0, nx=2, ny=2, model=model, mesh=(2, 2))
+    T.network_check(p)

@@ -19,54 +19,78 @@ def _oracle(oracle_lib, p, n, trace=True, **kw):
     return oracle_lib.run(p, p["dt"], n, trace=trace, **kw)
 
 
-def test_config1_full_horizon(oracle_lib):
+MODES = [0, 1]  # chi kernel: one lane per cell / one 16-lane row per cell
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config1_full_horizon(oracle_lib, mode):
     p = W.config1()
     o = _oracle(oracle_lib, p, p["n_steps"])
-    g = gpu_run(p, p["n_steps"], trace=True)
+    g = gpu_run(p, p["n_steps"], trace=True, chi_mode=mode)
     assert o.chi_events > 1000
     assert_same(g, o)
 
 
-def test_config2_reduced(oracle_lib):
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("mode", MODES)
+def test_config2_reduced(oracle_lib, mode, jit):
     p = W.config2(side=9, n_steps=12)  # 81 cells: two chi items, ragged S tail
     o = _oracle(oracle_lib, p, 12)
-    g = gpu_run(p, 12, trace=True)
+    g = gpu_run(p, 12, trace=True, chi_mode=mode, jit=jit)
     assert o.chi_events > 10000 and o.s_events > 1000
     assert_same(g, o)
 
 
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("lattice", [0, 1])
-def test_uneven_meshes_overlapping_faces(oracle_lib, lattice):
+def test_uneven_meshes_overlapping_faces(oracle_lib, lattice, mode, jit):
     p = W.random_problem(31 + lattice, lattice=lattice, nx=9, ny=7, model="nd5", uneven=True,
                          dt=0.05, n_steps=6)
     o = _oracle(oracle_lib, p, 6)
-    g = gpu_run(p, 6, trace=True)
+    g = gpu_run(p, 6, trace=True, chi_mode=mode, jit=jit)
     assert o.s_events > 0
     assert_same(g, o)
 
 
-@pytest.mark.parametrize("mesh", [(1, 1), (2, 2), (2, 1), (3, 5), (8, 8), (7, 3), (1, 8)])
-def test_mesh_shapes(oracle_lib, mesh):
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mesh", [(1, 1), (2, 2), (2, 1), (3, 5), (8, 8), (7, 3), (1, 8), (4, 4),
+                                  (2, 8)])
+def test_mesh_shapes(oracle_lib, mesh, mode):
     p = W.random_problem(40 + mesh[0] * 8 + mesh[1], lattice=1, nx=5, ny=4, model="nd5",
                          mesh=mesh, dt=0.05, n_steps=4)
     o = _oracle(oracle_lib, p, 4)
-    assert_same(gpu_run(p, 4, trace=True), o)
+    assert_same(gpu_run(p, 4, trace=True, chi_mode=mode), o)
 
 
-def test_nd4_well_mixed_square(oracle_lib):
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("model", ["nd5", "nd4", "bd", "dimer", "diff", "tr"])
+def test_networks(oracle_lib, model, mode, jit):
+    """Compiled-network and generic kernels on other table sizes: 4 species /
+    7 reactions, 1 species / 2 reactions, order-2 same-species, diffusion
+    only, signalling only."""
+    p = W.random_problem(51, lattice=0, nx=7, ny=6, model=model, mesh=(3, 3), dt=0.1,
+                         n_steps=5, rate_lo=-1.0, rate_hi=1.0)
+    o = _oracle(oracle_lib, p, 5)
+    assert_same(gpu_run(p, 5, trace=True, chi_mode=mode, jit=jit), o)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_nd4_well_mixed_square(oracle_lib, mode):
     p = W.random_problem(50, lattice=0, nx=13, ny=11, model="nd4", mesh=(1, 1), dt=0.1,
                          n_steps=20, rate_lo=-1.0, rate_hi=1.0)
     o = _oracle(oracle_lib, p, 20)
-    assert_same(gpu_run(p, 20, trace=True), o)
+    assert_same(gpu_run(p, 20, trace=True, chi_mode=mode), o)
 
 
-@pytest.mark.parametrize("persistent,wpc,chunk", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 3, 2),
-                                                  (0, 0, 3), (1, 8, 5)])
-def test_launch_shapes_do_not_change_bits(oracle_lib, persistent, wpc, chunk):
+@pytest.mark.parametrize("persistent,wpc,chunk,mode", [(0, 0, 0, 0), (1, 0, 0, 1), (1, 1, 0, 2),
+                                                       (1, 3, 2, 0), (0, 0, 3, 1), (1, 8, 5, 2)])
+def test_launch_shapes_do_not_change_bits(oracle_lib, persistent, wpc, chunk, mode):
     p = W.random_problem(60, lattice=1, nx=11, ny=10, model="nd5", uneven=True, dt=0.05,
                          n_steps=7)
     o = _oracle(oracle_lib, p, 7)
-    g = gpu_run(p, 7, trace=True, persistent=persistent, wpc=wpc, graph_chunk=chunk)
+    g = gpu_run(p, 7, trace=True, persistent=persistent, wpc=wpc, graph_chunk=chunk, chi_mode=mode)
     assert_same(g, o)
 
 
@@ -112,11 +136,14 @@ def test_batch_equals_plain_and_oracle(oracle_lib):
     ]
     probs[3]["start_step"] = 17
     n = 6
-    ts = [T.Tissue(p) for p in probs]
+    ts = [T.Tissue(p, jit=(i % 2 == 0)) for i, p in enumerate(probs)]  # mixed kernels in one batch
     b = T.Batch(ts)
     b.step(0.05, 2)
     b.set_launch(False)
-    b.step(0.05, 4)
+    b.set_chi_mode(1)
+    b.step(0.05, 3)
+    b.set_chi_mode(0)
+    b.step(0.05, 1)
     b.sync()
     for p, t in zip(probs, ts):
         o = oracle_lib.run(p, 0.05, n)
@@ -203,13 +230,14 @@ def test_config3_reduced_uneven(oracle_lib):
     assert_same(gpu_run(p, 3, trace=True), o)
 
 
-def test_full_size_config2_bench_launch(oracle_lib):
+@pytest.mark.parametrize("mode", [2, 0])
+def test_full_size_config2_bench_launch(oracle_lib, mode):
     """The 64x64 hex, 4x4-voxel workload at full size, persistent launches
-    replayed from a captured graph (as the benchmark runs it), two steps
-    against the oracle on every cell."""
+    replayed from a captured graph (as the benchmark runs it, automatic
+    kernel choice), two steps against the oracle on every cell."""
     p = W.config2()
     o = _oracle(oracle_lib, p, 2)
-    g = gpu_run(p, 2, trace=True, persistent=1, graph_chunk=1)
+    g = gpu_run(p, 2, trace=True, persistent=1, graph_chunk=1, chi_mode=mode)
     assert_same(g, o)
 
 
