@@ -167,9 +167,9 @@ def main():
     ap.add_argument("--roofline-steps", type=int, default=200)
     ap.add_argument("--plain-only", action="store_true")
     ap.add_argument("--batch-tissues", type=int, default=512)
-    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-reps", type=int, default=1)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")

@@ -481,6 +481,16 @@ constexpr int kDppQuadSwap = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;
 constexpr int kDppRowMirror = 0x140;
 
+// OR of a 32-bit value over the lane's 16-lane row (full wave required).
+__device__ __forceinline__ uint32_t row_or(uint32_t x)
+{
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppPairSwap, 0xF, 0xF, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppQuadSwap, 0xF, 0xF, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppHalfMirror, 0xF, 0xF, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowMirror, 0xF, 0xF, false);
+    return x;
+}
+
 // One descent level: children L (left) and R of the lane's ancestor, given
 // the lane's own subtree sum and its sibling's; bit = lane's side.
 __device__ __forceinline__ void descent_level(double own, double sib, int bit, double &r, bool &on)
@@ -494,12 +504,10 @@ __device__ __forceinline__ void descent_level(double own, double sib, int bit, d
 
 }  // namespace
 
-// LDS of the row kernel: per lane one pre-drawn (-plog(U1), U2) pair, per
-// row the broadcast word of a diffusion event (1 | spec << 4 | dst << 8).
+// LDS of the row kernel: per lane one pre-drawn (-plog(U1), U2) pair.
 struct RowShared {
     double rng_e[kWave];
     double rng_u[kWave];
-    uint32_t row_event[4];
 };
 
 template <class NET>
@@ -510,7 +518,6 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
     constexpr int SM = NET::SM, RM = NET::RM;
     double *rng_e = sh.rng_e;
     double *rng_u = sh.rng_u;
-    uint32_t *row_event = sh.row_event;
     const int lane = threadIdx.x, row = lane >> 4, lv = lane & 15;
     uint32_t cursor = blockIdx.x;
     for (;;) {
@@ -544,7 +551,26 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         double t = 0.0;
         uint32_t j = 0, ev = 0;
         bool run = has_cell, overflow = false, capped = false;
-        for (;;) {
+        // Every running row has drawn exactly once per iteration so far, so
+        // its draw ordinal j equals the wave-uniform iteration count.
+        for (uint32_t iter = 0;; ++iter) {
+            const uint32_t slot = iter & 15u;
+            if (slot == 0u) {
+                // draws iter .. iter+15 of the row, one per lane
+                if (run) {
+                    const tdev::Words4 wds = tdev::philox4x32_10(iter + (uint32_t)lv, c.step, cell,
+                                                                 c.tagword, c.key0, c.key1);
+                    double u1, uu;
+                    tdev::two_uniforms(wds, u1, uu);
+                    rng_e[lane] = -tdev::plog(u1);
+                    rng_u[lane] = uu;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            // this iteration's draw of the row (read early: its latency hides
+            // behind the tree rebuild)
+            const double e1 = rng_e[(row << 4) | (int)slot];
+            const double u2 = rng_u[(row << 4) | (int)slot];
             // the sum tree of the row, rebuilt from the leaves (full wave)
             const double p0 = dpp_f64<kDppPairSwap>(leaf);
             const double s1 = leaf + p0;
@@ -563,18 +589,6 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                 }
             }
             if (!__any(run)) break;
-            // draws j0 .. j0+15 of the row, one per lane (j is equal in all running rows)
-            if (run && (j & 15u) == 0u) {
-                const tdev::Words4 wds =
-                    tdev::philox4x32_10(j + (uint32_t)lv, c.step, cell, c.tagword, c.key0, c.key1);
-                double u1, u2;
-                tdev::two_uniforms(wds, u1, u2);
-                rng_e[lane] = -tdev::plog(u1);
-                rng_u[lane] = u2;
-            }
-            __builtin_amdgcn_wave_barrier();
-            const double e1 = rng_e[(row << 4) | (int)(j & 15u)];
-            const double u2 = rng_u[(row << 4) | (int)(j & 15u)];
             bool event = false;
             if (run) {
                 ++j;
@@ -614,14 +628,14 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                         if (q == spec) xd[q] -= 1.0;
                     word = 1u | ((uint32_t)spec << 4) | ((uint32_t)dst << 8);
                 }
-                row_event[row] = word;
                 changed = true;
             }
-            __builtin_amdgcn_wave_barrier();
+            // the row's diffusion word reaches every lane of the row (it is
+            // zero outside the selected lane): OR over the 16-lane row
+            word = row_or(word);
             if (event) {
-                const uint32_t w = row_event[row];
-                if ((w & 1u) && (int)(w >> 8) == lv) {
-                    const int spec = (int)((w >> 4) & 15u);
+                if ((word & 1u) && (int)(word >> 8) == lv) {
+                    const int spec = (int)((word >> 4) & 15u);
 #pragma unroll
                     for (int q = 0; q < SM; ++q)
                         if (q == spec) {
@@ -632,8 +646,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                 }
                 ++ev;
             }
-            __builtin_amdgcn_wave_barrier();
             if (changed) leaf = voxel_fold(net, xd, degd);
+            __builtin_amdgcn_wave_barrier();
         }
         if (vox) {
 #pragma unroll
