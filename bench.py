@@ -33,8 +33,8 @@ METRIC = "SSA events/sec on 1 MI355X (batched vs plain); p50/p99 sim latency"
 # Algorithmic VALU work per accepted event, in full-rate lane-operation
 # equivalents (a quarter-rate instruction counts 4), for the 5-species
 # network on 4x4-voxel cells; derivation in the design notes.
-OPS_PER_CHI_EVENT = 480
-OPS_PER_S_EVENT = 260
+OPS_PER_CHI_EVENT = 432
+OPS_PER_S_EVENT = 289
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
@@ -56,9 +56,15 @@ def run_plain(args, torch, T, W):
     p = W.config2(n_steps=args.n_steps)
     stream = torch.cuda.current_stream()
     t = T.Tissue(p, device="cuda:0", stream=stream)
-    t.set_launch(True, 0)
-    t.set_graph_chunk(args.graph_chunk)
     dt, n = p["dt"], p["n_steps"]
+    if args.no_tune:
+        t.set_launch(True, 0)
+        t.set_graph_chunk(args.graph_chunk)
+        tuned = None
+    else:
+        from paper_1806_10889_amd import autotune
+        tuned = autotune.tune([p], dt, steps=50, reps=2, target=t, log=log)
+        log(f"autotuned launch: {tuned['config']}")
 
     def one(k):
         t.restart(sim_id=k, start_step=0)
@@ -92,7 +98,9 @@ def run_plain(args, torch, T, W):
     s_avg_ms = tm["s_ms"] / max(tm["s_launches"], 1)
     achieved = chi_per_launch * OPS_PER_CHI_EVENT / (chi_avg_ms * 1e-3)
     roof = {
-        "bound": "alu", "kernel": "chi_kernel<16>",
+        "bound": "alu",
+        "kernel": ("tissue_chi_" if t.stats()["jit"] else "chi_kernel_") +
+                  ("lane" if tuned and tuned["config"]["chi_mode"] == 0 else "row"),
         "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
         "frac": achieved / PEAK_LANE_OPS, "traffic": None,
         "avg_launch_ms": chi_avg_ms, "events_per_launch": chi_per_launch,
@@ -100,7 +108,7 @@ def run_plain(args, torch, T, W):
         "chi_share_of_kernel_time": tm["chi_ms"] / max(tm["chi_ms"] + tm["s_ms"], 1e-12),
     }
     res = dict(p=p, value=events / elapsed, elapsed=elapsed, lat=lat, chi=chi_ev, s=s_ev,
-               roofline=roof, timing=tm)
+               roofline=roof, timing=tm, tuned=tuned, jit=bool(t.stats()["jit"]))
     t.close()
     return res
 
@@ -138,9 +146,50 @@ def run_batched(args, torch, T, W):
     cells = sum(p["nx"] * p["ny"] for p in probs)
     out = dict(events_per_s=tot_ev / tot_t, tissues=len(probs), cells=cells, steps=n, dt=dt,
                sweep_ms_p50=pct(walls, 50) * 1e3, sweep_ms_p99=pct(walls, 99) * 1e3)
+    # roofline of the batched chi kernel: HIP events around each launch of
+    # two eagerly launched steps
+    for i, t in enumerate(ts):
+        t.restart(sim_id=i + 777, start_step=0)
+    tm = b.step_timed(dt, 2)
+    chi_ev = sum(t.stats()["chi_events"] for t in ts)
+    per_launch_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
+    achieved = chi_ev / max(tm["chi_launches"], 1) * OPS_PER_CHI_EVENT / (per_launch_ms * 1e-3)
+    out["roofline"] = {"bound": "alu", "kernel": "tissue_chi_lane", "achieved": achieved / 1e12,
+                       "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                       "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                       "avg_launch_ms": per_launch_ms,
+                       "events_per_launch": chi_ev / max(tm["chi_launches"], 1),
+                       "ops_per_event": OPS_PER_CHI_EVENT}
     b.close()
     for t in ts:
         t.close()
+    return out
+
+
+def run_serving(args, torch):
+    """Config-5-shaped serving: Poisson arrivals replayed in real time,
+    continuous batching with HBM-budgeted admission; latency = arrival to
+    result in host memory."""
+    from paper_1806_10889_amd import serve
+    reqs = serve.requests_from_workload(args.serve_requests + args.serve_warmup,
+                                        rate_hz=args.serve_rate)
+    log(f"serving: {len(reqs)} requests generated")
+    be = serve.GpuBackend()
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(args.serve_hbm_gib * (1 << 30), 0.5 * free))
+    srv = serve.Server(be, max_bytes=budget, max_active=args.serve_slots, quantum=args.serve_quantum)
+    st, done = srv.run(reqs, real_time=True)
+    measured = [r for r in done if r.rid >= args.serve_warmup]
+    lat = sorted(r.finished - r.arrival for r in measured)
+    ev = sum(r.events for r in measured)
+    span = max(r.finished for r in measured) - min(r.arrival for r in measured)
+    out = st.summary()
+    out.update({"measured_requests": len(measured), "warmup_requests": args.serve_warmup,
+                "offered_rate_hz": args.serve_rate, "quantum_steps": args.serve_quantum,
+                "hbm_budget_bytes": budget,
+                "measured_req_per_s": len(measured) / span, "measured_events_per_s": ev / span,
+                "measured_latency_ms_p50": pct(lat, 50) * 1e3,
+                "measured_latency_ms_p99": pct(lat, 99) * 1e3})
     return out
 
 
@@ -170,6 +219,14 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-reps", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="fixed launch shape instead of the autotuner")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-quantum", type=int, default=10)
+    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-hbm-gib", type=float, default=64.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
@@ -205,7 +262,9 @@ def main():
                                "9+1 reactions, D=1.0, dt=0.05, T=100 (2000 splitting steps)",
                    "cells": 4096, "voxels_per_cell": 16, "species": 5, "dt": 0.05,
                    "T": 0.05 * args.n_steps, "splitting_steps": args.n_steps,
-                   "launch": f"persistent, hipGraph chunks of {args.graph_chunk} steps"},
+                   "launch": (plain["tuned"] or {}).get("config",
+                                                         f"persistent, graph chunk {args.graph_chunk}"),
+                   "network_kernels": "compiled per network" if plain["jit"] else "generic"},
         "plain": {"events_per_s": plain["value"], "chi_events": plain["chi"], "s_events": plain["s"],
                   "sim_latency_ms_p50": pct(plain["lat"], 50) * 1e3,
                   "sim_latency_ms_p99": pct(plain["lat"], 99) * 1e3},
@@ -213,6 +272,8 @@ def main():
     }
     if not args.plain_only:
         out["batched"] = run_batched(args, torch, T, W)
+        if not args.no_serve:
+            out["serving"] = run_serving(args, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, W, plain["p"])
     print(json.dumps(out), flush=True)

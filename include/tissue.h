@@ -214,6 +214,7 @@ int tissue_batch_step(tissue_batch_t *b, double dt, int32_t n_steps);
 int tissue_batch_step_timed(tissue_batch_t *b, double dt, int32_t n_steps, tissue_timing_t *out);
 int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workgroups_per_cu);
 int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode);
+int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph);
 int tissue_batch_sync(tissue_batch_t *b);
 int tissue_batch_destroy(tissue_batch_t *b);
 

@@ -1,0 +1,116 @@
+"""Autotuner of the launch shape.
+
+The launch shape -- chi kernel (one lane per cell / one 16-lane row per
+cell), persistent work queue or one workgroup per item, resident workgroups
+per CU, steps per captured HIP graph -- never changes results (every choice
+is bit-identical), only speed.  `tune` times candidate shapes on a clone of
+the workload (the same problems, restarted before each candidate so all see
+the same work), keeps the fastest, caches it on disk under a signature of
+the workload's shape and applies it.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+
+CACHE = os.environ.get("TISSUE_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "tissue_autotune.json"))
+
+
+def signature(problems) -> str:
+    """Shape of a workload: per problem the lattice, size, mesh histogram and
+    network structure (not the rates, counts or seeds)."""
+    h = hashlib.sha1()
+    for p in problems:
+        V = (np.asarray(p["mesh_w"], np.int64) * np.asarray(p["mesh_h"], np.int64))
+        hist = np.bincount(V, minlength=65)
+        h.update(repr((p["lattice"], p["nx"], p["ny"], p["n_species"], p["n_reactions"],
+                       np.asarray(p["reactants"]).tolist(), np.asarray(p["stoich"]).tolist(),
+                       (np.asarray(p["diffusion"]) > 0).tolist(), p["trans_n"] >= 0,
+                       hist.tolist())).encode())
+    return h.hexdigest()
+
+
+def candidates(max_voxels: int):
+    out = []
+    modes = [0, 1] if max_voxels <= 16 else [0]
+    for mode in modes:
+        for persistent, wpc in [(1, 0), (0, 0), (1, 2), (1, 8)]:
+            for chunk in (25, 100):
+                out.append(dict(chi_mode=mode, persistent=persistent, wpc=wpc, graph_chunk=chunk))
+    return out
+
+
+def apply(target, cfg: dict):
+    target.set_chi_mode(cfg["chi_mode"])
+    target.set_launch(bool(cfg["persistent"]), cfg["wpc"])
+    target.set_graph_chunk(cfg["graph_chunk"])
+
+
+def _load_cache():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def tune(problems, dt: float, steps: int = 50, reps: int = 2, device="cuda:0", target=None,
+         use_cache: bool = True, log=None) -> dict:
+    """Pick the fastest launch shape for `problems` (one tissue, or a batch
+    when several) and apply it to `target` (a Tissue or Batch) if given."""
+    from . import tissue as T
+    sig = signature(problems)
+    cache = _load_cache() if use_cache else {}
+    if sig in cache:
+        best = cache[sig]["config"]
+        if target is not None:
+            apply(target, best)
+        return dict(cache[sig], cached=True)
+    clones = [T.Tissue(p, device=device) for p in problems]
+    runner = clones[0] if len(clones) == 1 else T.Batch(clones, device=device)
+    vmax = max(int(np.max(np.asarray(p["mesh_w"]) * np.asarray(p["mesh_h"]))) for p in problems)
+    results = []
+    for cfg in candidates(vmax):
+        apply(runner, cfg)
+        times = []
+        for _ in range(reps + 1):  # the first run captures the graph
+            for t in clones:
+                t.restart(t.problem["sim_id"], 0)
+            a = time.perf_counter()
+            runner.step(dt, steps)
+            runner.sync()
+            times.append(time.perf_counter() - a)
+        ms = 1e3 * min(times[1:])
+        results.append((ms, cfg))
+        if log:
+            log(f"autotune {cfg}: {ms:.2f} ms / {steps} steps")
+    results.sort(key=lambda x: x[0])
+    best = results[0][1]
+    entry = {"config": best, "ms_per_step": results[0][0] / steps,
+             "worst_ms_per_step": results[-1][0] / steps, "candidates": len(results)}
+    cache[sig] = entry
+    if use_cache:
+        _save_cache(cache)
+    if target is not None:
+        apply(target, best)
+    if runner is not clones[0]:
+        runner.close()
+    for t in clones:
+        t.close()
+    return dict(entry, cached=False)

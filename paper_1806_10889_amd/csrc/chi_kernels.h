@@ -362,6 +362,16 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
         uint32_t j = 0, ev = 0;
         bool overflow = false, capped = false;
         if (active) {
+            // The draw of ordinal j depends only on the counter, so draw j+1
+            // is made while event j proceeds (two independent dependency
+            // chains for the scheduler); the one draw past the last is unused.
+            double e1, u2;
+            {
+                const tdev::Words4 wds = tdev::philox4x32_10(0u, c.step, cell, c.tagword, c.key0, c.key1);
+                double u1;
+                tdev::two_uniforms(wds, u1, u2);
+                e1 = -tdev::plog(u1);
+            }
             for (;;) {
                 const double a0 = tree[1 * stride];
                 if (a0 == 0.0) break;
@@ -369,15 +379,17 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                     capped = true;
                     break;
                 }
-                const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
                 ++j;
-                double u1, u2;
-                tdev::two_uniforms(wds, u1, u2);
-                const double tau = (-tdev::plog(u1)) / a0;
-                const double tn = t + tau;
+                const double tn = t + e1 / a0;
                 if (tn >= dt) break;
                 t = tn;
                 double r = u2 * a0;
+                {
+                    const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
+                    double u1;
+                    tdev::two_uniforms(wds, u1, u2);
+                    e1 = -tdev::plog(u1);
+                }
 
                 // descend the sum tree
                 int n = 1;

@@ -1175,6 +1175,15 @@ int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workg
     return TISSUE_OK;
 }
 
+int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph)
+{
+    if (!b || steps_per_graph < 0 || steps_per_graph > 100000) return fail(TISSUE_EINVAL, "bad graph chunk");
+    HIP_TRY(hipStreamSynchronize(b->lp.stream));
+    b->lp.graph_chunk = steps_per_graph;
+    b->lp.clear_graphs();
+    return TISSUE_OK;
+}
+
 int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode)
 {
     if (!b || mode < kModeLane || mode > kModeAuto) return fail(TISSUE_EINVAL, "chi mode must be 0, 1 or 2");

@@ -66,6 +66,7 @@ EXPORTS = [
     "tissue_read_stats", "tissue_read_trace", "tissue_restart", "tissue_write_counts",
     "tissue_set_launch", "tissue_set_chi_mode", "tissue_set_graph_chunk", "tissue_step_timed",
     "tissue_destroy", "tissue_batch_set_chi_mode", "tissue_network_check",
+    "tissue_batch_set_graph_chunk",
     "tissue_batch_required_bytes", "tissue_batch_create", "tissue_batch_step",
     "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
     "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
@@ -94,6 +95,7 @@ def _load():
         "tissue_set_graph_chunk": (C.c_int, [vp, i32]),
         "tissue_set_chi_mode": (C.c_int, [vp, i32]),
         "tissue_batch_set_chi_mode": (C.c_int, [vp, i32]),
+        "tissue_batch_set_graph_chunk": (C.c_int, [vp, i32]),
         "tissue_step_timed": (C.c_int, [vp, dbl, i32, C.POINTER(Timing)]),
         "tissue_destroy": (C.c_int, [vp]),
         "tissue_batch_required_bytes": (sz, [C.POINTER(vp), i32]),
@@ -260,6 +262,9 @@ class Tissue:
     def set_graph_chunk(self, steps: int):
         _check(lib.tissue_set_graph_chunk(self.handle, int(steps)), "tissue_set_graph_chunk")
 
+    def sync(self):
+        self.stats()
+
     def close(self):
         if getattr(self, "handle", None):
             lib.tissue_destroy(self.handle)
@@ -309,6 +314,13 @@ class Batch:
 
     def set_chi_mode(self, mode: int):
         _check(lib.tissue_batch_set_chi_mode(self.handle, int(mode)), "tissue_batch_set_chi_mode")
+
+    def set_graph_chunk(self, steps: int):
+        _check(lib.tissue_batch_set_graph_chunk(self.handle, int(steps)), "tissue_batch_set_graph_chunk")
+
+    def restart(self, sim_ids=None, start_step: int = 0):
+        for i, t in enumerate(self.tissues):
+            t.restart(t.problem["sim_id"] if sim_ids is None else sim_ids[i], start_step)
 
     def sync(self):
         _check(lib.tissue_batch_sync(self.handle), "tissue_batch_sync")
