@@ -150,59 +150,48 @@ __device__ __forceinline__ double voxel_fold(const NET &n, const double *xd, dou
 }
 
 // The selection scan over the same fold: the first channel with a_k > 0
-// and r < prefix through k, else the last channel with a_k > 0.  Returns the
-// channel slot (reactions 0..RM-1, diffusion RM + q), the residual r minus
-// the prefix before it, and for diffusion D_s x_s and s.
+// and r < prefix through k, else the last channel with a_k > 0.  Prefixes
+// never decrease and a zero channel repeats its predecessor's prefix, so
+// the first channel with r < prefix_k always has a_k > 0, and its index is
+// the number of channels whose prefix is <= r; the prefix before it is the
+// largest prefix <= r.  Counting and selecting (no branches) gives the same
+// channel as the sequential rule.  Returns the channel slot (reactions
+// 0..RM-1, diffusion RM + q), the residual r minus the prefix before it, and
+// for diffusion D_s x_s and s.
 template <class NET>
 __device__ __forceinline__ int voxel_select(const NET &n, const double *xd, double degd, double r,
                                             double &resid, double &a1, int &spec)
 {
     constexpr int RM = NET::RM, NDM = NET::NDM;
-    double acc = 0.0, before = 0.0, last_before = 0.0, a1_sel = 0.0, a1_last = 0.0;
-    int sel = -1, last = -1, s_sel = 0, s_last = 0;
+    double acc = 0.0, before = 0.0, last_before = 0.0;
+    int below = 0, last = -1;
 #pragma unroll
-    for (int k = 0; k < RM; ++k) {
-        const double a = reaction_prop(n, k, xd);
+    for (int k = 0; k < RM + NDM; ++k) {
+        const double a = k < RM ? reaction_prop(n, k, xd)
+                                : n.drate[k - RM] * (xd[n.dsp(k - RM)] * degd);
         const double next = acc + a;
-        if (a > 0.0) {
-            if (sel < 0 && r < next) {
-                sel = k;
-                before = acc;
-            }
-            last = k;
-            last_before = acc;
-        }
+        const bool under = r >= next;
+        below += under ? 1 : 0;
+        before = under ? next : before;
+        const bool pos = a > 0.0;
+        last = pos ? k : last;
+        last_before = pos ? acc : last_before;
         acc = next;
     }
-#pragma unroll
-    for (int q = 0; q < NDM; ++q) {
-        const double xs = xd[n.dsp(q)];
-        const double a = n.drate[q] * (xs * degd);
-        const double next = acc + a;
-        if (a > 0.0) {
-            const double one = n.drate[q] * xs;
-            if (sel < 0 && r < next) {
-                sel = RM + q;
-                before = acc;
-                a1_sel = one;
-                s_sel = n.dsp(q);
-            }
-            last = RM + q;
-            last_before = acc;
-            a1_last = one;
-            s_last = n.dsp(q);
-        }
-        acc = next;
-    }
-    if (sel < 0) {
+    int sel = below;
+    if (sel >= RM + NDM) {
         sel = last;
         before = last_before;
-        a1_sel = a1_last;
-        s_sel = s_last;
     }
     resid = r - before;
-    a1 = a1_sel;
-    spec = s_sel;
+    a1 = 0.0;
+    spec = 0;
+#pragma unroll
+    for (int q = 0; q < NDM; ++q) {
+        const bool is_q = sel == RM + q;
+        a1 = is_q ? n.drate[q] * xd[n.dsp(q)] : a1;
+        spec = is_q ? n.dsp(q) : spec;
+    }
     return sel;
 }
 
@@ -214,6 +203,17 @@ __device__ __forceinline__ int reaction_delta(const NET &n, int sel, int s)
 #pragma unroll
     for (int k = 0; k < NET::RM; ++k) d += (k == sel) ? n.delta(k, s) : 0;
     return d;
+}
+
+// The value unchanged, but opaque to the optimiser (an empty asm with a
+// vector-register constraint; no instruction is emitted).  Used inside the
+// event loops so that compares on loop-invariant per-lane values are redone
+// per iteration instead of being hoisted and held live as scalar lane masks,
+// which exhausts the scalar registers.
+__device__ __forceinline__ int opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
 }
 
 // Voxel v = y*w + x of a w x h mesh (v < 64, w <= 8): y = (v * inv_w) >> 16
@@ -406,10 +406,11 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                 const int v = n - P;
 
                 // the voxel's counts, the channel, the change
+                const Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
                 int32_t *x = cnt + v * S * stride;
 #pragma unroll
                 for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
-                const int deg = voxel_degree(g, v);
+                const int deg = voxel_degree(go, v);
                 double resid, a1;
                 int spec;
                 const int sel = voxel_select(net, xd, (double)deg, r, resid, a1, spec);
@@ -425,7 +426,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                         }
                     }
                 } else {
-                    dst = neighbour_at(g, v, jump_direction(resid, a1, deg));
+                    dst = neighbour_at(go, v, jump_direction(resid, a1, deg));
 #pragma unroll
                     for (int q = 0; q < SM; ++q)
                         if (q == spec) xd[q] -= 1.0;
@@ -439,7 +440,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                 if (dst != v) {
 #pragma unroll
                     for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(dst * S + q) * stride];
-                    tree[(P + dst) * stride] = voxel_fold(net, xd, (double)voxel_degree(g, dst));
+                    tree[(P + dst) * stride] = voxel_fold(net, xd, (double)voxel_degree(go, dst));
                 }
                 // ancestors of the changed leaves
                 int na = (P + v) >> 1, nb = (P + dst) >> 1;
@@ -613,12 +614,13 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                 }
             }
             // which lane's leaf the descent reaches
+            const int lvo = opaque(lv);
             double rr = u2 * a0;
             bool on = true;
-            descent_level(s3, p3, (lv >> 3) & 1, rr, on);
-            descent_level(s2, p2, (lv >> 2) & 1, rr, on);
-            descent_level(s1, p1, (lv >> 1) & 1, rr, on);
-            descent_level(leaf, p0, lv & 1, rr, on);
+            descent_level(s3, p3, (lvo >> 3) & 1, rr, on);
+            descent_level(s2, p2, (lvo >> 2) & 1, rr, on);
+            descent_level(s1, p1, (lvo >> 1) & 1, rr, on);
+            descent_level(leaf, p0, lvo & 1, rr, on);
             on = on && event;
 
             bool changed = false;
@@ -634,7 +636,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                         overflow |= (xd[q] < 0.0) | (xd[q] >= (double)kCountLimit);
                     }
                 } else {
-                    const int dst = neighbour_at(g, lv, jump_direction(resid, a1, deg));
+                    Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
+                    const int dst = neighbour_at(go, lvo, jump_direction(resid, a1, opaque(deg)));
 #pragma unroll
                     for (int q = 0; q < SM; ++q)
                         if (q == spec) xd[q] -= 1.0;
@@ -646,7 +649,7 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             // zero outside the selected lane): OR over the 16-lane row
             word = row_or(word);
             if (event) {
-                if ((word & 1u) && (int)(word >> 8) == lv) {
+                if ((word & 1u) && (int)(word >> 8) == lvo) {
                     const int spec = (int)((word >> 4) & 15u);
 #pragma unroll
                     for (int q = 0; q < SM; ++q)

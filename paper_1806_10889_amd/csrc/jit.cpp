@@ -83,10 +83,12 @@ std::string network_source(const DevModel &M)
       << "    __device__ __forceinline__ int delta(int r, int s) const { return kDelta[r * SM + s]; }\n"
       << "    __device__ __forceinline__ void load(const DevModel &M)\n"
       << "    {\n"
+      // rates as vector registers: scalar registers are the scarcer resource
+      // in these kernels (lane masks), vector registers do not limit occupancy
       << "#pragma unroll\n"
-      << "        for (int r = 0; r < RM; ++r) rate[r] = uni(M.rates[r]);\n"
+      << "        for (int r = 0; r < RM; ++r) rate[r] = M.rates[r];\n"
       << "#pragma unroll\n"
-      << "        for (int q = 0; q < NDM; ++q) drate[q] = uni(M.diff_rate[q]);\n"
+      << "        for (int q = 0; q < NDM; ++q) drate[q] = M.diff_rate[q];\n"
       << "    }\n"
       << "};\n"
       << "}  // namespace tissue_impl\n"
