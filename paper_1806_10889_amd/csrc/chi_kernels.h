@@ -44,8 +44,10 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *queue, bool persistent, 
 }
 
 // Called by every workgroup when it has no more items: the last one out
-// resets the queue and the exit counter (queue[0], queue[1]).
-__device__ __forceinline__ void leave_queue(uint32_t *queue, bool persistent)
+// resets the queue and the exit counter (queue[0], queue[1]) and, if given,
+// one more counter (the retry count consumed by a follow-up launch).
+__device__ __forceinline__ void leave_queue(uint32_t *queue, bool persistent,
+                                            uint32_t *also_reset = nullptr)
 {
     if (!persistent) return;
     if (threadIdx.x == 0) {
@@ -54,6 +56,7 @@ __device__ __forceinline__ void leave_queue(uint32_t *queue, bool persistent)
         if (done == gridDim.x - 1) {
             atomicExch(queue, 0u);
             atomicExch(queue + 1, 0u);
+            if (also_reset) atomicExch(also_reset, 0u);
         }
     }
 }
@@ -306,13 +309,17 @@ __device__ __forceinline__ void item_stats(const ItemCtx &c, uint32_t ev, uint32
 // chi, one lane per cell.  LDS per lane: the sum tree (2P doubles) and the
 // cell's counts (P*S int32, voxel-major), field-major across lanes.
 // ---------------------------------------------------------------------------
+// n_items_dev: when not null the item count is read from device memory
+// (the retry list of a lane16 launch) and *n_items_dev is cleared by the
+// last workgroup.
 template <class NET>
 __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissue *const *tbl,
                                               const ChiItem *items, uint32_t n_items, uint32_t *queue,
                                               int persistent, int cells_per_item, int log2p, double dt,
-                                              uint32_t kstep)
+                                              uint32_t kstep, uint32_t *n_items_dev)
 {
     constexpr int SM = NET::SM, RM = NET::RM;
+    if (n_items_dev) n_items = uni(*(volatile uint32_t *)n_items_dev);
     const int lane = threadIdx.x;
     const int stride = cells_per_item;
     const int P = 1 << log2p;
@@ -467,7 +474,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
         }
         item_stats(c, ev, j, overflow, capped, 0);
     }
-    leave_queue(queue, persistent != 0);
+    leave_queue(queue, persistent != 0, n_items_dev);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,6 +683,234 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
         }
         item_stats(c, lv == 0 ? ev : 0u, lv == 0 ? j : 0u, overflow, capped, 0);
+    }
+    leave_queue(queue, persistent != 0);
+}
+
+
+// ---------------------------------------------------------------------------
+// chi, one lane per cell of at most 16 voxels, compact LDS: per cell only the
+// 16 leaf propensities (FP64, stored as pairs so one 16-byte read fetches
+// two) and the counts as uint16 -- 288 B for 16 voxels x 5 species, half of
+// the full layout, so twice the wavefronts fit a CU.  The levels of the
+// 16-leaf sum tree are rebuilt in registers every event (the same pairwise
+// sums as the heap, so the same bits) and the descent selects among them.
+// A cell whose count would reach 2^16 abandons its step without writing
+// anything back and is queued (retry_items, *retry_count); a follow-up
+// launch of the full-width lane kernel redoes that cell-step from the
+// unchanged counts in HBM, with identical bits, since a cell-step depends
+// only on its starting counts and its counters.
+// ---------------------------------------------------------------------------
+constexpr int kLane16Leaves = 16;
+constexpr int32_t kLane16Limit = 1 << 16;
+
+__host__ __device__ inline size_t lane16_lds_bytes(int S, int stride)
+{
+    return (size_t)stride * ((size_t)kLane16Leaves * 8 + ((size_t)kLane16Leaves * S + kMaxSpecies) * 2);
+}
+
+template <class NET>
+__device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTissue *const *tbl,
+                                                const ChiItem *items, uint32_t n_items,
+                                                uint32_t *queue, int persistent, int cells_per_item,
+                                                double dt, uint32_t kstep, ChiItem *retry_items,
+                                                uint32_t *retry_count)
+{
+    constexpr int SM = NET::SM, RM = NET::RM;
+    const int lane = threadIdx.x;
+    const int stride = cells_per_item;
+    uint32_t cursor = blockIdx.x;
+    for (;;) {
+        const uint32_t it = next_item(queue, persistent != 0, cursor);
+        if (it >= n_items) break;
+        const ChiItem item = items[it];
+        const ItemCtx c = item_ctx(tbl, item, kstep);
+        NET net;
+        net.load(c.T->model);
+        const int S = c.S;
+        // leaf pairs: pair k of this lane at lds + (k * stride + lane) * 16
+        double *leafp = reinterpret_cast<double *>(lds) + 2 * lane;
+        uint16_t *cnt = reinterpret_cast<uint16_t *>(lds + (size_t)stride * kLane16Leaves * 8) + lane;
+
+        const bool active = lane < (int)c.count;
+        uint32_t cell = 0;
+        Mesh g{1, 1, 65537};
+        long long gbase = 0;
+        bool retry = false;
+        if (active) {
+            cell = (uint32_t)c.T->cell_list[c.first + lane];
+            g.w = c.T->wh[2 * cell];
+            g.h = c.T->wh[2 * cell + 1];
+            g.inv_w = 65536 / g.w + 1;
+            gbase = (long long)c.T->vox_off[cell] * S;
+            const int n = g.w * g.h * S;
+            for (int i = 0; i < n; ++i) {
+                const int32_t x = c.counts[gbase + i];
+                retry |= x >= kLane16Limit;
+                cnt[i * stride] = (uint16_t)x;
+            }
+        }
+        const int V = g.w * g.h;
+        double xd[SM];
+        if (active && !retry) {
+#pragma unroll
+            for (int k = 0; k < kLane16Leaves / 2; ++k) {
+                double two[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int v = 2 * k + h;
+                    two[h] = 0.0;
+                    if (v < V) {
+#pragma unroll
+                        for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(v * S + q) * stride];
+                        two[h] = voxel_fold(net, xd, (double)voxel_degree(g, v));
+                    }
+                }
+                double *slot = leafp + (size_t)k * stride * 2;
+                slot[0] = two[0];
+                slot[1] = two[1];
+            }
+        }
+
+        double t = 0.0;
+        uint32_t j = 0, ev = 0;
+        bool overflow = false, capped = false;
+        if (active && !retry) {
+            double e1, u2;
+            {
+                const tdev::Words4 wds = tdev::philox4x32_10(0u, c.step, cell, c.tagword, c.key0, c.key1);
+                double u1;
+                tdev::two_uniforms(wds, u1, u2);
+                e1 = -tdev::plog(u1);
+            }
+            for (;;) {
+                // the 16 leaves and the levels of the tree above them
+                double l[kLane16Leaves];
+#pragma unroll
+                for (int k = 0; k < kLane16Leaves / 2; ++k) {
+                    const double *slot = leafp + (size_t)k * stride * 2;
+                    l[2 * k] = slot[0];
+                    l[2 * k + 1] = slot[1];
+                }
+                double q1[8], q2[4], q3[2];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) q1[k] = l[2 * k] + l[2 * k + 1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) q2[k] = q1[2 * k] + q1[2 * k + 1];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) q3[k] = q2[2 * k] + q2[2 * k + 1];
+                const double a0 = q3[0] + q3[1];
+                if (a0 == 0.0) break;
+                if (ev >= c.cap) {
+                    capped = true;
+                    break;
+                }
+                ++j;
+                const double tn = t + e1 / a0;
+                if (tn >= dt) break;
+                t = tn;
+                double r = u2 * a0;
+                {
+                    const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
+                    double u1;
+                    tdev::two_uniforms(wds, u1, u2);
+                    e1 = -tdev::plog(u1);
+                }
+                // descent: left if r < L or R == 0, else r -= L and right
+                int v = 0;
+                {
+                    double L = q3[0], R = q3[1];
+                    bool left = (r < L) || (R == 0.0);
+                    r = left ? r : r - L;
+                    const int b3 = left ? 0 : 1;
+                    L = b3 ? q2[2] : q2[0];
+                    R = b3 ? q2[3] : q2[1];
+                    left = (r < L) || (R == 0.0);
+                    r = left ? r : r - L;
+                    const int i2 = 2 * b3 + (left ? 0 : 1);
+                    L = q1[0];
+                    R = q1[1];
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) {
+                        L = i2 == k ? q1[2 * k] : L;
+                        R = i2 == k ? q1[2 * k + 1] : R;
+                    }
+                    left = (r < L) || (R == 0.0);
+                    r = left ? r : r - L;
+                    const int i1 = 2 * i2 + (left ? 0 : 1);
+                    L = l[0];
+                    R = l[1];
+#pragma unroll
+                    for (int k = 1; k < 8; ++k) {
+                        L = i1 == k ? l[2 * k] : L;
+                        R = i1 == k ? l[2 * k + 1] : R;
+                    }
+                    left = (r < L) || (R == 0.0);
+                    r = left ? r : r - L;
+                    v = 2 * i1 + (left ? 0 : 1);
+                }
+
+                const Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
+                uint16_t *x = cnt + v * S * stride;
+#pragma unroll
+                for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
+                const int deg = voxel_degree(go, v);
+                double resid, a1;
+                int spec;
+                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1, spec);
+                int dst = v;
+                bool wide = false;
+                if (sel < RM) {
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) {
+                        const int d = reaction_delta(net, sel, q);
+                        if (q < S && d != 0) {
+                            xd[q] += (double)d;
+                            wide |= xd[q] >= (double)kLane16Limit;
+                            x[q * stride] = (uint16_t)(int32_t)xd[q];
+                        }
+                    }
+                } else {
+                    dst = neighbour_at(go, v, jump_direction(resid, a1, deg));
+#pragma unroll
+                    for (int q = 0; q < SM; ++q)
+                        if (q == spec) xd[q] -= 1.0;
+                    x[spec * stride] = (uint16_t)(x[spec * stride] - 1);
+                    uint16_t *xdst = cnt + (dst * S + spec) * stride;
+                    const int32_t nd = (int32_t)*xdst + 1;
+                    wide |= nd >= kLane16Limit;
+                    *xdst = (uint16_t)nd;
+                }
+                if (wide) {  // redo this cell-step at full width
+                    retry = true;
+                    break;
+                }
+                // new leaves of v (and dst)
+                const double lv = voxel_fold(net, xd, (double)deg);
+                leafp[(size_t)(v >> 1) * stride * 2 + (v & 1)] = lv;
+                if (dst != v) {
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(dst * S + q) * stride];
+                    leafp[(size_t)(dst >> 1) * stride * 2 + (dst & 1)] =
+                        voxel_fold(net, xd, (double)voxel_degree(go, dst));
+                }
+                ++ev;
+            }
+        }
+        if (active && retry) {
+            const uint32_t at = atomicAdd(retry_count, 1u);
+            retry_items[at] = ChiItem{item.tissue, c.first + (uint32_t)lane, 1u, 0u};
+        } else if (active) {
+            const int n = V * S;
+            for (int i = 0; i < n; ++i) c.counts[gbase + i] = (int32_t)cnt[i * stride];
+            if (c.T->tr_chi_ev) {
+                const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
+                const size_t slot = (size_t)(c.step % ts) * nc + cell;
+                c.T->tr_chi_ev[slot] = ev;
+                c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
+            }
+        }
+        item_stats(c, retry ? 0u : ev, retry ? 0u : j, overflow && !retry, capped && !retry, 0);
     }
     leave_queue(queue, persistent != 0);
 }

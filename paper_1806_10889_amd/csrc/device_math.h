@@ -23,6 +23,7 @@ using __hip_internal::int8_t;
 using __hip_internal::int32_t;
 using __hip_internal::int64_t;
 using __hip_internal::uint8_t;
+using __hip_internal::uint16_t;
 using __hip_internal::uint32_t;
 using __hip_internal::uint64_t;
 #endif

@@ -173,7 +173,8 @@ struct Plan {
     uint32_t trace_steps = 0;
     // byte offsets inside dev_buf
     size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
-           off_cells = 0, off_edges = 0, off_chi = 0, off_s = 0, off_ctl = 0, off_trace = 0, bytes = 0;
+           off_cells = 0, off_edges = 0, off_chi = 0, off_s = 0, off_ctl = 0, off_trace = 0,
+           off_retry = 0, bytes = 0;
     size_t n_chi_items = 0, n_s_items = 0;
 };
 
@@ -386,7 +387,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     p.off_edges = take((size_t)p.nedge * sizeof(EdgeRec));
     p.off_chi = take(p.n_chi_items * sizeof(ChiItem));
     p.off_s = take(p.n_s_items * sizeof(SItem));
-    p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue[2] u32
+    p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue words u32[8]
+    p.off_retry = take((size_t)p.ncell * sizeof(ChiItem));  // lane16 cells to redo
     p.off_trace = take((size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12));
     p.bytes = o;
     return TISSUE_OK;
@@ -397,7 +399,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
 // ---------------------------------------------------------------------------
 
 struct ChiLaunch {
-    int mode;                // kChiLane or kChiRow
+    int mode;                // kChiLane, kChiRow or kChiLane16
+    size_t retry_lds;        // lane16: LDS of the full-width redo launch
     const JitKernels *jit;   // compiled-network kernels, or null: generic ones
     int SM, RM, NDM;         // generic kernel instantiation (table sizes)
     int P, cells_per_item;
@@ -406,9 +409,10 @@ struct ChiLaunch {
     uint32_t n_items;
 };
 
-// chi mode request: lane, row, or automatic (row mode for classes of at
-// most 16 voxels when one lane per cell would not give every SIMD a wave)
-enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2 };
+// chi mode request: lane, row, automatic, or lane16.  Automatic: for classes
+// of at most 16 voxels, row mode when one lane per cell would not give every
+// SIMD a wavefront, else the compact lane16 layout; larger cells: lane mode.
+enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2, kModeLane16 = 3 };
 
 // Work items and launches of the chi operator over a set of tissues: one
 // launch per (leaf class, kernel instantiation).  Items are written to
@@ -458,8 +462,9 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         int mode = kChiLane;
         if (k.P <= 16) {
             if (mode_req == kModeRow) mode = kChiRow;
-            if (mode_req == kModeAuto && cells < (uint64_t)kWave * (uint64_t)std::max(n_simd, 1))
-                mode = kChiRow;
+            if (mode_req == kModeLane16) mode = kChiLane16;
+            if (mode_req == kModeAuto)
+                mode = cells < (uint64_t)kWave * (uint64_t)std::max(n_simd, 1) ? kChiRow : kChiLane16;
         }
         ChiLaunch L;
         L.mode = mode;
@@ -468,8 +473,17 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         L.RM = G.RM;
         L.NDM = G.NDM;
         L.P = k.P;
-        L.cells_per_item = mode == kChiRow ? 4 : lane_cells_per_item(k.P, G.max_s);
+        if (mode == kChiRow) {
+            L.cells_per_item = 4;
+        } else if (mode == kChiLane16) {
+            int cpi = 64;
+            while (cpi > 1 && chi_lds_bytes(kChiLane16, 16, G.max_s, cpi) > kChiLdsBudget) cpi >>= 1;
+            L.cells_per_item = cpi;
+        } else {
+            L.cells_per_item = lane_cells_per_item(k.P, G.max_s);
+        }
         L.lds = chi_lds_bytes(mode, k.P, G.max_s, L.cells_per_item);
+        L.retry_lds = chi_lds_bytes(kChiLane, k.P, G.max_s, 1);
         const size_t off = items_out.size();
         for (auto &m : G.cells) cut_items(m.first, m.second->first, m.second->count, L.cells_per_item, items_out);
         L.items = reinterpret_cast<const ChiItem *>(off);
@@ -498,6 +512,7 @@ struct LaunchPlan {
     std::vector<const Plan *> members;
     ChiItem *chi_items = nullptr;  // device region for chi work items
     size_t chi_items_cap = 0;
+    ChiItem *retry_items = nullptr;  // device region: lane16 cells to redo (one per cell)
     int chi_mode = kModeAuto;
     std::vector<ChiLaunch> chi;
     std::vector<SLaunch> s;
@@ -521,26 +536,65 @@ struct LaunchPlan {
         graphs.clear();
     }
 
+    // One chi launch of a group; for lane16 also the full-width redo of the
+    // cells it handed back (a persistent launch that reads the count from
+    // device memory and exits at once when it is zero).
     hipError_t launch_chi_any(const ChiLaunch &L, uint32_t grid, hipStream_t st, double dt,
                               uint32_t kstep)
     {
-        if (!L.jit)
-            return launch_chi(L.mode, L.SM, L.RM, L.NDM, L.P, grid, L.lds, st, tbl, L.items,
-                              L.n_items, queue, persistent, L.cells_per_item, dt, kstep);
-        const DevTissue *const *tb = tbl;
-        const ChiItem *it = L.items;
-        uint32_t ni = L.n_items;
-        uint32_t *qu = queue;
-        int pe = persistent, cpi = L.cells_per_item;
         int log2p = 0;
         while ((1 << log2p) < L.P) ++log2p;
-        if (L.mode == kChiRow) {
-            void *args[] = {&tb, &it, &ni, &qu, &pe, &dt, &kstep};
-            return hipModuleLaunchKernel(L.jit->row, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
+        ChiArgs a{};
+        a.mode = L.mode;
+        a.P = L.P;
+        a.grid = grid;
+        a.lds = L.lds;
+        a.stream = st;
+        a.tbl = tbl;
+        a.items = L.items;
+        a.n_items = L.n_items;
+        a.queue = queue + kQNext;
+        a.persistent = persistent;
+        a.cells_per_item = L.cells_per_item;
+        a.dt = dt;
+        a.kstep = kstep;
+        a.retry_items = retry_items;
+        a.retry_count = queue + kQRetry;
+        hipError_t e = hipSuccess;
+        if (!L.jit) {
+            e = launch_chi(L.SM, L.RM, L.NDM, a);
+        } else if (L.mode == kChiRow) {
+            void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.dt, &a.kstep};
+            e = hipModuleLaunchKernel(L.jit->row, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
+        } else if (L.mode == kChiLane16) {
+            void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
+                            &a.dt, &a.kstep, &a.retry_items, &a.retry_count};
+            e = hipModuleLaunchKernel(L.jit->lane16, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st,
+                                      args, nullptr);
+        } else {
+            uint32_t *none = nullptr;
+            void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
+                            &log2p, &a.dt, &a.kstep, &none};
+            e = hipModuleLaunchKernel(L.jit->lane, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st,
+                                      args, nullptr);
         }
-        void *args[] = {&tb, &it, &ni, &qu, &pe, &cpi, &log2p, &dt, &kstep};
-        return hipModuleLaunchKernel(L.jit->lane, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st, args,
-                                     nullptr);
+        if (e != hipSuccess || L.mode != kChiLane16) return e;
+        // the redo launch: one cell per item, full-width layout
+        ChiArgs r = a;
+        r.mode = kChiLane;
+        r.grid = (uint32_t)std::max(1, cus);
+        r.lds = L.retry_lds;
+        r.items = retry_items;
+        r.n_items = 0;
+        r.queue = queue + kQRetryNext;
+        r.persistent = 1;
+        r.cells_per_item = 1;
+        r.n_items_dev = queue + kQRetry;
+        if (!L.jit) return launch_chi(L.SM, L.RM, L.NDM, r);
+        void *args[] = {&r.tbl, &r.items, &r.n_items, &r.queue, &r.persistent, &r.cells_per_item,
+                        &log2p, &r.dt, &r.kstep, &r.n_items_dev};
+        return hipModuleLaunchKernel(L.jit->lane, r.grid, 1, 1, kWave, 1, 1, (unsigned)r.lds, st,
+                                     args, nullptr);
     }
 
     uint32_t chi_grid(const ChiLaunch &L) const
@@ -846,6 +900,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     L.stream = st;
     L.cus = cus;
     L.members = {&t->plan};
+    L.retry_items = reinterpret_cast<ChiItem *>(base + p.off_retry);
     L.chi_items = reinterpret_cast<ChiItem *>(base + p.off_chi);
     L.chi_items_cap = p.n_chi_items;
     size_t off = 0;
@@ -999,7 +1054,7 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
 
 int tissue_set_chi_mode(tissue_t *t, int32_t mode)
 {
-    if (!t || mode < kModeLane || mode > kModeAuto) return fail(TISSUE_EINVAL, "chi mode must be 0, 1 or 2");
+    if (!t || mode < kModeLane || mode > kModeLane16) return fail(TISSUE_EINVAL, "chi mode must be 0..3");
     return t->lp.set_chi_mode(mode);
 }
 
@@ -1027,7 +1082,7 @@ int tissue_destroy(tissue_t *t)
 namespace {
 
 struct BatchLayout {
-    size_t off_tbl = 0, off_queue = 0, off_chi = 0, off_s = 0, bytes = 0;
+    size_t off_tbl = 0, off_queue = 0, off_chi = 0, off_s = 0, off_retry = 0, bytes = 0;
     size_t chi_cap = 0;
     std::vector<std::vector<SItem>> s_passes;
 };
@@ -1074,6 +1129,9 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
     B.off_queue = take(64);
     B.off_chi = take(B.chi_cap * sizeof(ChiItem));
     B.off_s = take(n_s * sizeof(SItem));
+    size_t cells = 0;
+    for (int32_t i = 0; i < n; ++i) cells += ts[i]->plan.ncell;
+    B.off_retry = take(cells * sizeof(ChiItem));
     B.bytes = o;
     return TISSUE_OK;
 }
@@ -1121,6 +1179,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     L.stream = st;
     L.cus = cus;
     for (int32_t i = 0; i < n; ++i) L.members.push_back(&ts[i]->plan);
+    L.retry_items = reinterpret_cast<ChiItem *>(b->dev + B.off_retry);
     L.chi_items = reinterpret_cast<ChiItem *>(b->dev + B.off_chi);
     L.chi_items_cap = B.chi_cap;
     size_t off = 0;
@@ -1186,7 +1245,7 @@ int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph)
 
 int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode)
 {
-    if (!b || mode < kModeLane || mode > kModeAuto) return fail(TISSUE_EINVAL, "chi mode must be 0, 1 or 2");
+    if (!b || mode < kModeLane || mode > kModeLane16) return fail(TISSUE_EINVAL, "chi mode must be 0..3");
     return b->lp.set_chi_mode(mode);
 }
 

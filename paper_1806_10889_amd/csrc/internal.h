@@ -81,9 +81,16 @@ struct ChiItem {
     uint32_t pad;
 };
 
-// chi kernel variants: one lane per cell (any P), or one 16-lane row per cell
-// (P <= 16, four cells per wavefront)
-enum ChiMode { kChiLane = 0, kChiRow = 1 };
+// chi kernel variants: one lane per cell (any P); one 16-lane row per cell
+// (P <= 16, four cells per wavefront); one lane per cell with the compact
+// 16-leaf / uint16 LDS layout (P <= 16) and a full-width redo of cells whose
+// counts outgrow 16 bits
+enum ChiMode { kChiLane = 0, kChiRow = 1, kChiLane16 = 2 };
+
+// device control words of a launch plan (uint32 each): the persistent queue
+// of the main launches, the retry count of lane16 launches, and the queue of
+// the follow-up (retry) launches
+enum { kQNext = 0, kQDone = 1, kQRetry = 2, kQRetryNext = 4, kQRetryDone = 5 };
 
 // up to 64 consecutive edges [first, first + count) of one tissue
 struct SItem {

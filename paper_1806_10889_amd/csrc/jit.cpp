@@ -95,11 +95,21 @@ std::string network_source(const DevModel &M)
       << "using tissue_impl::ChiItem;\nusing tissue_impl::DevTissue;\n"
       << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane(\n"
       << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
-      << "    int persistent, int cells_per_item, int log2p, double dt, uint32_t kstep)\n"
+      << "    int persistent, int cells_per_item, int log2p, double dt, uint32_t kstep,\n"
+      << "    uint32_t *n_items_dev)\n"
       << "{\n"
       << "    extern __shared__ __align__(16) unsigned char lds[];\n"
       << "    tissue_impl::chi_lane_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
-      << "        persistent, cells_per_item, log2p, dt, kstep);\n"
+      << "        persistent, cells_per_item, log2p, dt, kstep, n_items_dev);\n"
+      << "}\n"
+      << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane16(\n"
+      << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
+      << "    int persistent, int cells_per_item, double dt, uint32_t kstep,\n"
+      << "    ChiItem *retry_items, uint32_t *retry_count)\n"
+      << "{\n"
+      << "    extern __shared__ __align__(16) unsigned char lds[];\n"
+      << "    tissue_impl::chi_lane16_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
+      << "        persistent, cells_per_item, dt, kstep, retry_items, retry_count);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row(\n"
       << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
@@ -171,6 +181,7 @@ int jit_kernels(const DevModel &M, const JitKernels **out, std::string &err)
     hipError_t e = hipModuleLoadData(&k->module, code.data());
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane, k->module, "tissue_chi_lane");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->row, k->module, "tissue_chi_row");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16, k->module, "tissue_chi_lane16");
     if (e != hipSuccess) {
         err = std::string("loading the compiled network: ") + hipGetErrorString(e);
         return -1;

@@ -13,6 +13,7 @@ struct JitKernels {
     hipModule_t module = nullptr;
     hipFunction_t lane = nullptr;  // one lane per cell
     hipFunction_t row = nullptr;   // one 16-lane row per cell
+    hipFunction_t lane16 = nullptr; // one lane per cell, compact LDS
 };
 
 // Cache key of a network's structure (not its rates).

@@ -8,16 +8,32 @@
 namespace tissue_impl {
 
 // Dynamic LDS bytes of one chi workgroup (lane mode: per cell 2P FP64 tree
-// nodes and P*S counts; row mode: none).
+// nodes and P*S int32 counts; lane16: 16 FP64 leaves and 16*S uint16 counts;
+// row mode: none).
 size_t chi_lds_bytes(int mode, int P, int S, int cells_per_item);
+
+// Arguments of one chi launch.
+struct ChiArgs {
+    int mode, P;
+    uint32_t grid;
+    size_t lds;
+    hipStream_t stream;
+    const DevTissue *const *tbl;
+    const ChiItem *items;
+    uint32_t n_items;
+    uint32_t *queue;
+    int persistent, cells_per_item;
+    double dt;
+    uint32_t kstep;
+    uint32_t *n_items_dev;   // lane mode: item count in device memory, or null
+    ChiItem *retry_items;    // lane16: cells to redo at full width
+    uint32_t *retry_count;
+};
 // Table sizes (species slots, reaction slots, diffusion slots) the kernels
 // are instantiated for, for a network of S species, R reactions and ND
 // diffusing species.
 void chi_variant(int S, int R, int ND, int &SM, int &RM, int &NDM);
-hipError_t launch_chi(int mode, int SM, int RM, int NDM, int P, uint32_t grid, size_t lds,
-                      hipStream_t stream, const DevTissue *const *tbl, const ChiItem *items,
-                      uint32_t n_items, uint32_t *queue, int persistent, int cells_per_item,
-                      double dt, uint32_t kstep);
+hipError_t launch_chi(int SM, int RM, int NDM, const ChiArgs &a);
 hipError_t launch_s(uint32_t grid, hipStream_t stream, const DevTissue *const *tbl,
                     const SItem *items, uint32_t n_items, uint32_t *queue, int persistent,
                     double dt, uint32_t kstep);

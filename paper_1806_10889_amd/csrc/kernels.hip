@@ -21,11 +21,24 @@ __global__ __launch_bounds__(kWave) void chi_lane_kernel(const DevTissue *const 
                                                          const ChiItem *items, uint32_t n_items,
                                                          uint32_t *queue, int persistent,
                                                          int cells_per_item, int log2p, double dt,
-                                                         uint32_t kstep)
+                                                         uint32_t kstep, uint32_t *n_items_dev)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     chi_lane_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
-                                           cells_per_item, log2p, dt, kstep);
+                                           cells_per_item, log2p, dt, kstep, n_items_dev);
+}
+
+template <int SM, int RM, int NDM>
+__global__ __launch_bounds__(kWave) void chi_lane16_kernel(const DevTissue *const *tbl,
+                                                           const ChiItem *items, uint32_t n_items,
+                                                           uint32_t *queue, int persistent,
+                                                           int cells_per_item, double dt,
+                                                           uint32_t kstep, ChiItem *retry_items,
+                                                           uint32_t *retry_count)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    chi_lane16_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
+                                             cells_per_item, dt, kstep, retry_items, retry_count);
 }
 
 template <int SM, int RM, int NDM>
@@ -210,6 +223,7 @@ __global__ void advance_kernel(DevTissue *const *tbl, uint32_t n_tissues, uint32
 size_t chi_lds_bytes(int mode, int P, int S, int cells_per_item)
 {
     if (mode == kChiRow) return 0;  // static LDS only
+    if (mode == kChiLane16) return lane16_lds_bytes(S, cells_per_item);
     // per cell: the tree (2P doubles) and P*S counts, plus slack for the
     // species-slot reads past the last voxel
     return (size_t)cells_per_item * ((size_t)2 * P * 8 + ((size_t)P * S + kMaxSpecies) * 4);
@@ -225,18 +239,19 @@ int log2_exact(int P)
 }
 
 template <int SM, int RM, int NDM>
-hipError_t launch_variant(int mode, int P, uint32_t grid, size_t lds, hipStream_t stream,
-                          const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items,
-                          uint32_t *queue, int persistent, int cells_per_item, double dt,
-                          uint32_t kstep)
+hipError_t launch_variant(const ChiArgs &a)
 {
-    if (mode == kChiRow) {
-        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM>), dim3(grid), dim3(kWave), 0, stream, tbl,
-                           items, n_items, queue, persistent, dt, kstep);
+    if (a.mode == kChiRow) {
+        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), 0, a.stream,
+                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep);
+    } else if (a.mode == kChiLane16) {
+        hipLaunchKernelGGL((chi_lane16_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
+                           a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
+                           a.cells_per_item, a.dt, a.kstep, a.retry_items, a.retry_count);
     } else {
-        hipLaunchKernelGGL((chi_lane_kernel<SM, RM, NDM>), dim3(grid), dim3(kWave), lds, stream,
-                           tbl, items, n_items, queue, persistent, cells_per_item, log2_exact(P),
-                           dt, kstep);
+        hipLaunchKernelGGL((chi_lane_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
+                           a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
+                           a.cells_per_item, log2_exact(a.P), a.dt, a.kstep, a.n_items_dev);
     }
     return hipGetLastError();
 }
@@ -253,15 +268,10 @@ void chi_variant(int S, int R, int ND, int &SM, int &RM, int &NDM)
     if (NDM > SM) SM = NDM;
 }
 
-hipError_t launch_chi(int mode, int SM, int RM, int NDM, int P, uint32_t grid, size_t lds,
-                      hipStream_t stream, const DevTissue *const *tbl, const ChiItem *items,
-                      uint32_t n_items, uint32_t *queue, int persistent, int cells_per_item,
-                      double dt, uint32_t kstep)
+hipError_t launch_chi(int SM, int RM, int NDM, const ChiArgs &a)
 {
-#define TISSUE_VARIANT(sm, rm, nd)                                                              \
-    if (SM == sm && RM == rm && NDM == nd)                                                      \
-        return launch_variant<sm, rm, nd>(mode, P, grid, lds, stream, tbl, items, n_items, queue, \
-                                          persistent, cells_per_item, dt, kstep);
+#define TISSUE_VARIANT(sm, rm, nd) \
+    if (SM == sm && RM == rm && NDM == nd) return launch_variant<sm, rm, nd>(a);
 #define TISSUE_VARIANTS_R(sm, nd)                                                               \
     TISSUE_VARIANT(sm, 4, nd) TISSUE_VARIANT(sm, 8, nd) TISSUE_VARIANT(sm, 12, nd)              \
     TISSUE_VARIANT(sm, 16, nd)

@@ -19,7 +19,8 @@ def _oracle(oracle_lib, p, n, trace=True, **kw):
     return oracle_lib.run(p, p["dt"], n, trace=trace, **kw)
 
 
-MODES = [0, 1]  # chi kernel: one lane per cell / one 16-lane row per cell
+# chi kernel: one lane per cell / one 16-lane row per cell / compact lane16
+MODES = [0, 1, 3]
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -85,7 +86,8 @@ def test_nd4_well_mixed_square(oracle_lib, mode):
 
 
 @pytest.mark.parametrize("persistent,wpc,chunk,mode", [(0, 0, 0, 0), (1, 0, 0, 1), (1, 1, 0, 2),
-                                                       (1, 3, 2, 0), (0, 0, 3, 1), (1, 8, 5, 2)])
+                                                       (1, 3, 2, 0), (0, 0, 3, 1), (1, 8, 5, 2),
+                                                       (1, 0, 0, 3), (0, 0, 4, 3)])
 def test_launch_shapes_do_not_change_bits(oracle_lib, persistent, wpc, chunk, mode):
     p = W.random_problem(60, lattice=1, nx=11, ny=10, model="nd5", uneven=True, dt=0.05,
                          n_steps=7)
@@ -153,11 +155,13 @@ def test_batch_equals_plain_and_oracle(oracle_lib):
         assert st["steps_done"] == p["start_step"] + n
 
 
-def test_config4_sampled_tissues(oracle_lib):
+@pytest.mark.parametrize("mode", [2, 3, 0])
+def test_config4_sampled_tissues(oracle_lib, mode):
     from paper_1806_10889_amd import tissue as T
     probs = W.config4(n_tissues=40, side_hi=24, n_steps=5)
     ts = [T.Tissue(p) for p in probs]
     b = T.Batch(ts)
+    b.set_chi_mode(mode)
     b.step(probs[0]["dt"], 5)
     b.sync()
     sizes = np.array([p["nx"] for p in probs])
@@ -261,3 +265,17 @@ def test_gpu_birth_death_ensemble_law():
     m4 = float(np.sum(pmf * (np.arange(120) - mean) ** 4))
     assert abs(x.var() - var) < 3 * math.sqrt((m4 - var ** 2) / x.size)
     assert refmath.discrete_ks_pvalue(x, pmf) > 0.01
+
+
+@pytest.mark.parametrize("jit", [True, False])
+def test_lane16_redo_of_wide_counts(oracle_lib, jit):
+    """Cells whose counts reach 2^16 (during a step, or from the start) are
+    redone at full width by the follow-up launch: same bits as the oracle."""
+    p = W.random_problem(95, lattice=1, nx=9, ny=8, model="nd5", mesh=(4, 4), dt=0.05, n_steps=4)
+    x = p["init_counts"].reshape(72, 16, 5)
+    x[3, 5, 0] = 65530          # N of a voxel of cell 3 crosses 2^16 under production
+    x[17, :, 0] = 65535
+    x[40, 2, 4] = 70000         # starts above 2^16
+    p["rates"][0] = 50.0
+    o = _oracle(oracle_lib, p, 4)
+    assert_same(gpu_run(p, 4, trace=True, chi_mode=3, jit=jit), o)
