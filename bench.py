@@ -9,16 +9,18 @@ the whole horizon T (tissue_step(dt, 2000), replayed from captured HIP
 graphs).  value = (chi + S events) / wall time of the K timed steps.
 
 Also reported: the chi kernel's roofline fraction (HIP events around every
-launch of one extra, eagerly launched step; VALU-bound, see the design
-notes), the CPU FP64 oracle's rate on a bounded sample on the host cores,
-and -- unless --plain-only -- the batched form (many tissues in one graph)
-with per-simulation latency.
+launch of one extra simulation over the same horizon, launched eagerly; the
+kernel is bound by vector ALU issue, 432 lane-operations per event), the CPU
+FP64 oracle's rate on a bounded sample on the host cores, the batched form
+(512 tissues in one batch, with its own roofline) and the serving loop
+(Poisson arrivals, continuous batching, p50/p99 latency).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--leg all|plain|batched|serving]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -37,6 +39,48 @@ OPS_PER_CHI_EVENT = 432
 OPS_PER_S_EVENT = 289
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+# HBM traffic of the dominant chi kernel per launch, from rocprofv3 counter
+# runs of this script's legs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch),
+# each scaled by what the counter reads for a plain 256 MiB device copy
+# (FETCH_SIZE 131087 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  The
+# figures hold for the kernel sources whose digest is recorded with them; any
+# change to those sources makes `traffic` null until the counters are taken
+# again.
+FETCH_SCALE = 262144.0 / 131087.0
+WRITE_SCALE = 262144.0 / 262144.0
+TRAFFIC = {   # leg -> counters of its dominant chi kernel
+    # hex 64x64 tissue, 4096 cells x 4x4 voxels: 400 dispatches of 200-step runs
+    "plain": {"digest": "3f0855f46b97c3846663a30906f5722117bc5b65", "kernel": "tissue_chi_row",
+              "fetch_kib": 936.51, "write_kib": 1344.0},
+    # 512 tissues, 3.12M cells, 20 steps: 60 dispatches
+    "batched": {"digest": "3f0855f46b97c3846663a30906f5722117bc5b65", "kernel": "tissue_chi_lane16",
+                "fetch_kib": 508703.0, "write_kib": 978937.0},
+}
+
+
+def kernel_source_digest() -> str:
+    """SHA-1 over the library's device and launch sources (csrc/)."""
+    d = os.path.join(ROOT, "paper_1806_10889_amd", "csrc")
+    h = hashlib.sha1()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(leg: str, kernel: str):
+    rec = TRAFFIC.get(leg)
+    if not rec or rec["kernel"] != kernel or rec["digest"] != kernel_source_digest():
+        return None
+    return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
+
+
+def chi_kernel_name(mode: int, jit: bool) -> str:
+    base = {0: "lane", 1: "row", 3: "lane16"}.get(mode, "unknown")
+    return f"tissue_chi_{base}" if jit else f"chi_{base}_kernel"
 
 
 def log(msg):
@@ -89,20 +133,20 @@ def run_plain(args, torch, T, W):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    # roofline pass: one more simulation, every kernel bracketed by HIP events
+    # roofline pass: one more simulation over the same horizon, launched
+    # eagerly with every kernel bracketed by HIP events on the tissue's stream
     t.restart(sim_id=args.steps + 7, start_step=0)
-    tm = t.step_timed(dt, min(n, args.roofline_steps))
+    tm = t.step_timed(dt, min(n, args.roofline_steps) if args.roofline_steps > 0 else n)
     st = t.stats()
     chi_per_launch = st["chi_events"] / max(tm["chi_launches"], 1)
     chi_avg_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
     s_avg_ms = tm["s_ms"] / max(tm["s_launches"], 1)
     achieved = chi_per_launch * OPS_PER_CHI_EVENT / (chi_avg_ms * 1e-3)
+    kernel = chi_kernel_name(tm["chi_kernel"], bool(st["jit"]))
     roof = {
-        "bound": "alu",
-        "kernel": ("tissue_chi_" if t.stats()["jit"] else "chi_kernel_") +
-                  ("lane" if tuned and tuned["config"]["chi_mode"] == 0 else "row"),
+        "bound": "alu", "kernel": kernel,
         "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-        "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+        "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_bytes("plain", kernel),
         "avg_launch_ms": chi_avg_ms, "events_per_launch": chi_per_launch,
         "ops_per_event": OPS_PER_CHI_EVENT, "s_kernel_avg_ms": s_avg_ms,
         "chi_share_of_kernel_time": tm["chi_ms"] / max(tm["chi_ms"] + tm["s_ms"], 1e-12),
@@ -146,17 +190,19 @@ def run_batched(args, torch, T, W):
     cells = sum(p["nx"] * p["ny"] for p in probs)
     out = dict(events_per_s=tot_ev / tot_t, tissues=len(probs), cells=cells, steps=n, dt=dt,
                sweep_ms_p50=pct(walls, 50) * 1e3, sweep_ms_p99=pct(walls, 99) * 1e3)
-    # roofline of the batched chi kernel: HIP events around each launch of
-    # two eagerly launched steps
+    # roofline of the batched chi kernel: the same sweep once more, launched
+    # eagerly with HIP events around each launch
     for i, t in enumerate(ts):
         t.restart(sim_id=i + 777, start_step=0)
-    tm = b.step_timed(dt, 2)
+    tm = b.step_timed(dt, n)
     chi_ev = sum(t.stats()["chi_events"] for t in ts)
     per_launch_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
     achieved = chi_ev / max(tm["chi_launches"], 1) * OPS_PER_CHI_EVENT / (per_launch_ms * 1e-3)
-    out["roofline"] = {"bound": "alu", "kernel": "tissue_chi_lane", "achieved": achieved / 1e12,
+    kernel = chi_kernel_name(tm["chi_kernel"], bool(ts[0].stats()["jit"]))
+    out["roofline"] = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
                        "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-                       "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                       "frac": achieved / PEAK_LANE_OPS,
+                       "traffic": traffic_bytes("batched", kernel),
                        "avg_launch_ms": per_launch_ms,
                        "events_per_launch": chi_ev / max(tm["chi_launches"], 1),
                        "ops_per_event": OPS_PER_CHI_EVENT}
@@ -213,12 +259,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-steps", type=int, default=2000, help="splitting steps per simulation")
     ap.add_argument("--graph-chunk", type=int, default=50)
-    ap.add_argument("--roofline-steps", type=int, default=200)
-    ap.add_argument("--plain-only", action="store_true")
+    ap.add_argument("--roofline-steps", type=int, default=0,
+                    help="steps of the eagerly timed roofline pass (0: the whole horizon)")
+    ap.add_argument("--leg", choices=["all", "plain", "batched", "serving"], default="all",
+                    help="run one leg only (profiling runs); the JSON line then carries that leg")
+    ap.add_argument("--plain-only", action="store_true", help="same as --leg plain")
     ap.add_argument("--batch-tissues", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-reps", type=int, default=1)
-    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=1200)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="fixed launch shape instead of the autotuner")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -232,8 +281,8 @@ def main():
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures "
-              "the single-GPU hot path; multi-GPU sharding is a design note, not a run.",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the simulation "
+              "path is single-GPU; sharding tissues over several GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -251,30 +300,34 @@ def main():
     from paper_1806_10889_amd import tissue as T
     from paper_1806_10889_amd import workloads as W
 
-    plain = run_plain(args, torch, T, W)
-    out = {
-        "metric": METRIC, "value": plain["value"], "unit": "events/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": plain["elapsed"] / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "hex 64x64 tissue, 4096 cells x 4x4 voxels, 5 species, "
-                               "9+1 reactions, D=1.0, dt=0.05, T=100 (2000 splitting steps)",
-                   "cells": 4096, "voxels_per_cell": 16, "species": 5, "dt": 0.05,
-                   "T": 0.05 * args.n_steps, "splitting_steps": args.n_steps,
-                   "launch": (plain["tuned"] or {}).get("config",
-                                                         f"persistent, graph chunk {args.graph_chunk}"),
-                   "network_kernels": "compiled per network" if plain["jit"] else "generic"},
-        "plain": {"events_per_s": plain["value"], "chi_events": plain["chi"], "s_events": plain["s"],
-                  "sim_latency_ms_p50": pct(plain["lat"], 50) * 1e3,
-                  "sim_latency_ms_p99": pct(plain["lat"], 99) * 1e3},
-        "roofline": plain["roofline"],
-    }
-    if not args.plain_only:
+    leg = "plain" if args.plain_only else args.leg
+    out = {"metric": METRIC, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    if leg != "all":
+        out["leg"] = leg
+    if leg in ("all", "plain"):
+        plain = run_plain(args, torch, T, W)
+        out.update({
+            "value": plain["value"], "ms_per_step": plain["elapsed"] / args.steps * 1e3,
+            "config": {"workload": "hex 64x64 tissue, 4096 cells x 4x4 voxels, 5 species, "
+                                   "9+1 reactions, D=1.0, dt=0.05, T=100 (2000 splitting steps)",
+                       "cells": 4096, "voxels_per_cell": 16, "species": 5, "dt": 0.05,
+                       "T": 0.05 * args.n_steps, "splitting_steps": args.n_steps,
+                       "launch": (plain["tuned"] or {}).get(
+                           "config", f"persistent, graph chunk {args.graph_chunk}"),
+                       "network_kernels": "compiled per network" if plain["jit"] else "generic"},
+            "plain": {"events_per_s": plain["value"], "chi_events": plain["chi"],
+                      "s_events": plain["s"],
+                      "sim_latency_ms_p50": pct(plain["lat"], 50) * 1e3,
+                      "sim_latency_ms_p99": pct(plain["lat"], 99) * 1e3},
+            "roofline": plain["roofline"],
+        })
+    if leg in ("all", "batched"):
         out["batched"] = run_batched(args, torch, T, W)
-        if not args.no_serve:
-            out["serving"] = run_serving(args, torch)
-    if not args.no_cpu_baseline:
+    if leg == "serving" or (leg == "all" and not args.no_serve):
+        out["serving"] = run_serving(args, torch)
+    if leg == "all" and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, W, plain["p"])
     print(json.dumps(out), flush=True)
 

@@ -177,20 +177,29 @@ int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in);
  * Results are bit-identical for every choice. */
 int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu);
 
-/* Kernel of the chi operator: 0 = one lane per cell (all cells), 1 = one
- * 16-lane row per cell (cells of at most 16 voxels; larger cells keep one
- * lane each), 2 = automatic (the default: rows for a leaf-count class when
- * one lane per cell would leave SIMDs without a wavefront).  Results are
- * bit-identical for every choice. */
+/* Kernel of the chi operator.  0 = one lane per cell with the full sum tree
+ * and 32-bit counts in LDS (every cell); 1 = one 16-lane row per cell;
+ * 3 = one lane per cell with the compact layout (16 FP64 leaves, 16-bit
+ * counts, upper tree levels rebuilt in registers), cells that reach 2^16
+ * molecules of a species handed to a full-width lane launch that redoes
+ * their step; 2 = automatic (the default): for cells of at most 16 voxels,
+ * rows when the leaf-count class has fewer cells than 64 per SIMD of the
+ * device, else the compact layout.  Modes 1 and 3 apply to cells of at most
+ * 16 voxels; larger cells always take mode 0.  Results are bit-identical
+ * for every choice.  Other values: TISSUE_EINVAL. */
 int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 
 /* Steps captured per HIP graph launch (0 disables graphs). */
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
 
-/* Per-kernel device time of the last tissue_step_timed call, in ms. */
+/* Per-kernel device time of the last tissue_step_timed call, in ms.
+ * chi_ms brackets each chi launch (for mode 3 with its redo launch);
+ * chi_kernel is the mode (0, 1 or 3, as in tissue_set_chi_mode) of the chi
+ * launch group that took the most time. */
 typedef struct {
     double chi_ms, s_ms, total_ms;
     uint32_t chi_launches, s_launches;
+    int32_t chi_kernel;
 } tissue_timing_t;
 
 /* tissue_step, launched eagerly with a HIP event pair around every kernel;

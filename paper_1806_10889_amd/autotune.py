@@ -1,6 +1,7 @@
 """Autotuner of the launch shape.
 
-The launch shape -- chi kernel (one lane per cell / one 16-lane row per
+The launch shape -- chi kernel (one lane per cell with a full sum tree, one
+lane per cell with the compact 16-leaf layout, or one 16-lane row per
 cell), persistent work queue or one workgroup per item, resident workgroups
 per CU, steps per captured HIP graph -- never changes results (every choice
 is bit-identical), only speed.  `tune` times candidate shapes on a clone of
@@ -37,7 +38,7 @@ def signature(problems) -> str:
 
 def candidates(max_voxels: int):
     out = []
-    modes = [0, 1] if max_voxels <= 16 else [0]
+    modes = [0, 1, 3] if max_voxels <= 16 else [0]
     for mode in modes:
         for persistent, wpc in [(1, 0), (0, 0), (1, 2), (1, 8)]:
             for chunk in (25, 100):

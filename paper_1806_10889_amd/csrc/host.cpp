@@ -613,7 +613,8 @@ struct LaunchPlan {
     }
 
     // Enqueue n steps (k = 0..n-1) then step_base += n.  With events
-    // (2 per launch, in launch order) each kernel is bracketed.
+    // (2 per launch, in launch order) each kernel is bracketed; kind gets the
+    // chi launch's index in `chi`, or -1 for an S launch.
     int enqueue(hipStream_t st, double dt, int32_t n, std::vector<hipEvent_t> *ev = nullptr,
                 std::vector<int> *kind = nullptr)
     {
@@ -625,7 +626,7 @@ struct LaunchPlan {
                 HIP_TRY(launch_chi_any(L, chi_grid(L), st, dt, (uint32_t)k));
                 if (ev) {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
-                    kind->push_back(0);
+                    kind->push_back((int)(&L - chi.data()));
                 }
             }
             for (const SLaunch &L : s) {
@@ -635,7 +636,7 @@ struct LaunchPlan {
                                  (uint32_t)k));
                 if (ev) {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
-                    kind->push_back(1);
+                    kind->push_back(-1);
                 }
             }
         }
@@ -717,16 +718,26 @@ struct LaunchPlan {
         HIP_TRY(hipEventRecord(t1, stream));
         HIP_TRY(hipEventSynchronize(t1));
         tissue_timing_t T{};
+        std::vector<double> per_group(chi.size(), 0.0);
         for (size_t q = 0; q < kind.size(); ++q) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
-            if (kind[q] == 0) {
+            if (kind[q] >= 0) {
                 T.chi_ms += ms;
                 T.chi_launches++;
+                per_group[(size_t)kind[q]] += ms;
             } else {
                 T.s_ms += ms;
                 T.s_launches++;
             }
+        }
+        T.chi_kernel = -1;
+        double longest = -1.0;
+        for (size_t g = 0; g < chi.size(); ++g) {
+            if (chi[g].n_items == 0 || per_group[g] <= longest) continue;
+            longest = per_group[g];
+            T.chi_kernel = chi[g].mode == kChiRow ? kModeRow
+                         : chi[g].mode == kChiLane16 ? kModeLane16 : kModeLane;
         }
         float tot = 0.f;
         HIP_TRY(hipEventElapsedTime(&tot, t0, t1));

@@ -279,3 +279,22 @@ def test_lane16_redo_of_wide_counts(oracle_lib, jit):
     p["rates"][0] = 50.0
     o = _oracle(oracle_lib, p, 4)
     assert_same(gpu_run(p, 4, trace=True, chi_mode=3, jit=jit), o)
+
+
+@pytest.mark.parametrize("mode,expect", [(0, 0), (1, 1), (3, 3), (2, 1)])
+def test_step_timed_same_bits_and_reports_kernel(oracle_lib, mode, expect):
+    """The eagerly launched, event-bracketed steps give the oracle's bits, one
+    chi launch and the same S passes per step, and name the chi layout that ran (auto
+    takes rows for a tissue with fewer cells than 64 per SIMD)."""
+    from paper_1806_10889_amd import tissue as T
+    p = W.config2(side=9, n_steps=7)
+    o = _oracle(oracle_lib, p, 7, trace=False)
+    t = T.Tissue(p)
+    t.set_chi_mode(mode)
+    tm = t.step_timed(p["dt"], 7)
+    g = dict(counts=t.read_counts(), stats=t.stats())
+    t.close()
+    assert_same(g, o, trace=False)
+    assert tm["chi_kernel"] == expect
+    assert tm["chi_launches"] == 7 and tm["s_launches"] >= 7 and tm["s_launches"] % 7 == 0
+    assert 0 < tm["chi_ms"] <= tm["total_ms"] and 0 < tm["s_ms"] <= tm["total_ms"]
