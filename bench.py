@@ -96,8 +96,10 @@ def pct(a, q):
     return a[lo] + (a[hi] - a[lo]) * (k - lo)
 
 
-def run_plain(args, torch, T, W):
-    p = W.config2(n_steps=args.n_steps)
+def run_single(args, torch, T, p, leg, sims, warmup):
+    """One resident tissue: `sims` timed simulations over the problem's whole
+    horizon (restart with a new sim_id, then tissue_step), after `warmup`
+    untimed ones; then the eager roofline pass."""
     stream = torch.cuda.current_stream()
     t = T.Tissue(p, device="cuda:0", stream=stream)
     dt, n = p["dt"], p["n_steps"]
@@ -107,7 +109,7 @@ def run_plain(args, torch, T, W):
         tuned = None
     else:
         from paper_1806_10889_amd import autotune
-        tuned = autotune.tune([p], dt, steps=50, reps=2, target=t, log=log)
+        tuned = autotune.tune([p], dt, steps=min(50, n), reps=2, target=t, log=log)
         log(f"autotuned launch: {tuned['config']}")
 
     def one(k):
@@ -116,26 +118,26 @@ def run_plain(args, torch, T, W):
         st = t.stats()  # synchronises the stream
         return st["chi_events"] + st["s_events"], st
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         one(1000 + w)
-        log(f"warmup {w + 1}/{args.warmup} done")
+        log(f"{leg}: warmup {w + 1}/{warmup} done")
     torch.cuda.synchronize()
     lat, events, chi_ev, s_ev = [], 0, 0, 0
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(sims):
         a = time.perf_counter()
         ev, st = one(k)
         lat.append(time.perf_counter() - a)
         events += ev
         chi_ev += st["chi_events"]
         s_ev += st["s_events"]
-        log(f"step {k + 1}/{args.steps}: {ev} events in {lat[-1] * 1e3:.1f} ms")
+        log(f"{leg}: simulation {k + 1}/{sims}: {ev} events in {lat[-1] * 1e3:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
     # roofline pass: one more simulation over the same horizon, launched
     # eagerly with every kernel bracketed by HIP events on the tissue's stream
-    t.restart(sim_id=args.steps + 7, start_step=0)
+    t.restart(sim_id=sims + 7, start_step=0)
     tm = t.step_timed(dt, min(n, args.roofline_steps) if args.roofline_steps > 0 else n)
     st = t.stats()
     chi_per_launch = st["chi_events"] / max(tm["chi_launches"], 1)
@@ -146,7 +148,7 @@ def run_plain(args, torch, T, W):
     roof = {
         "bound": "alu", "kernel": kernel,
         "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-        "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_bytes("plain", kernel),
+        "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_bytes(leg, kernel),
         "avg_launch_ms": chi_avg_ms, "events_per_launch": chi_per_launch,
         "ops_per_event": OPS_PER_CHI_EVENT, "s_kernel_avg_ms": s_avg_ms,
         "chi_share_of_kernel_time": tm["chi_ms"] / max(tm["chi_ms"] + tm["s_ms"], 1e-12),
@@ -179,7 +181,11 @@ def run_batched(args, torch, T, W):
             ev += st["chi_events"] + st["s_events"]
         return ev, wall
 
-    one(99)
+    # warm-up: network compilation and the graph capture of one chunk
+    for i, t in enumerate(ts):
+        t.restart(sim_id=i + 99000, start_step=0)
+    b.step(dt, min(n, 50))
+    b.sync()
     tot_ev, tot_t, walls = 0, 0.0, []
     for k in range(max(1, args.batch_reps)):
         ev, wall = one(k)
@@ -261,17 +267,19 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--roofline-steps", type=int, default=0,
                     help="steps of the eagerly timed roofline pass (0: the whole horizon)")
-    ap.add_argument("--leg", choices=["all", "plain", "batched", "serving"], default="all",
+    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving"], default="all",
                     help="run one leg only (profiling runs); the JSON line then carries that leg")
     ap.add_argument("--plain-only", action="store_true", help="same as --leg plain")
     ap.add_argument("--batch-tissues", type=int, default=512)
-    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--batch-reps", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=1200)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="fixed launch shape instead of the autotuner")
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--uneven-steps", type=int, default=1000)
+    ap.add_argument("--uneven-sims", type=int, default=1)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-quantum", type=int, default=10)
     ap.add_argument("--serve-slots", type=int, default=4096)
@@ -307,7 +315,8 @@ def main():
     if leg != "all":
         out["leg"] = leg
     if leg in ("all", "plain"):
-        plain = run_plain(args, torch, T, W)
+        plain = run_single(args, torch, T, W.config2(n_steps=args.n_steps), "plain",
+                           args.steps, args.warmup)
         out.update({
             "value": plain["value"], "ms_per_step": plain["elapsed"] / args.steps * 1e3,
             "config": {"workload": "hex 64x64 tissue, 4096 cells x 4x4 voxels, 5 species, "
@@ -323,6 +332,16 @@ def main():
                       "sim_latency_ms_p99": pct(plain["lat"], 99) * 1e3},
             "roofline": plain["roofline"],
         })
+    if leg in ("all", "uneven"):
+        p3 = W.config3(n_steps=args.uneven_steps)
+        u = run_single(args, torch, T, p3, "uneven", args.uneven_sims, 1)
+        out["uneven"] = {
+            "workload": "hex 256x256 tissue, 65536 cells, V ~ lognormal(median 16, sigma 0.5) "
+                        "in [4, 64], 5 species, dt=0.05, T=50 (1000 splitting steps)",
+            "cells": 65536, "voxels": int(W.n_voxels(p3)), "splitting_steps": args.uneven_steps,
+            "events_per_s": u["value"], "chi_events": u["chi"], "s_events": u["s"],
+            "sim_latency_ms_p50": pct(u["lat"], 50) * 1e3,
+            "launch": (u["tuned"] or {}).get("config"), "roofline": u["roofline"]}
     if leg in ("all", "batched"):
         out["batched"] = run_batched(args, torch, T, W)
     if leg == "serving" or (leg == "all" and not args.no_serve):

@@ -38,7 +38,9 @@ def signature(problems) -> str:
 
 def candidates(max_voxels: int):
     out = []
-    modes = [0, 1, 3] if max_voxels <= 16 else [0]
+    # rows and the compact layout apply to cells of at most 16 voxels (larger
+    # cells keep the full lane layout); auto mixes them per leaf-count class
+    modes = [0, 1, 3, 2] if max_voxels <= 16 else [0, 2, 1, 3]
     for mode in modes:
         for persistent, wpc in [(1, 0), (0, 0), (1, 2), (1, 8)]:
             for chunk in (25, 100):

@@ -83,6 +83,7 @@ __device__ __forceinline__ uint64_t uni(uint64_t v)
 
 // A network policy supplies the channel structure of the chi kernels:
 //   SM, RM, NDM   species slots, reaction slots, diffusion slots;
+//   kFixedSpecies true when every tissue using it has exactly SM species;
 //   ra(r), rb(r)  reactants of reaction r (-1: none), dsp(q) species of
 //                 diffusion channel q, delta(r, s) net change;
 //   rate[r], drate[q] the tissue's constants (runtime, wave-uniform);
@@ -95,6 +96,7 @@ __device__ __forceinline__ uint64_t uni(uint64_t v)
 template <int SM_, int RM_, int NDM_>
 struct NetGeneric {
     static constexpr int SM = SM_, RM = RM_, NDM = NDM_;
+    static constexpr bool kFixedSpecies = false;  // the tissue's species count is <= SM
     int ra_[RM], rb_[RM];
     uint32_t dlo_[RM], dhi_[RM];
     int dsp_[NDM > 0 ? NDM : 1];
@@ -156,56 +158,155 @@ __device__ __forceinline__ double voxel_fold(const NET &n, const double *xd, dou
 // and r < prefix through k, else the last channel with a_k > 0.  Prefixes
 // never decrease and a zero channel repeats its predecessor's prefix, so
 // the first channel with r < prefix_k always has a_k > 0, and its index is
-// the number of channels whose prefix is <= r; the prefix before it is the
-// largest prefix <= r.  Counting and selecting (no branches) gives the same
-// channel as the sequential rule.  Returns the channel slot (reactions
-// 0..RM-1, diffusion RM + q), the residual r minus the prefix before it, and
-// for diffusion D_s x_s and s.
+// the number of channels whose prefix is <= r.  Only a diffusion channel
+// needs its residual (r minus the prefix before it) and a1 = D_s x_s, so
+// those are tracked over the diffusion channels alone: channel k is the one
+// selected exactly when r >= prefix_{k-1} and r < prefix_k.  When r is at or
+// past the voxel's total (possible only through the rounding of the descent)
+// a second, rarely taken pass finds the last positive channel.  Returns the
+// channel slot (reactions 0..RM-1, diffusion RM + q), or the slot count when
+// the voxel has no positive channel.
 template <class NET>
 __device__ __forceinline__ int voxel_select(const NET &n, const double *xd, double degd, double r,
-                                            double &resid, double &a1, int &spec)
+                                            double &resid, double &a1)
 {
-    constexpr int RM = NET::RM, NDM = NET::NDM;
-    double acc = 0.0, before = 0.0, last_before = 0.0;
-    int below = 0, last = -1;
+    constexpr int RM = NET::RM, NDM = NET::NDM, NC = RM + NDM;
+    double acc = 0.0, before = 0.0;
+    int below = 0;
+    bool under_prev = true;
+    a1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < RM + NDM; ++k) {
+    for (int k = 0; k < NC; ++k) {
         const double a = k < RM ? reaction_prop(n, k, xd)
                                 : n.drate[k - RM] * (xd[n.dsp(k - RM)] * degd);
         const double next = acc + a;
         const bool under = r >= next;
         below += under ? 1 : 0;
-        before = under ? next : before;
-        const bool pos = a > 0.0;
-        last = pos ? k : last;
-        last_before = pos ? acc : last_before;
+        if (k >= RM) a1 = under_prev ? n.drate[k - RM] * xd[n.dsp(k - RM)] : a1;
+        if (k >= RM - 1) before = under ? next : before;
+        under_prev = under;
         acc = next;
     }
     int sel = below;
-    if (sel >= RM + NDM) {
-        sel = last;
-        before = last_before;
+    if (__builtin_expect(sel >= NC, 0)) {
+        double acc2 = 0.0;
+        sel = NC;
+        before = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const double a = k < RM ? reaction_prop(n, k, xd)
+                                    : n.drate[k - RM] * (xd[n.dsp(k - RM)] * degd);
+            if (a > 0.0) {
+                sel = k;
+                before = acc2;
+                a1 = k < RM ? 0.0 : n.drate[k - RM] * xd[n.dsp(k - RM)];
+            }
+            acc2 = acc2 + a;
+        }
     }
     resid = r - before;
-    a1 = 0.0;
-    spec = 0;
-#pragma unroll
-    for (int q = 0; q < NDM; ++q) {
-        const bool is_q = sel == RM + q;
-        a1 = is_q ? n.drate[q] * xd[n.dsp(q)] : a1;
-        spec = is_q ? n.dsp(q) : spec;
-    }
     return sel;
 }
 
-// Net change of species s by reaction slot sel (a per-lane index).
+// The fold of voxel_fold keeping, for the row kernel, every channel's
+// prefix (pre[k] = the fold through channel k) and every diffusion channel's
+// a1 = D_s x_s, so that a later selection on this voxel needs no products.
 template <class NET>
-__device__ __forceinline__ int reaction_delta(const NET &n, int sel, int s)
+__device__ __forceinline__ double voxel_fold_cached(const NET &n, const double *xd, double degd,
+                                                    double *pre, double *ad)
 {
-    int d = 0;
+    double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < NET::RM; ++k) d += (k == sel) ? n.delta(k, s) : 0;
-    return d;
+    for (int r = 0; r < NET::RM; ++r) {
+        acc = acc + reaction_prop(n, r, xd);
+        pre[r] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < NET::NDM; ++q) {
+        acc = acc + n.drate[q] * (xd[n.dsp(q)] * degd);
+        pre[NET::RM + q] = acc;
+        ad[q] = n.drate[q] * xd[n.dsp(q)];
+    }
+    return acc;
+}
+
+// voxel_select from the cached prefixes (same channel, residual and a1).
+// Only lanes with `need` get a correct result when r is at or past the
+// total (the others skip the second pass, whose cost the whole wave pays).
+template <class NET>
+__device__ __forceinline__ int voxel_select_cached(const NET &n, const double *pre, const double *ad,
+                                                   const double *xd, double degd, double r, bool need,
+                                                   double &resid, double &a1)
+{
+    constexpr int RM = NET::RM, NDM = NET::NDM, NC = RM + NDM;
+    double before = 0.0;
+    int below = 0;
+    bool under_prev = true;
+    a1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const bool under = r >= pre[k];
+        below += under ? 1 : 0;
+        if (k >= RM) a1 = under_prev ? ad[k - RM] : a1;
+        if (k >= RM - 1) before = under ? pre[k] : before;
+        under_prev = under;
+    }
+    if (__builtin_expect(need && below >= NC, 0)) return voxel_select(n, xd, degd, r, resid, a1);
+    resid = r - before;
+    return below;
+}
+
+// The channel table of a work item's network, in LDS: per channel slot the
+// net change of every species as signed bytes (species 0..3 in lo, 4..7 in
+// hi) and, for a diffusion channel, its species (else -1).  Slot RM + NDM is
+// all zero (no positive channel: no change).
+struct ChanEntry {
+    uint32_t lo, hi;
+    int32_t spec, pad;
+};
+constexpr int kChanSlots = kMaxReactions + kMaxSpecies + 1;
+
+template <class NET>
+__device__ __forceinline__ void load_channel_table(ChanEntry *tab, const DevModel &M)
+{
+    constexpr int RM = NET::RM, NDM = NET::NDM;
+    const int k = threadIdx.x;
+    if (k <= RM + NDM) {
+        ChanEntry e{0u, 0u, -1, 0};
+        if (k < RM) {
+            e.lo = M.delta_lo[k];
+            e.hi = M.delta_hi[k];
+        } else if (k < RM + NDM && k - RM < M.n_diff) {
+            const int sp = M.diff_species[k - RM];
+            e.spec = sp;
+            if (sp < 4) e.lo = 0xFFu << (8 * sp);
+            else e.hi = 0xFFu << (8 * (sp - 4));
+        }
+        tab[k] = e;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Whether any of the first S counts (held as doubles) left [0, limit).
+template <int SM>
+__device__ __forceinline__ bool out_of_range(const double *xd, int S, double limit)
+{
+    double mx = xd[0], mn = xd[0];
+#pragma unroll
+    for (int q = 1; q < SM; ++q) {
+        if (q < S) {
+            mx = __builtin_fmax(mx, xd[q]);
+            mn = __builtin_fmin(mn, xd[q]);
+        }
+    }
+    return (mn < 0.0) | (mx >= limit);
+}
+
+// Net change of species q in a table entry.
+__device__ __forceinline__ double entry_delta(const ChanEntry &e, int q)
+{
+    const uint32_t w = q < 4 ? e.lo : e.hi;
+    return (double)(int)(int8_t)((w >> (8 * (q & 3))) & 0xFFu);
 }
 
 // The value unchanged, but opaque to the optimiser (an empty asm with a
@@ -318,7 +419,8 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                                               int persistent, int cells_per_item, int log2p, double dt,
                                               uint32_t kstep, uint32_t *n_items_dev)
 {
-    constexpr int SM = NET::SM, RM = NET::RM;
+    constexpr int SM = NET::SM;
+    __shared__ ChanEntry tab[kChanSlots];
     if (n_items_dev) n_items = uni(*(volatile uint32_t *)n_items_dev);
     const int lane = threadIdx.x;
     const int stride = cells_per_item;
@@ -331,7 +433,8 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
         const ItemCtx c = item_ctx(tbl, item, kstep);
         NET net;
         net.load(c.T->model);
-        const int S = c.S;
+        load_channel_table<NET>(tab, c.T->model);
+        const int S = NET::kFixedSpecies ? NET::SM : c.S;
         double *tree = reinterpret_cast<double *>(lds) + lane;  // [2P][stride]
         int32_t *cnt = reinterpret_cast<int32_t *>(lds + (size_t)2 * P * stride * 8) + lane;
 
@@ -419,26 +522,20 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                 for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
                 const int deg = voxel_degree(go, v);
                 double resid, a1;
-                int spec;
-                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1, spec);
-                int dst = v;
-                if (sel < RM) {
+                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
+                const ChanEntry e = tab[sel];
 #pragma unroll
-                    for (int q = 0; q < SM; ++q) {
-                        const int d = reaction_delta(net, sel, q);
-                        if (q < S && d != 0) {
-                            xd[q] += (double)d;
-                            x[q * stride] = (int32_t)xd[q];
-                            overflow |= (xd[q] < 0.0) | (xd[q] >= (double)kCountLimit);
-                        }
+                for (int q = 0; q < SM; ++q) {
+                    if (q < S) {
+                        xd[q] += entry_delta(e, q);
+                        x[q * stride] = (int32_t)xd[q];
                     }
-                } else {
+                }
+                overflow |= out_of_range<SM>(xd, S, (double)kCountLimit);
+                int dst = v;
+                if (e.spec >= 0) {
                     dst = neighbour_at(go, v, jump_direction(resid, a1, deg));
-#pragma unroll
-                    for (int q = 0; q < SM; ++q)
-                        if (q == spec) xd[q] -= 1.0;
-                    x[spec * stride] -= 1;
-                    int32_t *xdst = cnt + (dst * S + spec) * stride;
+                    int32_t *xdst = cnt + (dst * S + e.spec) * stride;
                     const int32_t nd = *xdst + 1;
                     *xdst = nd;
                     overflow |= nd >= kCountLimit;
@@ -524,10 +621,12 @@ __device__ __forceinline__ void descent_level(double own, double sib, int bit, d
 
 }  // namespace
 
-// LDS of the row kernel: per lane one pre-drawn (-plog(U1), U2) pair.
+// LDS of the row kernel: per lane one pre-drawn (-plog(U1), U2) pair, and
+// the channel table.
 struct RowShared {
     double rng_e[kWave];
     double rng_u[kWave];
+    ChanEntry chan[kChanSlots];
 };
 
 template <class NET>
@@ -535,7 +634,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                                              const ChiItem *items, uint32_t n_items, uint32_t *queue,
                                              int persistent, double dt, uint32_t kstep)
 {
-    constexpr int SM = NET::SM, RM = NET::RM;
+    constexpr int SM = NET::SM;
+    ChanEntry *tab = sh.chan;
     double *rng_e = sh.rng_e;
     double *rng_u = sh.rng_u;
     const int lane = threadIdx.x, row = lane >> 4, lv = lane & 15;
@@ -547,7 +647,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         const ItemCtx c = item_ctx(tbl, item, kstep);
         NET net;
         net.load(c.T->model);
-        const int S = c.S;
+        load_channel_table<NET>(tab, c.T->model);
+        const int S = NET::kFixedSpecies ? NET::SM : c.S;
 
         const bool has_cell = row < (int)c.count;
         uint32_t cell = 0;
@@ -566,7 +667,19 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         for (int q = 0; q < SM; ++q) xd[q] = (vox && q < S) ? (double)c.counts[vbase + q] : 0.0;
         const int deg = vox ? voxel_degree(g, lv) : 0;
         const double degd = (double)deg;
-        double leaf = vox ? voxel_fold(net, xd, degd) : 0.0;
+        // cached with the leaf: the channel prefixes and D_s x_s
+        double pre[NET::RM + NET::NDM], ad[NET::NDM > 0 ? NET::NDM : 1];
+        double leaf = voxel_fold_cached(net, xd, degd, pre, ad);
+        if (!vox) leaf = 0.0;  // (a production channel is positive even at zero counts)
+        // the lane's present neighbours in jump order (-x, +x, -y, +y), and
+        // the jump thresholds' multipliers l for l = 1..3 (+inf past deg - 1,
+        // so that the comparison fails as the rule's range ends)
+        int nb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nb[k] = vox ? neighbour_at(g, lv, k < deg ? k : 0) : lv;
+        double thr[3];
+#pragma unroll
+        for (int l = 1; l <= 3; ++l) thr[l - 1] = l <= deg - 1 ? (double)l : __builtin_inf();
 
         double t = 0.0;
         uint32_t j = 0, ev = 0;
@@ -630,45 +743,36 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             descent_level(leaf, p0, lvo & 1, rr, on);
             on = on && event;
 
-            bool changed = false;
-            uint32_t word = 0;
-            if (on) {
-                double resid, a1;
-                int spec;
-                const int sel = voxel_select(net, xd, degd, rr, resid, a1, spec);
-                if (sel < RM) {
+            // every lane evaluates the selection on its own voxel (from the
+            // prefixes cached by its last fold); only the lane the descent
+            // reached applies it
+            double resid, a1;
+            int sel = voxel_select_cached(net, pre, ad, xd, degd, rr, on, resid, a1);
+            sel = sel < NET::RM + NET::NDM ? sel : NET::RM + NET::NDM;
+            const ChanEntry e = tab[sel];
+            int kdir = 0;
 #pragma unroll
-                    for (int q = 0; q < SM; ++q) {
-                        xd[q] += (double)reaction_delta(net, sel, q);
-                        overflow |= (xd[q] < 0.0) | (xd[q] >= (double)kCountLimit);
-                    }
-                } else {
-                    Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
-                    const int dst = neighbour_at(go, lvo, jump_direction(resid, a1, opaque(deg)));
+            for (int l = 0; l < 3; ++l) kdir += resid >= thr[l] * a1 ? 1 : 0;
+            int dst = nb[0];
 #pragma unroll
-                    for (int q = 0; q < SM; ++q)
-                        if (q == spec) xd[q] -= 1.0;
-                    word = 1u | ((uint32_t)spec << 4) | ((uint32_t)dst << 8);
-                }
-                changed = true;
-            }
+            for (int k = 1; k < 4; ++k) dst = kdir == k ? nb[k] : dst;
+            uint32_t word = (on && e.spec >= 0) ? (1u | ((uint32_t)e.spec << 4) | ((uint32_t)dst << 8)) : 0u;
             // the row's diffusion word reaches every lane of the row (it is
             // zero outside the selected lane): OR over the 16-lane row
             word = row_or(word);
-            if (event) {
-                if ((word & 1u) && (int)(word >> 8) == lvo) {
-                    const int spec = (int)((word >> 4) & 15u);
+            const bool recv = event && (word & 1u) && (int)(word >> 8) == lvo;
+            const uint32_t rs = (word >> 4) & 15u;
+            const uint32_t inc = recv ? (1u << (8u * (rs & 3u))) : 0u;
+            // the source lane's change and the destination's +1 (never the
+            // same lane) as one packed change
+            const ChanEntry ch{(on ? e.lo : 0u) + (rs < 4u ? inc : 0u),
+                               (on ? e.hi : 0u) + (rs < 4u ? 0u : inc), -1, 0};
+            const bool changed = on || recv;
 #pragma unroll
-                    for (int q = 0; q < SM; ++q)
-                        if (q == spec) {
-                            xd[q] += 1.0;
-                            overflow |= xd[q] >= (double)kCountLimit;
-                        }
-                    changed = true;
-                }
-                ++ev;
-            }
-            if (changed) leaf = voxel_fold(net, xd, degd);
+            for (int q = 0; q < SM; ++q) xd[q] += entry_delta(ch, q);
+            overflow |= changed & out_of_range<SM>(xd, S, (double)kCountLimit);
+            if (changed) leaf = voxel_fold_cached(net, xd, degd, pre, ad);
+            if (event) ++ev;
             __builtin_amdgcn_wave_barrier();
         }
         if (vox) {
@@ -716,7 +820,8 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                                                 double dt, uint32_t kstep, ChiItem *retry_items,
                                                 uint32_t *retry_count)
 {
-    constexpr int SM = NET::SM, RM = NET::RM;
+    constexpr int SM = NET::SM;
+    __shared__ ChanEntry tab[kChanSlots];
     const int lane = threadIdx.x;
     const int stride = cells_per_item;
     uint32_t cursor = blockIdx.x;
@@ -727,7 +832,8 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
         const ItemCtx c = item_ctx(tbl, item, kstep);
         NET net;
         net.load(c.T->model);
-        const int S = c.S;
+        load_channel_table<NET>(tab, c.T->model);
+        const int S = NET::kFixedSpecies ? NET::SM : c.S;
         // leaf pairs: pair k of this lane at lds + (k * stride + lane) * 16
         double *leafp = reinterpret_cast<double *>(lds) + 2 * lane;
         uint16_t *cnt = reinterpret_cast<uint16_t *>(lds + (size_t)stride * kLane16Leaves * 8) + lane;
@@ -856,27 +962,20 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
                 const int deg = voxel_degree(go, v);
                 double resid, a1;
-                int spec;
-                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1, spec);
-                int dst = v;
-                bool wide = false;
-                if (sel < RM) {
+                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
+                const ChanEntry e = tab[sel];
 #pragma unroll
-                    for (int q = 0; q < SM; ++q) {
-                        const int d = reaction_delta(net, sel, q);
-                        if (q < S && d != 0) {
-                            xd[q] += (double)d;
-                            wide |= xd[q] >= (double)kLane16Limit;
-                            x[q * stride] = (uint16_t)(int32_t)xd[q];
-                        }
+                for (int q = 0; q < SM; ++q) {
+                    if (q < S) {
+                        xd[q] += entry_delta(e, q);
+                        x[q * stride] = (uint16_t)(int32_t)xd[q];
                     }
-                } else {
+                }
+                bool wide = out_of_range<SM>(xd, S, (double)kLane16Limit);
+                int dst = v;
+                if (e.spec >= 0) {
                     dst = neighbour_at(go, v, jump_direction(resid, a1, deg));
-#pragma unroll
-                    for (int q = 0; q < SM; ++q)
-                        if (q == spec) xd[q] -= 1.0;
-                    x[spec * stride] = (uint16_t)(x[spec * stride] - 1);
-                    uint16_t *xdst = cnt + (dst * S + spec) * stride;
+                    uint16_t *xdst = cnt + (dst * S + e.spec) * stride;
                     const int32_t nd = (int32_t)*xdst + 1;
                     wide |= nd >= kLane16Limit;
                     *xdst = (uint16_t)nd;

@@ -51,6 +51,7 @@ int hip_fail(hipError_t e, const char *what)
 constexpr size_t kAlign = 256;
 constexpr size_t kChiLdsBudget = 40 * 1024;  // per workgroup: >= 4 resident per CU
 constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t kChiStaticLds = 512;  // the chi kernels' static LDS (channel table), rounded up
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -601,7 +602,7 @@ struct LaunchPlan {
     {
         if (!persistent) return L.n_items;
         int per_cu = wpc;
-        if (per_cu <= 0) per_cu = (int)std::min<size_t>(16, std::max<size_t>(1, kLdsPerCu / std::max<size_t>(L.lds, 1)));
+        if (per_cu <= 0) per_cu = (int)std::min<size_t>(16, std::max<size_t>(1, kLdsPerCu / (L.lds + kChiStaticLds)));
         return std::max<uint32_t>(1, std::min<uint32_t>(L.n_items, (uint32_t)(cus * per_cu)));
     }
 

@@ -71,6 +71,7 @@ std::string network_source(const DevModel &M)
       << "namespace tissue_impl {\n"
       << "struct NetCompiled {\n"
       << "    static constexpr int SM = " << S << ", RM = " << R << ", NDM = " << ND << ";\n"
+      << "    static constexpr bool kFixedSpecies = true;\n"
       << "    static constexpr int kRa[" << std::max(R, 1) << "] = " << array_init(ra) << ";\n"
       << "    static constexpr int kRb[" << std::max(R, 1) << "] = " << array_init(rb) << ";\n"
       << "    static constexpr int kDsp[" << std::max(ND, 1) << "] = " << array_init(dsp) << ";\n"
