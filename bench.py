@@ -103,7 +103,13 @@ def run_single(args, torch, T, p, leg, sims, warmup):
     stream = torch.cuda.current_stream()
     t = T.Tissue(p, device="cuda:0", stream=stream)
     dt, n = p["dt"], p["n_steps"]
-    if args.no_tune:
+    if args.launch:
+        mode, persistent, wpc, chunk = (int(v) for v in args.launch.split(","))
+        t.set_chi_mode(mode)
+        t.set_launch(bool(persistent), wpc)
+        t.set_graph_chunk(chunk)
+        tuned = {"config": dict(chi_mode=mode, persistent=persistent, wpc=wpc, graph_chunk=chunk)}
+    elif args.no_tune:
         t.set_launch(True, 0)
         t.set_graph_chunk(args.graph_chunk)
         tuned = None
@@ -276,6 +282,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1200)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="fixed launch shape instead of the autotuner")
+    ap.add_argument("--launch", default="",
+                    help="MODE,PERSISTENT,WPC,CHUNK: this launch shape instead of the autotuner")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--uneven-steps", type=int, default=1000)

@@ -771,7 +771,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
 #pragma unroll
             for (int q = 0; q < SM; ++q) xd[q] += entry_delta(ch, q);
             overflow |= changed & out_of_range<SM>(xd, S, (double)kCountLimit);
-            if (changed) leaf = voxel_fold_cached(net, xd, degd, pre, ad);
+            leaf = voxel_fold_cached(net, xd, degd, pre, ad);
+            leaf = vox ? leaf : 0.0;
             if (event) ++ev;
             __builtin_amdgcn_wave_barrier();
         }
@@ -934,23 +935,20 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     left = (r < L) || (R == 0.0);
                     r = left ? r : r - L;
                     const int i2 = 2 * b3 + (left ? 0 : 1);
-                    L = q1[0];
-                    R = q1[1];
-#pragma unroll
-                    for (int k = 1; k < 4; ++k) {
-                        L = i2 == k ? q1[2 * k] : L;
-                        R = i2 == k ? q1[2 * k + 1] : R;
-                    }
+                    // the two lower levels from the four leaves under node
+                    // i2, read back by address (the same pairwise sums as
+                    // q1, so the same bits) rather than selected among
+                    // registers
+                    const double *pa = leafp + (size_t)(2 * i2) * stride * 2;
+                    const double *pb = pa + (size_t)stride * 2;
+                    const double la0 = pa[0], la1 = pa[1], lb0 = pb[0], lb1 = pb[1];
+                    L = la0 + la1;
+                    R = lb0 + lb1;
                     left = (r < L) || (R == 0.0);
                     r = left ? r : r - L;
                     const int i1 = 2 * i2 + (left ? 0 : 1);
-                    L = l[0];
-                    R = l[1];
-#pragma unroll
-                    for (int k = 1; k < 8; ++k) {
-                        L = i1 == k ? l[2 * k] : L;
-                        R = i1 == k ? l[2 * k + 1] : R;
-                    }
+                    L = left ? la0 : lb0;
+                    R = left ? la1 : lb1;
                     left = (r < L) || (R == 0.0);
                     r = left ? r : r - L;
                     v = 2 * i1 + (left ? 0 : 1);

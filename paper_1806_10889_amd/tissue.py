@@ -18,7 +18,8 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtissue.so")
+# TISSUE_LIBRARY may name another build of the same library (same ABI)
+LIB_PATH = os.environ.get("TISSUE_LIBRARY") or os.path.join(_HERE, "libtissue.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ESTATE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 FLAG_TRACE = 1
