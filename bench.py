@@ -232,7 +232,7 @@ def run_serving(args, torch):
     reqs = serve.requests_from_workload(args.serve_requests + args.serve_warmup,
                                         rate_hz=args.serve_rate)
     log(f"serving: {len(reqs)} requests generated")
-    be = serve.GpuBackend()
+    be = serve.GpuBackend(lanes=args.serve_lanes)
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(args.serve_hbm_gib * (1 << 30), 0.5 * free))
     srv = serve.Server(be, max_bytes=budget, max_active=args.serve_slots, quantum=args.serve_quantum)
@@ -244,6 +244,7 @@ def run_serving(args, torch):
     out = st.summary()
     out.update({"measured_requests": len(measured), "warmup_requests": args.serve_warmup,
                 "offered_rate_hz": args.serve_rate, "quantum_steps": args.serve_quantum,
+                "lanes": args.serve_lanes,
                 "hbm_budget_bytes": budget,
                 "measured_req_per_s": len(measured) / span, "measured_events_per_s": ev / span,
                 "measured_latency_ms_p50": pct(lat, 50) * 1e3,
@@ -291,6 +292,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-quantum", type=int, default=10)
     ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--serve-hbm-gib", type=float, default=64.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

@@ -182,9 +182,9 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
  * 3 = one lane per cell with the compact layout (16 FP64 leaves, 16-bit
  * counts, upper tree levels rebuilt in registers), cells that reach 2^16
  * molecules of a species handed to a full-width lane launch that redoes
- * their step; 2 = automatic (the default): for cells of at most 16 voxels,
- * rows when the leaf-count class has fewer cells than 64 per SIMD of the
- * device, else the compact layout.  Modes 1 and 3 apply to cells of at most
+ * their step; 2 = automatic (the default): for cells of 9 to 16 voxels,
+ * rows when that class has fewer cells than 64 per SIMD of the device, else
+ * the compact layout; mode 0 for all other cells.  Modes 1 and 3 apply to cells of at most
  * 16 voxels; larger cells always take mode 0.  Results are bit-identical
  * for every choice.  Other values: TISSUE_EINVAL. */
 int tissue_set_chi_mode(tissue_t *t, int32_t mode);

@@ -464,7 +464,11 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         if (k.P <= 16) {
             if (mode_req == kModeRow) mode = kChiRow;
             if (mode_req == kModeLane16) mode = kChiLane16;
-            if (mode_req == kModeAuto)
+            // automatic: cells of at most 8 leaves keep the full lane layout
+            // (small in LDS, few tree levels; a row would idle most of its
+            // lanes); 16-leaf cells take rows when one lane per cell would
+            // leave SIMDs without a wavefront, else the compact layout
+            if (mode_req == kModeAuto && k.P == 16)
                 mode = cells < (uint64_t)kWave * (uint64_t)std::max(n_simd, 1) ? kChiRow : kChiLane16;
         }
         ChiLaunch L;
@@ -653,8 +657,11 @@ struct LaunchPlan {
         plan_chi(members, mode, cus * 4, items, launches);
         if (items.size() > chi_items_cap) return fail(TISSUE_EINVAL, "chi item region too small");
         HIP_TRY(hipStreamSynchronize(stream));
-        if (!items.empty())
-            HIP_TRY(hipMemcpy(chi_items, items.data(), items.size() * sizeof(ChiItem), hipMemcpyHostToDevice));
+        if (!items.empty()) {
+            HIP_TRY(hipMemcpyAsync(chi_items, items.data(), items.size() * sizeof(ChiItem),
+                                   hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+        }
         for (ChiLaunch &L : launches) L.items = chi_items + reinterpret_cast<uintptr_t>(L.items);
         chi = std::move(launches);
         chi_mode = mode;
@@ -963,19 +970,19 @@ int tissue_read_counts(tissue_t *t, int32_t *host_out, size_t n_out)
     if (!t || !host_out) return fail(TISSUE_EINVAL, "null argument");
     const size_t n = (size_t)t->plan.nvox * t->plan.S;
     if (n_out != n) return fail(TISSUE_EINVAL, "n_out must equal n_voxels * n_species");
-    HIP_TRY(hipStreamSynchronize(t->stream));
-    HIP_TRY(hipMemcpy(host_out, t->d_counts(), n * 4, hipMemcpyDeviceToHost));
     unsigned char ctl[64];
-    HIP_TRY(hipMemcpy(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(host_out, t->d_counts(), n * 4, hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipMemcpyAsync(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));
     return check_flags(ctl);
 }
 
 int tissue_read_stats(tissue_t *t, tissue_stats_t *out)
 {
     if (!t || !out) return fail(TISSUE_EINVAL, "null argument");
-    HIP_TRY(hipStreamSynchronize(t->stream));
     unsigned char ctl[64];
-    HIP_TRY(hipMemcpy(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost, t->stream));
+    HIP_TRY(hipStreamSynchronize(t->stream));
     uint64_t st[3];
     uint32_t fl[2];
     std::memcpy(st, ctl, 24);
@@ -1049,8 +1056,8 @@ int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in)
     for (size_t i = 0; i < n; ++i)
         if (host_in[i] < 0 || host_in[i] >= TISSUE_COUNT_LIMIT)
             return fail(TISSUE_EINVAL, "counts must be in [0, 2^26)");
+    HIP_TRY(hipMemcpyAsync(t->d_counts(), host_in, n * 4, hipMemcpyHostToDevice, t->stream));
     HIP_TRY(hipStreamSynchronize(t->stream));
-    HIP_TRY(hipMemcpy(t->d_counts(), host_in, n * 4, hipMemcpyHostToDevice));
     return TISSUE_OK;
 }
 

@@ -1,18 +1,25 @@
 """Serving loop: continuous batching of tissue simulations on one GPU.
 
 Requests (a tissue problem plus its number of splitting steps) arrive over
-time.  The server keeps every admitted tissue resident in HBM and, tick by
-tick, advances all of them together by a quantum of steps in one batch
-(`tissue_batch_step`: every chi/S launch covers the work items of all active
-tissues).  A request is admitted as soon as a slot is free and its device
-bytes (`tissue_required_bytes`) fit the memory budget; it leaves as soon as
-its last step is done, its counts are read back and its buffer is released.
-So requests that arrive while others run join the next tick and their work
-overlaps on the device with everyone else's.
+time.  The server keeps every admitted tissue resident in HBM and advances
+them in batches (`tissue_batch_step`: every chi/S launch covers the work
+items of all the batch's tissues) by a quantum of steps per tick.  A request
+is admitted as soon as a slot is free and its device bytes
+(`tissue_required_bytes`) fit the memory budget; it leaves as soon as its
+last step is done, its counts are read back and its buffer is released.
+
+The requests are spread over independent lanes, each with its own stream,
+batch and tick: a tick's duration is set by the cell with the longest event
+chain in the batch, so requests are routed by an estimate of that chain (the
+expected events per step of their busiest cell) and light requests do not
+wait on heavy ones.  While the device runs one lane's tick, the host
+finishes other lanes' ticks, creates newly admitted tissues and launches the
+next ticks.
 
 Each tissue carries its own step counter and random stream (seed, sim_id,
-step index), so its result does not depend on which other tissues shared its
-launches: a request gives the same bits alone and in the mix.
+step index), so its result does not depend on which lane or which other
+tissues shared its launches: a request gives the same bits alone and in the
+mix.
 
 The loop is written against a small backend interface (`GpuBackend` below);
 the tests drive the same loop with a CPU backend to check admission and
@@ -20,10 +27,13 @@ accounting.
 """
 from __future__ import annotations
 
+import bisect
 import collections
 import heapq
 import time
 from dataclasses import dataclass, field
+
+import numpy as np
 
 
 @dataclass
@@ -39,6 +49,7 @@ class Request:
     bytes: int = 0
     result: object = None
     events: int = 0
+    lane: int = 0
 
 
 @dataclass
@@ -50,6 +61,7 @@ class ServeStats:
     mean_active: float = 0.0
     max_bytes: int = 0
     ticks: int = 0
+    lanes: int = 1
     latencies: list = field(default_factory=list)
     queue_waits: list = field(default_factory=list)
 
@@ -70,18 +82,43 @@ class ServeStats:
             "latency_ms_p99": None if not lat else pct(99) * 1e3,
             "latency_ms_mean": None if not lat else 1e3 * sum(lat) / len(lat),
             "max_active": self.max_active, "mean_active": self.mean_active,
-            "max_hbm_bytes": self.max_bytes, "ticks": self.ticks,
+            "max_hbm_bytes": self.max_bytes, "ticks": self.ticks, "lanes": self.lanes,
         }
 
 
-class Server:
-    """Continuous-batching loop.
+def chain_estimate(problem: dict) -> float:
+    """Expected events per step of the tissue's busiest cell: the propensity
+    of an average voxel (mass action at the mean initial counts, diffusion
+    at degree 3) times the largest cell's voxel count times dt."""
+    p = problem
+    S = int(p["n_species"])
+    x = np.asarray(p["init_counts"], np.float64).reshape(-1, S).mean(axis=0)
+    a = 0.0
+    for r, (ra, rb) in enumerate(np.asarray(p["reactants"], np.int64).reshape(-1, 2)):
+        if ra < 0 and rb < 0:
+            a += p["rates"][r]
+        elif ra < 0 or rb < 0:
+            a += p["rates"][r] * x[max(ra, rb)]
+        elif ra == rb:
+            a += p["rates"][r] * x[ra] * (x[ra] - 1.0) * 0.5
+        else:
+            a += p["rates"][r] * x[ra] * x[rb]
+    a += 3.0 * float(np.dot(np.asarray(p["diffusion"], np.float64), x))
+    vmax = int(np.max(np.asarray(p["mesh_w"], np.int64) * np.asarray(p["mesh_h"], np.int64)))
+    return a * vmax * float(p["dt"])
 
-    backend: object with required_bytes(problem), create(problem),
-      step(handles, dt, n) (advance all handles by n steps, async allowed),
-      sync(), events(handle), read(handle), free(handle).
-    max_bytes: HBM budget for resident tissues; max_active: slot count;
-    quantum: steps per tick.
+
+class Server:
+    """Continuous-batching loop over `lanes` independent lanes.
+
+    backend: object with lanes (int), required_bytes(problem),
+      create(problem, lane), step(lane, handles, dt, n) (advance all handles
+      by n steps, asynchronously allowed), busy(lane) (the lane's last step
+      still running), sync(lane), events(handle), read(handle),
+      free(lane, handle).
+    max_bytes: HBM budget for resident tissues; max_active: slot count over
+    all lanes; quantum: steps per tick.  Requests go to lanes by the rank of
+    chain_estimate among the requests seen so far (one lane: all).
     """
 
     def __init__(self, backend, max_bytes: int, max_active: int = 4096, quantum: int = 10,
@@ -92,134 +129,186 @@ class Server:
         self.quantum = int(quantum)
         self.clock = clock
         self.keep_results = keep_results
+        self.lanes = max(1, int(getattr(backend, "lanes", 1)))
+        self._seen: list = []
+
+    def _route(self, r: Request) -> int:
+        if self.lanes == 1:
+            return 0
+        e = chain_estimate(r.problem)
+        rank = bisect.bisect_left(self._seen, e) / max(len(self._seen), 1)
+        bisect.insort(self._seen, e)
+        return min(self.lanes - 1, int(rank * self.lanes))
 
     def run(self, requests, real_time: bool = True) -> tuple[ServeStats, list]:
         """Serve `requests` (sorted by arrival).  With real_time, arrivals are
         replayed against the wall clock (a request cannot be admitted before
-        its arrival time); otherwise the clock is virtual and every tick
-        advances it by the tick's measured duration."""
+        its arrival time); otherwise the clock is virtual: it advances by the
+        measured time of each pass of the loop and jumps over idle gaps."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        waiting: list = []  # arrived, not admitted: (arrival, rid, req)
-        active: list[Request] = []
+        K = self.lanes
+        waiting = [[] for _ in range(K)]   # per lane: (arrival, rid, req)
+        active = [[] for _ in range(K)]
+        inflight = [0] * K                 # steps of the running tick (0: idle)
         done: list[Request] = []
-        st = ServeStats()
+        st = ServeStats(lanes=K)
         used = 0
+        n_active = 0
         t0 = self.clock()
         vt = 0.0
+        last = t0
         active_sum = 0
-        while pending or waiting or active:
-            now = (self.clock() - t0) if real_time else vt
-            while pending and pending[0].arrival <= now:
+
+        def now():
+            return (self.clock() - t0) if real_time else vt
+
+        while pending or any(waiting) or n_active:
+            if not real_time:
+                c = self.clock()
+                vt += c - last
+                last = c
+            while pending and pending[0].arrival <= now():
                 r = pending.popleft()
-                heapq.heappush(waiting, (r.arrival, r.rid, r))
-            # admission: oldest first, by free slots and free HBM
-            while waiting and len(active) < self.max_active:
-                r = waiting[0][2]
-                need = self.backend.required_bytes(r.problem)
-                if need > self.max_bytes:
-                    raise ValueError(f"request {r.rid} needs {need} B, over the whole budget")
-                if used + need > self.max_bytes:
-                    break
-                heapq.heappop(waiting)
-                r.bytes = need
-                r.handle = self.backend.create(r.problem)
-                r.admitted = now
-                used += need
-                active.append(r)
-            if not active:
-                # idle: jump to the next arrival
+                r.lane = self._route(r)
+                heapq.heappush(waiting[r.lane], (r.arrival, r.rid, r))
+            progressed = False
+            for L in range(K):
+                if inflight[L]:
+                    if self.backend.busy(L):
+                        continue
+                    # the lane's tick has finished: account for it
+                    q = inflight[L]
+                    inflight[L] = 0
+                    progressed = True
+                    end = now()
+                    still = []
+                    for r in active[L]:
+                        r.steps_done += q
+                        if r.steps_done >= r.n_steps:
+                            r.events = self.backend.events(r.handle)
+                            if self.keep_results:
+                                r.result = self.backend.read(r.handle)
+                            self.backend.free(L, r.handle)
+                            r.handle = None
+                            used -= r.bytes
+                            n_active -= 1
+                            r.finished = end
+                            st.completed += 1
+                            st.events += r.events
+                            st.latencies.append(r.finished - r.arrival)
+                            st.queue_waits.append(r.admitted - r.arrival)
+                            done.append(r)
+                        else:
+                            still.append(r)
+                    active[L] = still
+                # admission into this lane: oldest first, by slots and HBM
+                while waiting[L] and n_active < self.max_active:
+                    r = waiting[L][0][2]
+                    need = self.backend.required_bytes(r.problem)
+                    if need > self.max_bytes:
+                        raise ValueError(f"request {r.rid} needs {need} B, over the whole budget")
+                    if used + need > self.max_bytes:
+                        break
+                    heapq.heappop(waiting[L])
+                    r.bytes = need
+                    r.handle = self.backend.create(r.problem, L)
+                    r.admitted = now()
+                    used += need
+                    n_active += 1
+                    active[L].append(r)
+                    progressed = True
+                if active[L]:
+                    q = min([self.quantum] + [r.n_steps - r.steps_done for r in active[L]])
+                    by_dt = collections.defaultdict(list)
+                    for r in active[L]:
+                        by_dt[r.problem["dt"]].append(r.handle)
+                    for d, hs in by_dt.items():
+                        self.backend.step(L, hs, d, q)
+                    inflight[L] = q
+                    st.ticks += 1
+                    active_sum += n_active
+                    progressed = True
+            st.max_active = max(st.max_active, n_active)
+            st.max_bytes = max(st.max_bytes, used)
+            if progressed:
+                continue
+            if not any(inflight):
+                # idle: wait for the next arrival
                 if not pending:
                     break
                 if real_time:
-                    delay = pending[0].arrival - (self.clock() - t0)
+                    delay = pending[0].arrival - now()
                     if delay > 0:
                         time.sleep(min(delay, 0.05))
                 else:
                     vt = max(vt, pending[0].arrival)
-                continue
-            st.max_active = max(st.max_active, len(active))
-            st.max_bytes = max(st.max_bytes, used)
-            active_sum += len(active)
-            # one tick: every active tissue advances by up to one quantum;
-            # tissues needing fewer steps than the quantum finish this tick
-            tick_start = self.clock()
-            q = min([self.quantum] + [r.n_steps - r.steps_done for r in active])
-            dt = active[0].problem["dt"]
-            same_dt = all(r.problem["dt"] == dt for r in active)
-            if same_dt:
-                self.backend.step([r.handle for r in active], dt, q)
+                    last = self.clock()
             else:
-                by_dt = collections.defaultdict(list)
-                for r in active:
-                    by_dt[r.problem["dt"]].append(r.handle)
-                for d, hs in by_dt.items():
-                    self.backend.step(hs, d, q)
-            self.backend.sync()
-            st.ticks += 1
-            finished_now = self.clock()
-            if not real_time:
-                vt += finished_now - tick_start
-            end = (finished_now - t0) if real_time else vt
-            still = []
-            for r in active:
-                r.steps_done += q
-                if r.steps_done >= r.n_steps:
-                    r.events = self.backend.events(r.handle)
-                    if self.keep_results:
-                        r.result = self.backend.read(r.handle)
-                    self.backend.free(r.handle)
-                    r.handle = None
-                    used -= r.bytes
-                    r.finished = end
-                    st.completed += 1
-                    st.events += r.events
-                    st.latencies.append(r.finished - r.arrival)
-                    st.queue_waits.append(r.admitted - r.arrival)
-                    done.append(r)
-                else:
-                    still.append(r)
-            active = still
-        st.wall_s = (self.clock() - t0) if real_time else vt
+                # the device is busy: wait a little for a lane to finish
+                time.sleep(2e-4)
+        st.wall_s = now()
         st.mean_active = active_sum / st.ticks if st.ticks else 0.0
         return st, done
 
 
 class GpuBackend:
     """The C-ABI library as a serving backend: one Tissue per request (its
-    own device buffer) and one Batch per distinct active set, rebuilt only
-    when the set changes."""
+    own device buffer), per lane one stream and one Batch per distinct
+    active set, rebuilt only when the set changes."""
 
-    def __init__(self, device="cuda:0", stream=None, graph_chunk: int = 0):
+    def __init__(self, device="cuda:0", lanes: int = 4, graph_chunk: int = 0,
+                 persistent: bool = False):
         import torch
 
         from . import tissue as T
         self.T = T
         self.torch = torch
         self.device = device
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.lanes = int(lanes)
+        # default priority on every stream
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(self.lanes)]
         self.graph_chunk = graph_chunk
-        self._batch = None
-        self._batch_key = None
+        # one workgroup per work item, so that the lanes' kernels share the
+        # compute units as their workgroups retire (a persistent grid holds
+        # every CU until its slowest item is done)
+        self.persistent = bool(persistent)
+        self._batch = [None] * self.lanes
+        self._key = [None] * self.lanes
+        self._done = [None] * self.lanes
+        self._bytes = {}
 
     def required_bytes(self, problem):
-        return self.T.required_bytes(problem) + 256
+        k = id(problem)
+        if k not in self._bytes:
+            self._bytes[k] = self.T.required_bytes(problem) + 256
+        return self._bytes[k]
 
-    def create(self, problem):
-        t = self.T.Tissue(problem, device=self.device, stream=self.stream)
-        return t
+    def create(self, problem, lane):
+        self._bytes.pop(id(problem), None)
+        with self.torch.cuda.stream(self.streams[lane]):
+            return self.T.Tissue(problem, device=self.device, stream=self.streams[lane])
 
-    def step(self, handles, dt, n):
+    def step(self, lane, handles, dt, n):
         key = tuple(id(h) for h in handles)
-        if key != self._batch_key:
-            if self._batch is not None:
-                self._batch.close()
-            self._batch = self.T.Batch(handles, device=self.device, stream=self.stream)
-            self._batch_key = key
-        self._batch.step(dt, n)
+        if key != self._key[lane]:
+            if self._batch[lane] is not None:
+                self._batch[lane].close()
+            self._batch[lane] = self.T.Batch(handles, device=self.device, stream=self.streams[lane])
+            self._batch[lane].set_graph_chunk(self.graph_chunk)
+            self._batch[lane].set_launch(self.persistent, 0)
+            self._key[lane] = key
+        self._batch[lane].step(dt, n)
+        ev = self.torch.cuda.Event()
+        ev.record(self.streams[lane])
+        self._done[lane] = ev
 
-    def sync(self):
-        if self._batch is not None:
-            self._batch.sync()
+    def busy(self, lane):
+        ev = self._done[lane]
+        return ev is not None and not ev.query()
+
+    def sync(self, lane):
+        if self._batch[lane] is not None:
+            self._batch[lane].sync()
 
     def events(self, h):
         st = h.stats()
@@ -228,10 +317,10 @@ class GpuBackend:
     def read(self, h):
         return h.read_counts()
 
-    def free(self, h):
-        if self._batch is not None:
-            self._batch.close()
-            self._batch, self._batch_key = None, None
+    def free(self, lane, h):
+        if self._batch[lane] is not None:
+            self._batch[lane].close()
+            self._batch[lane], self._key[lane] = None, None
         h.close()
         h.buffer = None
 
