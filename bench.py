@@ -252,6 +252,17 @@ def run_serving(args, torch):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, W, p):
     import oracle
     oracle.build(force=False)
@@ -259,10 +270,19 @@ def cpu_baseline(args, W, p):
     a = time.perf_counter()
     r = oracle.run(p, p["dt"], steps, threads=0)
     el = time.perf_counter() - a
+    cores = oracle.max_threads()
+    # the same oracle on one thread, over a shorter prefix
+    s1 = max(1, steps // 20)
+    a = time.perf_counter()
+    r1 = oracle.run(p, p["dt"], s1, threads=1)
+    el1 = time.perf_counter() - a
     return {"value": (r.chi_events + r.s_events) / el, "unit": "events/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"first {steps} splitting steps of the same 4096-cell tissue "
-                      f"({r.chi_events + r.s_events} events, {el:.1f} s)"}
+                      f"({r.chi_events + r.s_events} events, {el:.1f} s)",
+            "single_thread": {"value": (r1.chi_events + r1.s_events) / el1, "unit": "events/s",
+                              "sample": f"first {s1} splitting steps "
+                                        f"({r1.chi_events + r1.s_events} events, {el1:.1f} s)"}}
 
 
 def main():

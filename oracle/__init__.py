@@ -16,7 +16,9 @@ Functions mirror the parts of the method they compute:
   layer; coupling through a single face);
 * :func:`run` -- ``n_steps`` splitting steps, chi for every cell then the
   signalling operator S over colour classes (Algorithm section: operator
-  splitting; Fig. 1: chi then S every timestep).
+  splitting; Fig. 1: chi then S every timestep); with ``problem["scheme"] ==
+  "strang"`` Strang's symmetric splitting instead (chi over dt/2 with counter
+  tag 0, S over dt, chi over dt/2 with tag 2).
 """
 from __future__ import annotations
 
@@ -55,7 +57,7 @@ class _Problem(C.Structure):
         ("pad0", C.c_int32),
         ("trans_rate", C.c_double),
         ("seed", C.c_uint64), ("sim_id", C.c_uint32), ("start_step", C.c_uint32),
-        ("event_cap", C.c_uint32), ("pad1", C.c_uint32),
+        ("event_cap", C.c_uint32), ("scheme", C.c_uint32),
     ]
 
 
@@ -190,6 +192,7 @@ def run(problem: dict, dt: float, n_steps: int, counts=None, start_step=None,
     pr.seed = int(p["seed"]); pr.sim_id = int(p["sim_id"])
     pr.start_step = int(p.get("start_step", 0) if start_step is None else start_step)
     pr.event_cap = int(p.get("event_cap", 1 << 20))
+    pr.scheme = 1 if p.get("scheme", "lie") == "strang" else 0
     ncell = pr.nx * pr.ny
     E = lib().oracle_num_edges(C.byref(pr))
     st = _Stats()

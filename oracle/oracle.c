@@ -255,7 +255,7 @@ typedef struct {
     uint32_t sim_id;
     uint32_t start_step;
     uint32_t event_cap;       /* events per unit-step before the unit stops */
-    uint32_t pad1;
+    uint32_t scheme;          /* 0 Lie: S o chi; 1 Strang: chi/2 o S o chi/2 */
 } oracle_problem;
 
 typedef struct {
@@ -357,7 +357,7 @@ static void check_count(int32_t v, uint32_t *flag)
 /* One chi step of one cell: direct method over the cell's voxels, over the
  * interval [0, dt), clock restarted at 0 every step. */
 static void chi_cell_step(const oracle_problem *p, int cell, int w, int h,
-                          int32_t *cnt, double dt, uint32_t step,
+                          int32_t *cnt, double dt, uint32_t step, uint32_t tag,
                           uint64_t *events_out, uint64_t *draws_out,
                           double *last_t_out, uint32_t *overflow, uint32_t *capped)
 {
@@ -387,7 +387,7 @@ static void chi_cell_step(const oracle_problem *p, int cell, int w, int h,
         if (events >= p->event_cap) { set_flag(capped); break; }
 
         double u1, u2;
-        draw_pair(p->seed, p->sim_id, 0u, (uint32_t)cell, step, j, &u1, &u2);
+        draw_pair(p->seed, p->sim_id, tag, (uint32_t)cell, step, j, &u1, &u2);
         ++j;
         double tau = (-oracle_plog(u1)) / a0;
         double tn = t + tau;
@@ -525,11 +525,17 @@ int oracle_num_edges(const oracle_problem *p)
     return oracle_lattice_edges(p->lattice, p->nx, p->ny, NULL, NULL, NULL, NULL);
 }
 
-/* Run n_steps splitting steps Phi = S_{C-1} o ... o S_0 o chi with global
- * step indices start_step + k.  counts: [cell][voxel][species], updated in
- * place.  Trace arrays are optional (NULL): chi_ev/chi_t are
- * [n_steps][n_cells], s_ev/s_t are [n_steps][n_edges]; *_t hold the bits of
- * the clock after the last accepted event of the unit-step (0.0 if none). */
+/* Run n_steps splitting steps with global step indices start_step + k.
+ * Lie (scheme 0): Phi = S_{C-1} o ... o S_0 o chi, the modules one after the
+ * other over dt (the splitting the paper's framework rests on: section "A
+ * parallel framework for multiscale simulation of cells", design
+ * assumptions).  Strang (scheme 1, G. Strang 1968, symmetric splitting):
+ * chi over dt/2 with counter tag 0, S over dt, chi over dt/2 with tag 2.
+ * counts: [cell][voxel][species], updated in place.  Trace arrays are
+ * optional (NULL): chi_ev/chi_t are [n_steps][n_cells], s_ev/s_t are
+ * [n_steps][n_edges]; *_t hold the bits of the clock after the last accepted
+ * event of the unit-step (0.0 if none); under Strang chi_ev sums the two
+ * halves and chi_t is the second half's clock. */
 int oracle_run(const oracle_problem *p, double dt, int32_t n_steps, int32_t *counts,
                oracle_stats *st, uint32_t *chi_ev, uint64_t *chi_t,
                uint32_t *s_ev, uint64_t *s_t, int32_t n_threads)
@@ -560,14 +566,15 @@ int oracle_run(const oracle_problem *p, double dt, int32_t n_steps, int32_t *cou
 
     for (int k = 0; k < n_steps; ++k) {
         uint32_t step = p->start_step + (uint32_t)k;
-        /* chi: every cell independently */
+        /* chi: every cell independently (first half under Strang) */
+        const double dchi = p->scheme == 1 ? dt * 0.5 : dt;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 16) reduction(+:chi_events, draws)
 #endif
         for (int c = 0; c < ncell; ++c) {
             uint64_t ev, dr;
             double lt;
-            chi_cell_step(p, c, p->mesh_w[c], p->mesh_h[c], counts + off[c], dt, step,
+            chi_cell_step(p, c, p->mesh_w[c], p->mesh_h[c], counts + off[c], dchi, step, 0u,
                           &ev, &dr, &lt, &st->overflow, &st->capped);
             chi_events += ev;
             draws += dr;
@@ -595,6 +602,22 @@ int oracle_run(const oracle_problem *p, double dt, int32_t n_steps, int32_t *cou
                     if (s_ev) s_ev[(int64_t)k * E + e] = (uint32_t)ev;
                     if (s_t) s_t[(int64_t)k * E + e] = dbits(lt);
                 }
+            }
+        }
+        /* Strang: the second half of chi */
+        if (p->scheme == 1) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) reduction(+:chi_events, draws)
+#endif
+            for (int c = 0; c < ncell; ++c) {
+                uint64_t ev, dr;
+                double lt;
+                chi_cell_step(p, c, p->mesh_w[c], p->mesh_h[c], counts + off[c], dchi, step, 2u,
+                              &ev, &dr, &lt, &st->overflow, &st->capped);
+                chi_events += ev;
+                draws += dr;
+                if (chi_ev) chi_ev[(int64_t)k * ncell + c] += (uint32_t)ev;
+                if (chi_t) chi_t[(int64_t)k * ncell + c] = dbits(lt);
             }
         }
     }
