@@ -71,6 +71,12 @@ enum { TISSUE_LATTICE_SQUARE = 0, TISSUE_LATTICE_HEX = 1 };
 /* descriptor flags */
 #define TISSUE_FLAG_TRACE 1u  /* keep per-(unit, step) event counts and clocks */
 #define TISSUE_FLAG_NO_JIT 2u /* use the ahead-of-time generic chi kernels only  */
+/* Strang's symmetric splitting (G. Strang 1968) instead of the paper's
+ * sequential (Lie) splitting: each step is chi over dt/2 (counter tag 0),
+ * S over dt (tag 1), chi over dt/2 (tag 2).  The per-(cell, step) chi trace
+ * then sums both halves' events and holds the second half's clock.  Members
+ * of one batch must agree on this flag. */
+#define TISSUE_FLAG_STRANG 4u
 
 #define TISSUE_MAX_SPECIES 8
 #define TISSUE_MAX_REACTIONS 16

@@ -372,7 +372,7 @@ struct ItemCtx {
 };
 
 __device__ __forceinline__ ItemCtx item_ctx(const DevTissue *const *tbl, const ChiItem &item,
-                                            uint32_t kstep)
+                                            uint32_t kstep, uint32_t tag)
 {
     ItemCtx c;
     c.T = tbl[uni(item.tissue)];
@@ -384,7 +384,7 @@ __device__ __forceinline__ ItemCtx item_ctx(const DevTissue *const *tbl, const C
     const uint64_t seed = uni((uint64_t)c.T->seed);
     c.key0 = (uint32_t)seed;
     c.key1 = (uint32_t)(seed >> 32);
-    c.tagword = (uni(c.T->sim_id) << 2) | 0u;
+    c.tagword = (uni(c.T->sim_id) << 2) | tag;
     c.cap = uni(c.T->event_cap);
     return c;
 }
@@ -417,7 +417,7 @@ template <class NET>
 __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissue *const *tbl,
                                               const ChiItem *items, uint32_t n_items, uint32_t *queue,
                                               int persistent, int cells_per_item, int log2p, double dt,
-                                              uint32_t kstep, uint32_t *n_items_dev)
+                                              uint32_t kstep, uint32_t tag, uint32_t *n_items_dev)
 {
     constexpr int SM = NET::SM;
     __shared__ ChanEntry tab[kChanSlots];
@@ -430,7 +430,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
         const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const ChiItem item = items[it];
-        const ItemCtx c = item_ctx(tbl, item, kstep);
+        const ItemCtx c = item_ctx(tbl, item, kstep, tag);
         NET net;
         net.load(c.T->model);
         load_channel_table<NET>(tab, c.T->model);
@@ -565,7 +565,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
             if (c.T->tr_chi_ev) {
                 const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
                 const size_t slot = (size_t)(c.step % ts) * nc + cell;
-                c.T->tr_chi_ev[slot] = ev;
+                c.T->tr_chi_ev[slot] = tag ? c.T->tr_chi_ev[slot] + ev : ev;  // 2nd half adds
                 c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
             }
         }
@@ -632,7 +632,7 @@ struct RowShared {
 template <class NET>
 __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *const *tbl,
                                              const ChiItem *items, uint32_t n_items, uint32_t *queue,
-                                             int persistent, double dt, uint32_t kstep)
+                                             int persistent, double dt, uint32_t kstep, uint32_t tag)
 {
     constexpr int SM = NET::SM;
     ChanEntry *tab = sh.chan;
@@ -644,7 +644,7 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const ChiItem item = items[it];
-        const ItemCtx c = item_ctx(tbl, item, kstep);
+        const ItemCtx c = item_ctx(tbl, item, kstep, tag);
         NET net;
         net.load(c.T->model);
         load_channel_table<NET>(tab, c.T->model);
@@ -784,7 +784,7 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         if (has_cell && lv == 0 && c.T->tr_chi_ev) {
             const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
             const size_t slot = (size_t)(c.step % ts) * nc + cell;
-            c.T->tr_chi_ev[slot] = ev;
+            c.T->tr_chi_ev[slot] = tag ? c.T->tr_chi_ev[slot] + ev : ev;  // 2nd half adds
             c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
         }
         item_stats(c, lv == 0 ? ev : 0u, lv == 0 ? j : 0u, overflow, capped, 0);
@@ -818,8 +818,8 @@ template <class NET>
 __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTissue *const *tbl,
                                                 const ChiItem *items, uint32_t n_items,
                                                 uint32_t *queue, int persistent, int cells_per_item,
-                                                double dt, uint32_t kstep, ChiItem *retry_items,
-                                                uint32_t *retry_count)
+                                                double dt, uint32_t kstep, uint32_t tag,
+                                                ChiItem *retry_items, uint32_t *retry_count)
 {
     constexpr int SM = NET::SM;
     __shared__ ChanEntry tab[kChanSlots];
@@ -830,7 +830,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
         const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const ChiItem item = items[it];
-        const ItemCtx c = item_ctx(tbl, item, kstep);
+        const ItemCtx c = item_ctx(tbl, item, kstep, tag);
         NET net;
         net.load(c.T->model);
         load_channel_table<NET>(tab, c.T->model);
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
             if (c.T->tr_chi_ev) {
                 const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
                 const size_t slot = (size_t)(c.step % ts) * nc + cell;
-                c.T->tr_chi_ev[slot] = ev;
+                c.T->tr_chi_ev[slot] = tag ? c.T->tr_chi_ev[slot] + ev : ev;  // 2nd half adds
                 c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
             }
         }

@@ -172,6 +172,7 @@ struct Plan {
     std::string net_key;                // structure of the network (cache key)
     const JitKernels *jit = nullptr;    // compiled-network chi kernels, if any
     uint32_t trace_steps = 0;
+    bool strang = false;                // TISSUE_FLAG_STRANG
     // byte offsets inside dev_buf
     size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
            off_cells = 0, off_edges = 0, off_chi = 0, off_s = 0, off_ctl = 0, off_trace = 0,
@@ -194,6 +195,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     if (!d->init_counts) return fail(TISSUE_EINVAL, "init_counts is null");
     if ((d->mesh_w == nullptr) != (d->mesh_h == nullptr))
         return fail(TISSUE_EINVAL, "mesh_w and mesh_h must both be given or both be null");
+    if (d->flags & ~(TISSUE_FLAG_TRACE | TISSUE_FLAG_NO_JIT | TISSUE_FLAG_STRANG))
+        return fail(TISSUE_EINVAL, "unknown bits in flags");
     if ((d->flags & TISSUE_FLAG_TRACE) && d->trace_steps < 1)
         return fail(TISSUE_EINVAL, "trace needs trace_steps >= 1");
     const int S = (int)d->n_species, R = (int)d->n_reactions;
@@ -372,6 +375,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
 
     // device layout
     if (d->flags & TISSUE_FLAG_TRACE) p.trace_steps = d->trace_steps;
+    p.strang = (d->flags & TISSUE_FLAG_STRANG) != 0;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -524,6 +528,7 @@ struct LaunchPlan {
     uint32_t *queue = nullptr;  // device: [0] next item, [1] workgroups done
     hipStream_t stream = nullptr;
     int persistent = 1;
+    bool strang = false;        // chi over dt/2 (tag 0), S over dt, chi over dt/2 (tag 2)
     int wpc = 0;                // workgroups per CU in persistent mode (0 auto)
     int cus = 0;
     int graph_chunk = 50;
@@ -545,7 +550,7 @@ struct LaunchPlan {
     // cells it handed back (a persistent launch that reads the count from
     // device memory and exits at once when it is zero).
     hipError_t launch_chi_any(const ChiLaunch &L, uint32_t grid, hipStream_t st, double dt,
-                              uint32_t kstep)
+                              uint32_t kstep, uint32_t tag)
     {
         int log2p = 0;
         while ((1 << log2p) < L.P) ++log2p;
@@ -563,23 +568,25 @@ struct LaunchPlan {
         a.cells_per_item = L.cells_per_item;
         a.dt = dt;
         a.kstep = kstep;
+        a.tag = tag;
         a.retry_items = retry_items;
         a.retry_count = queue + kQRetry;
         hipError_t e = hipSuccess;
         if (!L.jit) {
             e = launch_chi(L.SM, L.RM, L.NDM, a);
         } else if (L.mode == kChiRow) {
-            void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.dt, &a.kstep};
+            void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.dt, &a.kstep,
+                            &a.tag};
             e = hipModuleLaunchKernel(L.jit->row, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
         } else if (L.mode == kChiLane16) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
-                            &a.dt, &a.kstep, &a.retry_items, &a.retry_count};
+                            &a.dt, &a.kstep, &a.tag, &a.retry_items, &a.retry_count};
             e = hipModuleLaunchKernel(L.jit->lane16, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st,
                                       args, nullptr);
         } else {
             uint32_t *none = nullptr;
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
-                            &log2p, &a.dt, &a.kstep, &none};
+                            &log2p, &a.dt, &a.kstep, &a.tag, &none};
             e = hipModuleLaunchKernel(L.jit->lane, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st,
                                       args, nullptr);
         }
@@ -597,7 +604,7 @@ struct LaunchPlan {
         r.n_items_dev = queue + kQRetry;
         if (!L.jit) return launch_chi(L.SM, L.RM, L.NDM, r);
         void *args[] = {&r.tbl, &r.items, &r.n_items, &r.queue, &r.persistent, &r.cells_per_item,
-                        &log2p, &r.dt, &r.kstep, &r.n_items_dev};
+                        &log2p, &r.dt, &r.kstep, &r.tag, &r.n_items_dev};
         return hipModuleLaunchKernel(L.jit->lane, r.grid, 1, 1, kWave, 1, 1, (unsigned)r.lds, st,
                                      args, nullptr);
     }
@@ -624,16 +631,23 @@ struct LaunchPlan {
                 std::vector<int> *kind = nullptr)
     {
         size_t e = 0;
-        for (int32_t k = 0; k < n; ++k) {
+        // the chi launches of one (half-)step, counter tag `tag`
+        auto chi_pass = [&](double dchi, uint32_t k, uint32_t tag) -> int {
             for (const ChiLaunch &L : chi) {
                 if (L.n_items == 0) continue;
                 if (ev) HIP_TRY(hipEventRecord((*ev)[e++], st));
-                HIP_TRY(launch_chi_any(L, chi_grid(L), st, dt, (uint32_t)k));
+                HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag));
                 if (ev) {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
                     kind->push_back((int)(&L - chi.data()));
                 }
             }
+            return TISSUE_OK;
+        };
+        const double dchi = strang ? dt * 0.5 : dt;
+        for (int32_t k = 0; k < n; ++k) {
+            int rc = chi_pass(dchi, (uint32_t)k, 0u);
+            if (rc != TISSUE_OK) return rc;
             for (const SLaunch &L : s) {
                 if (L.n_items == 0) continue;
                 if (ev) HIP_TRY(hipEventRecord((*ev)[e++], st));
@@ -643,6 +657,10 @@ struct LaunchPlan {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
                     kind->push_back(-1);
                 }
+            }
+            if (strang) {
+                rc = chi_pass(dchi, (uint32_t)k, 2u);
+                if (rc != TISSUE_OK) return rc;
             }
         }
         HIP_TRY(launch_advance(st, tbl, n_tissues, (uint32_t)n));
@@ -672,7 +690,7 @@ struct LaunchPlan {
     int launches_per_step() const
     {
         int c = 0;
-        for (const ChiLaunch &L : chi) c += L.n_items > 0;
+        for (const ChiLaunch &L : chi) c += (L.n_items > 0) * (strang ? 2 : 1);
         for (const SLaunch &L : s) c += L.n_items > 0;
         return c;
     }
@@ -918,6 +936,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     L.queue = reinterpret_cast<uint32_t *>(base + p.off_ctl + 32);
     L.stream = st;
     L.cus = cus;
+    L.strang = p.strang;
     L.members = {&t->plan};
     L.retry_items = reinterpret_cast<ChiItem *>(base + p.off_retry);
     L.chi_items = reinterpret_cast<ChiItem *>(base + p.off_chi);
@@ -1111,6 +1130,9 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
     if (!ts || n < 1) return fail(TISSUE_EINVAL, "batch needs >= 1 tissue");
     for (int32_t i = 0; i < n; ++i)
         if (!ts[i]) return fail(TISSUE_EINVAL, "null tissue in batch");
+    for (int32_t i = 1; i < n; ++i)
+        if (ts[i]->plan.strang != ts[0]->plan.strang)
+            return fail(TISSUE_EINVAL, "batch members must share the splitting scheme");
     // chi items: room for both cuts of every member's classes
     for (int32_t i = 0; i < n; ++i) B.chi_cap += ts[i]->plan.n_chi_items;
     // S: pass 0 holds all edges of members with disjoint faces and class 0
@@ -1197,6 +1219,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     L.queue = reinterpret_cast<uint32_t *>(b->dev + B.off_queue);
     L.stream = st;
     L.cus = cus;
+    L.strang = ts[0]->plan.strang;
     for (int32_t i = 0; i < n; ++i) L.members.push_back(&ts[i]->plan);
     L.retry_items = reinterpret_cast<ChiItem *>(b->dev + B.off_retry);
     L.chi_items = reinterpret_cast<ChiItem *>(b->dev + B.off_chi);

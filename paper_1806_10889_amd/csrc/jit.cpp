@@ -97,28 +97,28 @@ std::string network_source(const DevModel &M)
       << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane(\n"
       << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
       << "    int persistent, int cells_per_item, int log2p, double dt, uint32_t kstep,\n"
-      << "    uint32_t *n_items_dev)\n"
+      << "    uint32_t tag, uint32_t *n_items_dev)\n"
       << "{\n"
       << "    extern __shared__ __align__(16) unsigned char lds[];\n"
       << "    tissue_impl::chi_lane_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
-      << "        persistent, cells_per_item, log2p, dt, kstep, n_items_dev);\n"
+      << "        persistent, cells_per_item, log2p, dt, kstep, tag, n_items_dev);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane16(\n"
       << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
-      << "    int persistent, int cells_per_item, double dt, uint32_t kstep,\n"
+      << "    int persistent, int cells_per_item, double dt, uint32_t kstep, uint32_t tag,\n"
       << "    ChiItem *retry_items, uint32_t *retry_count)\n"
       << "{\n"
       << "    extern __shared__ __align__(16) unsigned char lds[];\n"
       << "    tissue_impl::chi_lane16_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
-      << "        persistent, cells_per_item, dt, kstep, retry_items, retry_count);\n"
+      << "        persistent, cells_per_item, dt, kstep, tag, retry_items, retry_count);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row(\n"
       << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
-      << "    int persistent, double dt, uint32_t kstep)\n"
+      << "    int persistent, double dt, uint32_t kstep, uint32_t tag)\n"
       << "{\n"
       << "    __shared__ tissue_impl::RowShared sh;\n"
       << "    tissue_impl::chi_row_body<tissue_impl::NetCompiled>(sh, tbl, items, n_items, queue,\n"
-      << "        persistent, dt, kstep);\n"
+      << "        persistent, dt, kstep, tag);\n"
       << "}\n";
     return o.str();
 }

@@ -25,6 +25,7 @@ struct ChiArgs {
     int persistent, cells_per_item;
     double dt;
     uint32_t kstep;
+    uint32_t tag;            // counter tag of the chi draws: 0, or 2 for a second half-step
     uint32_t *n_items_dev;   // lane mode: item count in device memory, or null
     ChiItem *retry_items;    // lane16: cells to redo at full width
     uint32_t *retry_count;

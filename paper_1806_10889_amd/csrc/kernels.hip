@@ -21,11 +21,12 @@ __global__ __launch_bounds__(kWave) void chi_lane_kernel(const DevTissue *const 
                                                          const ChiItem *items, uint32_t n_items,
                                                          uint32_t *queue, int persistent,
                                                          int cells_per_item, int log2p, double dt,
-                                                         uint32_t kstep, uint32_t *n_items_dev)
+                                                         uint32_t kstep, uint32_t tag,
+                                                         uint32_t *n_items_dev)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     chi_lane_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
-                                           cells_per_item, log2p, dt, kstep, n_items_dev);
+                                           cells_per_item, log2p, dt, kstep, tag, n_items_dev);
 }
 
 template <int SM, int RM, int NDM>
@@ -33,22 +34,24 @@ __global__ __launch_bounds__(kWave) void chi_lane16_kernel(const DevTissue *cons
                                                            const ChiItem *items, uint32_t n_items,
                                                            uint32_t *queue, int persistent,
                                                            int cells_per_item, double dt,
-                                                           uint32_t kstep, ChiItem *retry_items,
-                                                           uint32_t *retry_count)
+                                                           uint32_t kstep, uint32_t tag,
+                                                           ChiItem *retry_items, uint32_t *retry_count)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     chi_lane16_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
-                                             cells_per_item, dt, kstep, retry_items, retry_count);
+                                             cells_per_item, dt, kstep, tag, retry_items,
+                                             retry_count);
 }
 
 template <int SM, int RM, int NDM>
 __global__ __launch_bounds__(kWave) void chi_row_kernel(const DevTissue *const *tbl,
                                                         const ChiItem *items, uint32_t n_items,
                                                         uint32_t *queue, int persistent, double dt,
-                                                        uint32_t kstep)
+                                                        uint32_t kstep, uint32_t tag)
 {
     __shared__ RowShared sh;
-    chi_row_body<NetGeneric<SM, RM, NDM>>(sh, tbl, items, n_items, queue, persistent, dt, kstep);
+    chi_row_body<NetGeneric<SM, RM, NDM>>(sh, tbl, items, n_items, queue, persistent, dt, kstep,
+                                          tag);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,15 +246,15 @@ hipError_t launch_variant(const ChiArgs &a)
 {
     if (a.mode == kChiRow) {
         hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), 0, a.stream,
-                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep);
+                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
     } else if (a.mode == kChiLane16) {
         hipLaunchKernelGGL((chi_lane16_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
                            a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, a.dt, a.kstep, a.retry_items, a.retry_count);
+                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count);
     } else {
         hipLaunchKernelGGL((chi_lane_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
                            a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, log2_exact(a.P), a.dt, a.kstep, a.n_items_dev);
+                           a.cells_per_item, log2_exact(a.P), a.dt, a.kstep, a.tag, a.n_items_dev);
     }
     return hipGetLastError();
 }

@@ -24,6 +24,7 @@ LIB_PATH = os.environ.get("TISSUE_LIBRARY") or os.path.join(_HERE, "libtissue.so
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ESTATE, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 FLAG_TRACE = 1
 FLAG_NO_JIT = 2
+FLAG_STRANG = 4
 ABI_VERSION = 1
 
 
@@ -165,7 +166,11 @@ class _DescHolder:
         d.sim_id = int(p["sim_id"])
         d.start_step = int(p.get("start_step", 0))
         d.event_cap = int(p.get("event_cap", 0))
-        d.flags = (FLAG_TRACE if trace_steps > 0 else 0) | (0 if jit else FLAG_NO_JIT)
+        scheme = p.get("scheme", "lie")
+        if scheme not in ("lie", "strang"):
+            raise ValueError(f"scheme must be 'lie' or 'strang', not {scheme!r}")
+        d.flags = ((FLAG_TRACE if trace_steps > 0 else 0) | (0 if jit else FLAG_NO_JIT) |
+                   (FLAG_STRANG if scheme == "strang" else 0))
         d.trace_steps = int(trace_steps)
         self.desc = d
 

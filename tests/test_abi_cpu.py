@@ -60,6 +60,24 @@ def test_required_bytes_and_validation():
         q["reactants"][1, 0] = 7
     assert "reactant" in bad(reactant_range)
 
+    # flags: unknown bits are refused; the Strang flag is accepted and does
+    # not change the layout
+    h = T._DescHolder(p)
+    h.desc.flags = 8
+    assert T.lib.tissue_required_bytes(T.C.byref(h.desc)) == 0
+    assert "flags" in T.lib.tissue_last_error().decode()
+    q = dict(p)
+    q["scheme"] = "strang"
+    assert T.required_bytes(q) == T.required_bytes(p)
+    h = T._DescHolder(q)
+    assert h.desc.flags & T.FLAG_STRANG
+    try:
+        T._DescHolder(dict(p, scheme="leapfrog"))
+    except ValueError as e:
+        assert "scheme" in str(e)
+    else:
+        raise AssertionError("expected a ValueError")
+
 
 def test_error_strings():
     from paper_1806_10889_amd import tissue as T

@@ -298,3 +298,65 @@ def test_step_timed_same_bits_and_reports_kernel(oracle_lib, mode, expect):
     assert tm["chi_kernel"] == expect
     assert tm["chi_launches"] == 7 and tm["s_launches"] >= 7 and tm["s_launches"] % 7 == 0
     assert 0 < tm["chi_ms"] <= tm["total_ms"] and 0 < tm["s_ms"] <= tm["total_ms"]
+
+
+# ---------------------------------------------------------------------------
+# Strang splitting: chi over dt/2 (tag 0), S over dt, chi over dt/2 (tag 2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("mode", MODES)
+def test_strang_config2_reduced(oracle_lib, mode, jit):
+    p = W.config2(side=9, n_steps=10)
+    p["scheme"] = "strang"
+    o = _oracle(oracle_lib, p, 10)
+    g = gpu_run(p, 10, trace=True, chi_mode=mode, jit=jit)
+    assert o.chi_events > 10000 and o.s_events > 1000
+    assert_same(g, o)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_strang_uneven_overlapping_faces_and_redo(oracle_lib, mode):
+    p = W.random_problem(33, lattice=1, nx=9, ny=7, model="nd5", uneven=True, dt=0.05, n_steps=6)
+    p["scheme"] = "strang"
+    o = _oracle(oracle_lib, p, 6)
+    assert o.s_events > 0
+    assert_same(gpu_run(p, 6, trace=True, chi_mode=mode, chunks=[2, 4]), o)
+    q = W.random_problem(95, lattice=1, nx=9, ny=8, model="nd5", mesh=(4, 4), dt=0.05, n_steps=3)
+    q["scheme"] = "strang"
+    q["init_counts"].reshape(72, 16, 5)[17, :, 0] = 65535  # the compact layout redoes these
+    assert_same(gpu_run(q, 3, trace=True, chi_mode=mode), _oracle(oracle_lib, q, 3))
+
+
+def test_strang_batch_and_scheme_mismatch(oracle_lib):
+    from paper_1806_10889_amd import tissue as T
+    probs = [W.random_problem(60 + i, lattice=i % 2, nx=5 + i, ny=4, model="nd5",
+                              mesh=(1 + i % 4, 2), dt=0.1, n_steps=5) for i in range(4)]
+    for p in probs:
+        p["scheme"] = "strang"
+    ts = [T.Tissue(p) for p in probs]
+    b = T.Batch(ts)
+    b.step(0.1, 5)
+    b.sync()
+    for p, t in zip(probs, ts):
+        o = _oracle(oracle_lib, p, 5, trace=False)
+        assert_same(dict(counts=t.read_counts(), stats=t.stats()), o, trace=False)
+    b.close()
+    lie = dict(probs[0], scheme="lie", sim_id=99)
+    t2 = T.Tissue(lie)
+    with pytest.raises(T.TissueError, match="scheme"):
+        T.Batch([ts[1], t2])
+    t2.close()
+    for t in ts:
+        t.close()
+
+
+def test_strang_step_timed_two_chi_launches_per_step(oracle_lib):
+    from paper_1806_10889_amd import tissue as T
+    p = W.config2(side=9, n_steps=4)
+    p["scheme"] = "strang"
+    t = T.Tissue(p)
+    tm = t.step_timed(p["dt"], 4)
+    g = dict(counts=t.read_counts(), stats=t.stats())
+    t.close()
+    assert_same(g, _oracle(oracle_lib, p, 4, trace=False), trace=False)
+    assert tm["chi_launches"] == 8
