@@ -252,6 +252,153 @@ def run_serving(args, torch):
     return out
 
 
+# ---------------------------------------------------------------------------
+# dt study: accuracy of the two splittings against the unsplit CME, and the
+# time to solution of the headline tissue, as dt varies
+# ---------------------------------------------------------------------------
+DT_STUDY = (0.4, 0.2, 0.1, 0.05, 0.025)
+
+
+def two_cell_problem(W):
+    """A closed two-cell tissue (one voxel each, no diffusion) whose CME is
+    solvable: cis binding/unbinding and NICD decay in each cell, the trans
+    reaction over the one edge."""
+    import numpy as np
+    rates = np.zeros(9)
+    rates[4], rates[7], rates[8] = 0.7, 0.8, 0.5
+    init = np.array([[3, 1, 0, 0, 0], [1, 3, 0, 0, 0]], np.int32)
+    return W.make_problem(W.model_nd5(), lattice=0, nx=2, ny=1, mesh_w=1, mesh_h=1, rates=rates,
+                          trans_rate=1.5, diffusion=0.0, init_counts=init, seed=31)
+
+
+def split_cme(p):
+    """Reference for the accuracy study (analysis only, not a simulation
+    path): the chi and S generators of the two-cell tissue on its reachable
+    states, as dense matrices, and the initial distribution."""
+    import numpy as np
+    S = p["n_species"]
+    reac = np.asarray(p["reactants"]).reshape(-1, 2)
+    st = np.asarray(p["stoich"]).reshape(-1, S)
+
+    def chi(s):
+        out = []
+        for cell in range(2):
+            x = s[cell * S:(cell + 1) * S]
+            for r in range(p["n_reactions"]):
+                a, b = int(reac[r][0]), int(reac[r][1])
+                c = float(p["rates"][r])
+                if c == 0:
+                    continue
+                h = (1 if a < 0 and b < 0 else x[max(a, b)] if a < 0 or b < 0
+                     else x[a] * (x[a] - 1) // 2 if a == b else x[a] * x[b])
+                if h:
+                    ns = list(s)
+                    for q in range(S):
+                        ns[cell * S + q] += int(st[r][q])
+                    out.append((c * h, tuple(ns)))
+        return out
+
+    def sig(s):
+        out = []
+        for recv, send in ((0, 1), (1, 0)):
+            h = s[recv * S + p["trans_n"]] * s[send * S + p["trans_d"]]
+            if h:
+                ns = list(s)
+                ns[recv * S + p["trans_n"]] -= 1
+                ns[send * S + p["trans_d"]] -= 1
+                ns[recv * S + p["trans_i"]] += 1
+                out.append((p["trans_rate"] * h, tuple(ns)))
+        return out
+
+    x0 = tuple(int(v) for v in np.asarray(p["init_counts"]).ravel())
+    states, index = [x0], {x0: 0}
+    q = 0
+    while q < len(states):
+        for _, ns in chi(states[q]) + sig(states[q]):
+            if ns not in index:
+                index[ns] = len(states)
+                states.append(ns)
+        q += 1
+    n = len(states)
+    Qc, Qs = np.zeros((n, n)), np.zeros((n, n))
+    for Q, f in ((Qc, chi), (Qs, sig)):
+        for a, s in enumerate(states):
+            for rate, ns in f(s):
+                Q[index[ns], a] += rate
+                Q[a, a] -= rate
+    p0 = np.zeros(n)
+    p0[0] = 1.0
+    return states, index, Qc, Qs, p0
+
+
+def run_dt_study(args, torch, T, W):
+    import numpy as np
+    from scipy import linalg
+    p2 = two_cell_problem(W)
+    states, index, Qc, Qs, p0 = split_cme(p2)
+    S = p2["n_species"]
+    obs = np.array([s[p2["trans_i"]] for s in states], np.float64)  # I of cell 0
+    T_acc = 1.2
+    exact = linalg.expm((Qc + Qs) * T_acc) @ p0
+    rows = []
+    # GPU replicas of the two-cell tissue, one set per scheme
+    R = args.dt_replicas
+    reps = {}
+    for scheme in ("lie", "strang"):
+        ts = []
+        for r in range(R):
+            q = dict(p2, sim_id=r, scheme=scheme)
+            ts.append(T.Tissue(q, device="cuda:0"))
+        reps[scheme] = (ts, T.Batch(ts, device="cuda:0"))
+    head = W.config2(n_steps=1)
+    for dt in DT_STUDY:
+        n = int(round(T_acc / dt))
+        row = {"dt": dt}
+        for scheme in ("lie", "strang"):
+            Ec, Es, Eh = (linalg.expm(Qc * dt), linalg.expm(Qs * dt), linalg.expm(Qc * dt * 0.5))
+            pv = p0.copy()
+            for _ in range(n):
+                pv = Es @ (Ec @ pv) if scheme == "lie" else Eh @ (Es @ (Eh @ pv))
+            ts, b = reps[scheme]
+            for r, t in enumerate(ts):
+                t.restart(sim_id=r + 1000 * int(dt * 1000), start_step=0)
+            b.step(dt, n)
+            b.sync()
+            x = np.array([t.read_counts()[p2["trans_i"]] for t in ts], np.float64)
+            row[scheme] = {"law_l1": float(np.abs(pv - exact).sum()),
+                           "mean_err": float(obs @ pv - obs @ exact),
+                           "gpu_mean_err": float(x.mean() - obs @ exact),
+                           "gpu_se": float(x.std(ddof=1) / np.sqrt(len(x)))}
+        # time to solution of the headline tissue over T = args.dt_T
+        n_head = int(round(args.dt_T / dt))
+        for scheme in ("lie", "strang"):
+            ph = dict(head, n_steps=n_head, scheme=scheme)
+            t = T.Tissue(ph, device="cuda:0")
+            t.set_chi_mode(2)
+            t.set_launch(False, 0)
+            t.set_graph_chunk(25)
+            t.step(dt, n_head)  # warm-up (graph capture)
+            t.restart(sim_id=5, start_step=0)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            t.step(dt, n_head)
+            st = t.stats()
+            el = time.perf_counter() - a
+            row[scheme]["headline_ms"] = el * 1e3
+            row[scheme]["headline_events_per_s"] = (st["chi_events"] + st["s_events"]) / el
+            t.close()
+        log(f"dt study: dt={dt} lie={row['lie']} strang={row['strang']}")
+        rows.append(row)
+    for ts, b in reps.values():
+        b.close()
+        for t in ts:
+            t.close()
+    return {"observable": "E[I] of cell 0 of a closed two-cell tissue", "T_accuracy": T_acc,
+            "exact_mean": float(obs @ exact), "replicas": R,
+            "headline": f"hex 64x64 tissue, 4096 cells x 4x4 voxels, T = {args.dt_T}",
+            "rows": rows}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -294,7 +441,10 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--roofline-steps", type=int, default=0,
                     help="steps of the eagerly timed roofline pass (0: the whole horizon)")
-    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving"], default="all",
+    ap.add_argument("--dt-replicas", type=int, default=16384)
+    ap.add_argument("--dt-T", type=float, default=20.0)
+    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt"],
+                    default="all",
                     help="run one leg only (profiling runs); the JSON line then carries that leg")
     ap.add_argument("--plain-only", action="store_true", help="same as --leg plain")
     ap.add_argument("--batch-tissues", type=int, default=512)
@@ -374,6 +524,8 @@ def main():
             "launch": (u["tuned"] or {}).get("config"), "roofline": u["roofline"]}
     if leg in ("all", "batched"):
         out["batched"] = run_batched(args, torch, T, W)
+    if leg == "dt":
+        out["dt_study"] = run_dt_study(args, torch, T, W)
     if leg == "serving" or (leg == "all" and not args.no_serve):
         out["serving"] = run_serving(args, torch)
     if leg == "all" and not args.no_cpu_baseline:
