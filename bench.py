@@ -30,6 +30,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default);
+# the serving leg's lanes each need a queue of their own, or a lane's
+# synchronisation waits behind another lane's kernels.  Set before the HIP
+# runtime starts (torch is imported later).
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+
 METRIC = "SSA events/sec on 1 MI355X (batched vs plain); p50/p99 sim latency"
 
 # Algorithmic VALU work per accepted event, in full-rate lane-operation

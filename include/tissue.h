@@ -160,6 +160,17 @@ int tissue_read_counts(tissue_t *t, int32_t *host_out, size_t n_out);
 /* Synchronise and report the running totals. */
 int tissue_read_stats(tissue_t *t, tissue_stats_t *out);
 
+/* The same totals without blocking, for loops that must not wait on the
+ * device (serving): tissue_stats_enqueue puts a copy of the tissue's
+ * statistics block (TISSUE_STATS_BLOCK_BYTES bytes) into host memory `dst`
+ * on the tissue's stream (use pinned host memory for the copy to be
+ * asynchronous; `dst` must stay valid until the stream has passed it).
+ * After that point tissue_stats_decode turns the block into the totals;
+ * steps_done is the count of steps enqueued when decoding. */
+#define TISSUE_STATS_BLOCK_BYTES 64
+int tissue_stats_enqueue(tissue_t *t, void *dst);
+int tissue_stats_decode(tissue_t *t, const void *block, tissue_stats_t *out);
+
 /* Trace of the last trace_steps steps (tissues created with
  * TISSUE_FLAG_TRACE): for global steps [first_step, first_step + n_steps),
  * chi_events/chi_t_bits are [n_steps][n_cells] and s_events/s_t_bits

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -52,6 +53,41 @@ constexpr size_t kAlign = 256;
 constexpr size_t kChiLdsBudget = 40 * 1024;  // per workgroup: >= 4 resident per CU
 constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kChiStaticLds = 512;  // the chi kernels' static LDS (channel table), rounded up
+
+// Pinned host memory for the copies of the control path (tissue and batch
+// creation, work-item uploads, counts and stats readback).  The runtime
+// stages a copy from pageable memory through a blit kernel, which waits for
+// compute units behind other streams' kernels; from pinned memory the copy
+// engines serve it.  One process-wide buffer, grown on demand and held under
+// its lock until the copy has completed.
+struct PinnedStaging {
+    std::mutex mu;
+    unsigned char *buf = nullptr;
+    size_t cap = 0;
+};
+
+PinnedStaging &staging()
+{
+    static PinnedStaging s;
+    return s;
+}
+
+hipError_t staging_acquire(std::unique_lock<std::mutex> &lk, size_t n, unsigned char **out)
+{
+    PinnedStaging &s = staging();
+    lk = std::unique_lock<std::mutex>(s.mu);
+    if (s.cap < n) {
+        if (s.buf) (void)hipHostFree(s.buf);
+        s.buf = nullptr;
+        s.cap = 0;
+        const size_t c = std::max<size_t>(n, (size_t)1 << 20);
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&s.buf), c, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        s.cap = c;
+    }
+    *out = s.buf;
+    return hipSuccess;
+}
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -676,8 +712,12 @@ struct LaunchPlan {
         if (items.size() > chi_items_cap) return fail(TISSUE_EINVAL, "chi item region too small");
         HIP_TRY(hipStreamSynchronize(stream));
         if (!items.empty()) {
-            HIP_TRY(hipMemcpyAsync(chi_items, items.data(), items.size() * sizeof(ChiItem),
-                                   hipMemcpyHostToDevice, stream));
+            std::unique_lock<std::mutex> lk;
+            unsigned char *h = nullptr;
+            const size_t nb = items.size() * sizeof(ChiItem);
+            HIP_TRY(staging_acquire(lk, nb, &h));
+            std::memcpy(h, items.data(), nb);
+            HIP_TRY(hipMemcpyAsync(chi_items, h, nb, hipMemcpyHostToDevice, stream));
             HIP_TRY(hipStreamSynchronize(stream));
         }
         for (ChiLaunch &L : launches) L.items = chi_items + reinterpret_cast<uintptr_t>(L.items);
@@ -904,30 +944,36 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     R.model = p.model;
     t->steps_done = d->start_step;
 
-    // upload (synchronous on the tissue's stream; create is not on the hot path)
+    // upload (synchronous on the tissue's stream): the buffer's image up to
+    // the control block, assembled in pinned memory, in one copy
     hipStream_t st = t->stream;
     const size_t cbytes = (size_t)p.nvox * p.S * 4;
     DevTissue *d_rec = t->d_rec();
-    HIP_TRY(hipMemcpyAsync(base + p.off_tissue, &R, sizeof(DevTissue), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(base + p.off_tbl, &d_rec, sizeof(DevTissue *), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(base + p.off_counts, d->init_counts, cbytes, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(base + p.off_init, d->init_counts, cbytes, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(base + p.off_voxoff, p.vox_off.data(), p.vox_off.size() * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(base + p.off_wh, p.wh.data(), p.wh.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(base + p.off_cells, p.cell_list.data(), p.cell_list.size() * 4, hipMemcpyHostToDevice, st));
-    if (p.nedge)
-        HIP_TRY(hipMemcpyAsync(base + p.off_edges, p.edges.data(), p.edges.size() * sizeof(EdgeRec),
-                               hipMemcpyHostToDevice, st));
     std::vector<SItem> s_all;
     for (auto &ps : p.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
-    if (!s_all.empty())
-        HIP_TRY(hipMemcpyAsync(base + p.off_s, s_all.data(), s_all.size() * sizeof(SItem),
-                               hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemsetAsync(base + p.off_ctl, 0, 64, st));
-    if (p.trace_steps)
-        HIP_TRY(hipMemsetAsync(base + p.off_trace, 0,
-                               (size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12), st));
-    HIP_TRY(hipStreamSynchronize(st));
+    {
+        std::unique_lock<std::mutex> lk;
+        unsigned char *h = nullptr;
+        const size_t up = p.off_ctl + 64;
+        HIP_TRY(staging_acquire(lk, up, &h));
+        std::memcpy(h + p.off_tissue, &R, sizeof(DevTissue));
+        std::memcpy(h + p.off_tbl, &d_rec, sizeof(DevTissue *));
+        std::memcpy(h + p.off_counts, d->init_counts, cbytes);
+        std::memcpy(h + p.off_init, d->init_counts, cbytes);
+        std::memcpy(h + p.off_voxoff, p.vox_off.data(), p.vox_off.size() * 4);
+        std::memcpy(h + p.off_wh, p.wh.data(), p.wh.size());
+        std::memcpy(h + p.off_cells, p.cell_list.data(), p.cell_list.size() * 4);
+        if (p.nedge) std::memcpy(h + p.off_edges, p.edges.data(), p.edges.size() * sizeof(EdgeRec));
+        std::memset(h + p.off_chi, 0, p.off_s - p.off_chi);
+        if (!s_all.empty()) std::memcpy(h + p.off_s, s_all.data(), s_all.size() * sizeof(SItem));
+        std::memset(h + p.off_ctl, 0, 64);
+        HIP_TRY(hipMemcpyAsync(base, h, up, hipMemcpyHostToDevice, st));
+        if (p.trace_steps)
+            HIP_TRY(hipMemsetAsync(base + p.off_trace, 0,
+                                   (size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12),
+                                   st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
 
     // launch plan of this tissue alone
     LaunchPlan &L = t->lp;
@@ -990,9 +1036,16 @@ int tissue_read_counts(tissue_t *t, int32_t *host_out, size_t n_out)
     const size_t n = (size_t)t->plan.nvox * t->plan.S;
     if (n_out != n) return fail(TISSUE_EINVAL, "n_out must equal n_voxels * n_species");
     unsigned char ctl[64];
-    HIP_TRY(hipMemcpyAsync(host_out, t->d_counts(), n * 4, hipMemcpyDeviceToHost, t->stream));
-    HIP_TRY(hipMemcpyAsync(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost, t->stream));
-    HIP_TRY(hipStreamSynchronize(t->stream));
+    {
+        std::unique_lock<std::mutex> lk;
+        unsigned char *h = nullptr;
+        HIP_TRY(staging_acquire(lk, n * 4 + 64, &h));
+        HIP_TRY(hipMemcpyAsync(h, t->d_counts(), n * 4, hipMemcpyDeviceToHost, t->stream));
+        HIP_TRY(hipMemcpyAsync(h + n * 4, t->d_ctl(), 64, hipMemcpyDeviceToHost, t->stream));
+        HIP_TRY(hipStreamSynchronize(t->stream));
+        std::memcpy(host_out, h, n * 4);
+        std::memcpy(ctl, h + n * 4, 64);
+    }
     return check_flags(ctl);
 }
 
@@ -1000,8 +1053,28 @@ int tissue_read_stats(tissue_t *t, tissue_stats_t *out)
 {
     if (!t || !out) return fail(TISSUE_EINVAL, "null argument");
     unsigned char ctl[64];
-    HIP_TRY(hipMemcpyAsync(ctl, t->d_ctl(), 64, hipMemcpyDeviceToHost, t->stream));
-    HIP_TRY(hipStreamSynchronize(t->stream));
+    {
+        std::unique_lock<std::mutex> lk;
+        unsigned char *h = nullptr;
+        HIP_TRY(staging_acquire(lk, 64, &h));
+        HIP_TRY(hipMemcpyAsync(h, t->d_ctl(), 64, hipMemcpyDeviceToHost, t->stream));
+        HIP_TRY(hipStreamSynchronize(t->stream));
+        std::memcpy(ctl, h, 64);
+    }
+    return tissue_stats_decode(t, ctl, out);
+}
+
+int tissue_stats_enqueue(tissue_t *t, void *dst)
+{
+    if (!t || !dst) return fail(TISSUE_EINVAL, "null argument");
+    HIP_TRY(hipMemcpyAsync(dst, t->d_ctl(), TISSUE_STATS_BLOCK_BYTES, hipMemcpyDeviceToHost, t->stream));
+    return TISSUE_OK;
+}
+
+int tissue_stats_decode(tissue_t *t, const void *block, tissue_stats_t *out)
+{
+    if (!t || !block || !out) return fail(TISSUE_EINVAL, "null argument");
+    const unsigned char *ctl = static_cast<const unsigned char *>(block);
     uint64_t st[3];
     uint32_t fl[2];
     std::memcpy(st, ctl, 24);
@@ -1075,7 +1148,11 @@ int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in)
     for (size_t i = 0; i < n; ++i)
         if (host_in[i] < 0 || host_in[i] >= TISSUE_COUNT_LIMIT)
             return fail(TISSUE_EINVAL, "counts must be in [0, 2^26)");
-    HIP_TRY(hipMemcpyAsync(t->d_counts(), host_in, n * 4, hipMemcpyHostToDevice, t->stream));
+    std::unique_lock<std::mutex> lk;
+    unsigned char *h = nullptr;
+    HIP_TRY(staging_acquire(lk, n * 4, &h));
+    std::memcpy(h, host_in, n * 4);
+    HIP_TRY(hipMemcpyAsync(t->d_counts(), h, n * 4, hipMemcpyHostToDevice, t->stream));
     HIP_TRY(hipStreamSynchronize(t->stream));
     return TISSUE_OK;
 }
@@ -1208,11 +1285,18 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     for (int32_t i = 0; i < n; ++i) tbl[i] = ts[i]->d_rec();
     std::vector<SItem> s_all;
     for (auto &ps : B.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
-    HIP_TRY(hipMemcpyAsync(b->dev + B.off_tbl, tbl.data(), tbl.size() * sizeof(DevTissue *), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemsetAsync(b->dev + B.off_queue, 0, 64, st));
-    if (!s_all.empty())
-        HIP_TRY(hipMemcpyAsync(b->dev + B.off_s, s_all.data(), s_all.size() * sizeof(SItem), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    {
+        // the buffer's image up to the end of the S items, in one copy
+        std::unique_lock<std::mutex> lk;
+        unsigned char *h = nullptr;
+        const size_t up = B.off_s + s_all.size() * sizeof(SItem);
+        HIP_TRY(staging_acquire(lk, up, &h));
+        std::memcpy(h + B.off_tbl, tbl.data(), tbl.size() * sizeof(DevTissue *));
+        std::memset(h + B.off_queue, 0, 64);
+        if (!s_all.empty()) std::memcpy(h + B.off_s, s_all.data(), s_all.size() * sizeof(SItem));
+        HIP_TRY(hipMemcpyAsync(b->dev, h, up, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
     LaunchPlan &L = b->lp;
     L.tbl = reinterpret_cast<DevTissue **>(b->dev + B.off_tbl);
     L.n_tissues = (uint32_t)n;

@@ -112,10 +112,11 @@ class Server:
     """Continuous-batching loop over `lanes` independent lanes.
 
     backend: object with lanes (int), required_bytes(problem),
-      create(problem, lane), step(lane, handles, dt, n) (advance all handles
-      by n steps, asynchronously allowed), busy(lane) (the lane's last step
-      still running), sync(lane), events(handle), read(handle),
-      free(lane, handle).
+      create(problem, lane), step(lane, handles, dt, n, finishing) (advance
+      all handles by n steps, asynchronously allowed; `finishing` are the
+      handles whose last step this is, whose totals events() will report),
+      busy(lane) (the lane's last step still running), sync(lane),
+      events(handle), read(handle), free(lane, handle).
     max_bytes: HBM budget for resident tissues; max_active: slot count over
     all lanes; quantum: steps per tick.  Requests go to lanes by the rank of
     chain_estimate among the requests seen so far (one lane: all).
@@ -220,10 +221,13 @@ class Server:
                 if active[L]:
                     q = min([self.quantum] + [r.n_steps - r.steps_done for r in active[L]])
                     by_dt = collections.defaultdict(list)
+                    ending = collections.defaultdict(list)
                     for r in active[L]:
                         by_dt[r.problem["dt"]].append(r.handle)
+                        if r.steps_done + q >= r.n_steps:
+                            ending[r.problem["dt"]].append(r.handle)
                     for d, hs in by_dt.items():
-                        self.backend.step(L, hs, d, q)
+                        self.backend.step(L, hs, d, q, ending[d])
                     inflight[L] = q
                     st.ticks += 1
                     active_sum += n_active
@@ -254,10 +258,19 @@ class Server:
 class GpuBackend:
     """The C-ABI library as a serving backend: one Tissue per request (its
     own device buffer), per lane one stream and one Batch per distinct
-    active set, rebuilt only when the set changes."""
+    active set, rebuilt only when the set changes.
+
+    Each lane needs a hardware queue of its own: HIP maps streams onto
+    GPU_MAX_HW_QUEUES queues (4 by default, set before the runtime starts),
+    and a lane sharing a queue waits behind the other lane's kernels in
+    every synchronisation (creation, batch rebuild), which the loop cannot
+    hide.  Use a queue count of at least the lanes plus two."""
 
     def __init__(self, device="cuda:0", lanes: int = 4, graph_chunk: int = 0,
-                 persistent: bool = False):
+                 persistent: bool = False, max_slots: int = 8192):
+        import os
+        import warnings
+
         import torch
 
         from . import tissue as T
@@ -265,6 +278,10 @@ class GpuBackend:
         self.torch = torch
         self.device = device
         self.lanes = int(lanes)
+        if self.lanes > 1 and int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < self.lanes + 2:
+            warnings.warn(f"{self.lanes} serving lanes with GPU_MAX_HW_QUEUES="
+                          f"{os.environ.get('GPU_MAX_HW_QUEUES', '4 (default)')}: lanes may share "
+                          "hardware queues and wait on each other", RuntimeWarning)
         # default priority on every stream
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.lanes)]
         self.graph_chunk = graph_chunk
@@ -276,6 +293,12 @@ class GpuBackend:
         self._key = [None] * self.lanes
         self._done = [None] * self.lanes
         self._bytes = {}
+        # pinned host slots for the statistics blocks copied at the end of a
+        # request's last tick (no blocking read in the serving loop)
+        B = T.STATS_BLOCK_BYTES
+        self._stats_host = torch.empty(max_slots * B, dtype=torch.uint8, pin_memory=True)
+        self._free_slots = list(range(max_slots - 1, -1, -1))
+        self._slot = {}
 
     def required_bytes(self, problem):
         k = id(problem)
@@ -286,9 +309,14 @@ class GpuBackend:
     def create(self, problem, lane):
         self._bytes.pop(id(problem), None)
         with self.torch.cuda.stream(self.streams[lane]):
-            return self.T.Tissue(problem, device=self.device, stream=self.streams[lane])
+            t = self.T.Tissue(problem, device=self.device, stream=self.streams[lane])
+        self._slot[id(t)] = self._free_slots.pop()
+        return t
 
-    def step(self, lane, handles, dt, n):
+    def _slot_ptr(self, h):
+        return self._stats_host.data_ptr() + self._slot[id(h)] * self.T.STATS_BLOCK_BYTES
+
+    def step(self, lane, handles, dt, n, finishing=()):
         key = tuple(id(h) for h in handles)
         if key != self._key[lane]:
             if self._batch[lane] is not None:
@@ -298,6 +326,8 @@ class GpuBackend:
             self._batch[lane].set_launch(self.persistent, 0)
             self._key[lane] = key
         self._batch[lane].step(dt, n)
+        for h in finishing:
+            h.stats_enqueue(self._slot_ptr(h))
         ev = self.torch.cuda.Event()
         ev.record(self.streams[lane])
         self._done[lane] = ev
@@ -311,7 +341,9 @@ class GpuBackend:
             self._batch[lane].sync()
 
     def events(self, h):
-        st = h.stats()
+        # the block copied at the end of the request's last tick (the lane's
+        # completion event has passed it)
+        st = h.stats_decode(self._slot_ptr(h))
         return st["chi_events"] + st["s_events"]
 
     def read(self, h):
@@ -323,6 +355,7 @@ class GpuBackend:
             self._batch[lane], self._key[lane] = None, None
         h.close()
         h.buffer = None
+        self._free_slots.append(self._slot.pop(id(h)))
 
 
 def requests_from_workload(n: int, seed: int = 5, rate_hz: float = 200.0, n_steps: int = 100,

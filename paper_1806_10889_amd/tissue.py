@@ -25,6 +25,7 @@ OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ESTATE, ELIMIT = 0, -1, -2, -3, -
 FLAG_TRACE = 1
 FLAG_NO_JIT = 2
 FLAG_STRANG = 4
+STATS_BLOCK_BYTES = 64
 ABI_VERSION = 1
 
 
@@ -68,6 +69,7 @@ EXPORTS = [
     "tissue_required_bytes", "tissue_create", "tissue_step", "tissue_read_counts",
     "tissue_read_stats", "tissue_read_trace", "tissue_restart", "tissue_write_counts",
     "tissue_set_launch", "tissue_set_chi_mode", "tissue_set_graph_chunk", "tissue_step_timed",
+    "tissue_stats_enqueue", "tissue_stats_decode",
     "tissue_destroy", "tissue_batch_set_chi_mode", "tissue_network_check",
     "tissue_batch_set_graph_chunk",
     "tissue_batch_required_bytes", "tissue_batch_create", "tissue_batch_step",
@@ -100,6 +102,8 @@ def _load():
         "tissue_batch_set_chi_mode": (C.c_int, [vp, i32]),
         "tissue_batch_set_graph_chunk": (C.c_int, [vp, i32]),
         "tissue_step_timed": (C.c_int, [vp, dbl, i32, C.POINTER(Timing)]),
+        "tissue_stats_enqueue": (C.c_int, [vp, vp]),
+        "tissue_stats_decode": (C.c_int, [vp, vp, C.POINTER(Stats)]),
         "tissue_destroy": (C.c_int, [vp]),
         "tissue_batch_required_bytes": (sz, [C.POINTER(vp), i32]),
         "tissue_batch_create": (C.c_int, [C.POINTER(vp), i32, vp, sz, vp, C.POINTER(vp)]),
@@ -237,6 +241,18 @@ class Tissue:
     def stats(self) -> dict:
         s = Stats()
         _check(lib.tissue_read_stats(self.handle, C.byref(s)), "tissue_read_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def stats_enqueue(self, dst_ptr: int):
+        """Enqueue a copy of the statistics block (STATS_BLOCK_BYTES) to host
+        address dst_ptr (pinned) on the tissue's stream; decode it with
+        stats_decode once the stream has passed that point."""
+        _check(lib.tissue_stats_enqueue(self.handle, C.c_void_p(int(dst_ptr))), "tissue_stats_enqueue")
+
+    def stats_decode(self, src_ptr: int) -> dict:
+        s = Stats()
+        _check(lib.tissue_stats_decode(self.handle, C.c_void_p(int(src_ptr)), C.byref(s)),
+               "tissue_stats_decode")
         return {f: getattr(s, f) for f, _ in Stats._fields_}
 
     def trace(self, first_step: int, n_steps: int):

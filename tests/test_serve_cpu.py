@@ -28,7 +28,7 @@ class OracleBackend:
         self.created.append(p["sim_id"])
         return h
 
-    def step(self, lane, handles, dt, n):
+    def step(self, lane, handles, dt, n, finishing=()):
         for h in handles:
             s = self.live[id(h)]
             r = self.o.run(s["p"], dt, n, counts=s["counts"], start_step=s["step"])
