@@ -54,7 +54,7 @@ class _Problem(C.Structure):
         ("reactants", C.POINTER(C.c_int32)), ("stoich", C.POINTER(C.c_int32)),
         ("rates", C.POINTER(C.c_double)), ("diffusion", C.POINTER(C.c_double)),
         ("trans_n", C.c_int32), ("trans_d", C.c_int32), ("trans_i", C.c_int32),
-        ("pad0", C.c_int32),
+        ("signal_order", C.c_int32),
         ("trans_rate", C.c_double),
         ("seed", C.c_uint64), ("sim_id", C.c_uint32), ("start_step", C.c_uint32),
         ("event_cap", C.c_uint32), ("scheme", C.c_uint32),
@@ -193,6 +193,7 @@ def run(problem: dict, dt: float, n_steps: int, counts=None, start_step=None,
     pr.start_step = int(p.get("start_step", 0) if start_step is None else start_step)
     pr.event_cap = int(p.get("event_cap", 1 << 20))
     pr.scheme = 1 if p.get("scheme", "lie") == "strang" else 0
+    pr.signal_order = 1 if p.get("signal", "trans") == "first_order" else 2
     ncell = pr.nx * pr.ny
     E = lib().oracle_num_edges(C.byref(pr))
     st = _Stats()

@@ -248,8 +248,10 @@ typedef struct {
     const int32_t *stoich;    /* [R][S] */
     const double *rates;      /* [R] */
     const double *diffusion;  /* [S] */
-    int32_t trans_n, trans_d, trans_i; /* trans_n < 0: no S operator */
-    int32_t pad0;
+    int32_t trans_n, trans_d, trans_i; /* see signal_order */
+    int32_t signal_order;     /* 2: N_i + D_j -> I_i (no S when trans_n < 0);
+                                 1: D_i -> I_j into the facing voxel (no S when
+                                 trans_d < 0) */
     double trans_rate;
     uint64_t seed;
     uint32_t sim_id;
@@ -445,11 +447,37 @@ static void chi_cell_step(const oracle_problem *p, int cell, int w, int h,
 
 /* S channels of one edge: first N_i(v) D_j(w) for v in A, w in B, then the
  * mirror N_j(w) D_i(v) for w in B, v in A; propensity trans_rate * N * D. */
+/* Whether the problem has an S operator at all. */
+static int has_signal(const oracle_problem *p)
+{
+    return p->signal_order == 1 ? p->trans_d >= 0 : p->trans_n >= 0;
+}
+
+/* First-order signalling: the voxel of the receiving face group that a
+ * sending face voxel k of a group of m_from voxels faces.  Both groups are
+ * slices of their cells' membrane rings, traversed the same way round, so
+ * along the shared face they run in opposite directions: the k-th of m_from
+ * faces the (m_to - 1 - floor(k m_to / m_from))-th of m_to (the mirror
+ * image when the groups are equal). */
+static int facing_voxel(int k, int m_from, int m_to)
+{
+    return m_to - 1 - (k * m_to) / m_from;
+}
+
+/* The edge's S channels in order.  Bimolecular (order 2): c N_i(a) D_j(b)
+ * for a in A, b in B, then c N_j(b) D_i(a) for b in B, a in A.  First order
+ * (order 1, the paper's Delta turning into the neighbour's NICD at k_N,
+ * Results, Model): c D_i(a) for a in A, then c D_j(b) for b in B. */
 static int edge_channels(const oracle_problem *p, const int32_t *ci, const int32_t *cj,
                          const int *A, int mA, const int *B, int mB, double *a)
 {
     const int S = p->n_species;
     int K = 0;
+    if (p->signal_order == 1) {
+        for (int ia = 0; ia < mA; ++ia) a[K++] = p->trans_rate * (double)ci[A[ia] * S + p->trans_d];
+        for (int ib = 0; ib < mB; ++ib) a[K++] = p->trans_rate * (double)cj[B[ib] * S + p->trans_d];
+        return K;
+    }
     for (int ia = 0; ia < mA; ++ia)
         for (int ib = 0; ib < mB; ++ib) {
             int64_t nn = ci[A[ia] * S + p->trans_n], dd = cj[B[ib] * S + p->trans_d];
@@ -491,6 +519,21 @@ static void s_edge_step(const oracle_problem *p, int e, int32_t *ci, int32_t *cj
         double r = u2 * a0;
         double resid;
         int k = select_channel(a, K, r, &resid);
+        if (p->signal_order == 1) {
+            int32_t *from, *to;
+            int vf, vt;
+            if (k < mA) {           /* a Delta of cell i becomes NICD in cell j */
+                from = ci; to = cj; vf = A[k]; vt = B[facing_voxel(k, mA, mB)];
+            } else {                /* and the mirror */
+                from = cj; to = ci; vf = B[k - mA]; vt = A[facing_voxel(k - mA, mB, mA)];
+            }
+            from[vf * S + p->trans_d] -= 1;
+            to[vt * S + p->trans_i] += 1;
+            check_count(from[vf * S + p->trans_d], overflow);
+            check_count(to[vt * S + p->trans_i], overflow);
+            ++events;
+            continue;
+        }
         int32_t *recv, *send;
         int vr, vs;
         if (k < mA * mB) {          /* into cell i */
@@ -582,7 +625,7 @@ int oracle_run(const oracle_problem *p, double dt, int32_t n_steps, int32_t *cou
             if (chi_t) chi_t[(int64_t)k * ncell + c] = dbits(lt);
         }
         /* S: colour classes in order, edges of one class independently */
-        if (p->trans_n >= 0) {
+        if (has_signal(p)) {
             for (int col = 0; col < ncol; ++col) {
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 16) reduction(+:s_events, draws)

@@ -113,6 +113,50 @@ def model_dimer():
 # ---------------------------------------------------------------------------
 
 
+def model_notch_paper():
+    """The paper's Notch model (Results, Setup, Model; Table I) as an RDME
+    network: Delta (D) and NICD (I) diffuse, a promoter (G free, B bound to
+    NICD) transcribes Delta while free, NICD binds and unbinds the promoter,
+    D and I degrade; signalling turns a Delta in a face voxel into an NICD
+    in the facing voxel of the neighbour (first order, the S operator)."""
+    m = _net(
+        ["D", "I", "G", "B"],
+        [("transcribe", ["G"], {"D": 1}),
+         ("bind", ["I", "G"], {"I": -1, "G": -1, "B": 1}),
+         ("unbind", ["B"], {"B": -1, "G": 1, "I": 1}),
+         ("deg_D", ["D"], {"D": -1}),
+         ("deg_I", ["I"], {"I": -1})],
+        None)
+    m["trans_d"], m["trans_i"] = 0, 1
+    m["signal"] = "first_order"
+    return m
+
+
+# Table I in per-voxel units for cells of 4 x 4 voxels of side h = 0.25 um:
+# t_D = 1e2 /s; k_a / h^3 = 1e-18 m^3/s / (0.25 um)^3 = 64 /s; k_d = 25 /s;
+# D / h^2 = 1e-12 m^2/s / (0.25 um)^2 = 16 /s per direction; k_N = 1 /s.
+# The degradation rate d is not given; this project takes d = 1 /s.
+NOTCH_PAPER = dict(t_D=100.0, k_a=64.0, k_d=25.0, d=1.0, D=16.0, k_N=1.0)
+
+
+def config_notch(side: int = 64, dt: float = 0.1, n_steps: int = 200, seed: int = 6,
+                 params: dict | None = None) -> dict:
+    """The paper's tissue: identical cubic cells in a 2D square layer (at
+    most four neighbours), here 4 x 4 voxels each with the promoter in voxel
+    (2, 2), no Delta or NICD at the start (fluctuations break the symmetry).
+    dt 0.1 s is the smallest splitting step of the paper's experiments."""
+    m = model_notch_paper()
+    c = dict(NOTCH_PAPER, **(params or {}))
+    ncell = side * side
+    x0 = np.zeros((ncell, 16, 4), dtype=np.int32)
+    x0[:, 2 * 4 + 2, 2] = 1  # G = 1 in voxel (x=2, y=2)
+    rates = [c["t_D"], c["k_a"], c["k_d"], c["d"], c["d"]]
+    return make_problem(m, lattice=0, nx=side, ny=side, mesh_w=4, mesh_h=4, rates=rates,
+                        trans_rate=c["k_N"], diffusion=[c["D"], c["D"], 0.0, 0.0],
+                        init_counts=x0.reshape(-1, 4), seed=seed, dt=dt, n_steps=n_steps,
+                        name=f"notch (paper's model): square {side}x{side}, 4x4 voxels")
+
+
 def make_problem(model: dict, *, lattice: int, nx: int, ny: int, mesh_w, mesh_h,
                  rates, trans_rate: float, diffusion, init_counts, seed: int,
                  sim_id: int = 0, start_step: int = 0, dt: float = 0.1,
@@ -136,7 +180,7 @@ def make_problem(model: dict, *, lattice: int, nx: int, ny: int, mesh_w, mesh_h,
         init_counts=init_counts, seed=int(seed), sim_id=int(sim_id),
         start_step=int(start_step), event_cap=int(event_cap),
         dt=float(dt), n_steps=int(n_steps),
-        species=model["species"])
+        species=model["species"], signal=model.get("signal", "trans"))
 
 
 def n_voxels(problem: dict) -> int:
