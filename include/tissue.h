@@ -77,6 +77,14 @@ enum { TISSUE_LATTICE_SQUARE = 0, TISSUE_LATTICE_HEX = 1 };
  * then sums both halves' events and holds the second half's clock.  Members
  * of one batch must agree on this flag. */
 #define TISSUE_FLAG_STRANG 4u
+/* First-order signalling (the paper's model, Results, Setup, Model): S
+ * turns each trans_d molecule in a face voxel of a cell into a trans_i
+ * molecule of the neighbour at trans_rate per molecule.  The receiving voxel
+ * is the facing one: face groups are slices of the cells' membrane rings,
+ * traversed the same way round, so the k-th voxel of a group of m faces the
+ * (m' - 1 - floor(k m' / m))-th of the neighbour's group of m'.  Channels in
+ * order: trans_rate * D_i(a) for a in A, then trans_rate * D_j(b) for b in B. */
+#define TISSUE_FLAG_SIGNAL_FIRST_ORDER 8u
 
 #define TISSUE_MAX_SPECIES 8
 #define TISSUE_MAX_REACTIONS 16
@@ -108,7 +116,10 @@ typedef struct {
     const double *rates;      /* [n_reactions] in [0, 1e12]: propensity constants */
     const double *diffusion;  /* [n_species] in [0, 1e12]: jump rate per direction */
     int32_t trans_n, trans_d, trans_i; /* S reaction N_i + D_j -> I_i; trans_n < 0
-                                          disables S; otherwise three distinct species */
+                                          disables S; otherwise three distinct species.
+                                          With TISSUE_FLAG_SIGNAL_FIRST_ORDER:
+                                          D_i -> I_j, trans_n unused, trans_d < 0
+                                          disables S; trans_d, trans_i distinct */
     uint32_t flags;           /* TISSUE_FLAG_*                                  */
     double trans_rate;        /* in [0, 1e12]                                   */
     const int32_t *init_counts; /* [sum_c V_c][n_species], each in [0, 2^26)   */

@@ -231,7 +231,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     if (!d->init_counts) return fail(TISSUE_EINVAL, "init_counts is null");
     if ((d->mesh_w == nullptr) != (d->mesh_h == nullptr))
         return fail(TISSUE_EINVAL, "mesh_w and mesh_h must both be given or both be null");
-    if (d->flags & ~(TISSUE_FLAG_TRACE | TISSUE_FLAG_NO_JIT | TISSUE_FLAG_STRANG))
+    if (d->flags & ~(TISSUE_FLAG_TRACE | TISSUE_FLAG_NO_JIT | TISSUE_FLAG_STRANG |
+                     TISSUE_FLAG_SIGNAL_FIRST_ORDER))
         return fail(TISSUE_EINVAL, "unknown bits in flags");
     if ((d->flags & TISSUE_FLAG_TRACE) && d->trace_steps < 1)
         return fail(TISSUE_EINVAL, "trace needs trace_steps >= 1");
@@ -297,11 +298,17 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         M.diff_species[q] = 0;
         M.diff_rate[q] = 0.0;
     }
-    p.has_s = d->trans_n >= 0;
+    const bool first_order = (d->flags & TISSUE_FLAG_SIGNAL_FIRST_ORDER) != 0;
+    p.has_s = first_order ? d->trans_d >= 0 : d->trans_n >= 0;
+    M.signal_order = first_order ? 1 : 2;
     if (p.has_s) {
-        const int tn = d->trans_n, td = d->trans_d, ti = d->trans_i;
-        if (tn >= S || td < 0 || td >= S || ti < 0 || ti >= S || tn == td || tn == ti || td == ti)
+        const int tn = first_order ? -1 : d->trans_n, td = d->trans_d, ti = d->trans_i;
+        if (first_order) {
+            if (td >= S || ti < 0 || ti >= S || td == ti)
+                return fail(TISSUE_EINVAL, "trans_d, trans_i must be distinct species");
+        } else if (tn >= S || td < 0 || td >= S || ti < 0 || ti >= S || tn == td || tn == ti || td == ti) {
             return fail(TISSUE_EINVAL, "trans_n, trans_d, trans_i must be distinct species");
+        }
         if (!finite_nonneg(d->trans_rate)) return fail(TISSUE_EINVAL, "trans_rate must be finite, >= 0 and <= 1e12");
         M.trans_n = tn;
         M.trans_d = td;

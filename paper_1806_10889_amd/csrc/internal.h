@@ -29,7 +29,8 @@ struct DevModel {
     int32_t n_species;
     int32_t n_reactions;
     int32_t n_diff;                      // species with D > 0
-    int32_t trans_n, trans_d, trans_i;   // trans_n < 0: no S operator
+    int32_t trans_n, trans_d, trans_i;   // S species (-1: unused); no S when trans_d < 0
+    int32_t signal_order;                // 2: N_i + D_j -> I_i; 1: D_i -> I_j (facing voxel)
     int8_t reac_a[kMaxReactions];        // first reactant or -1
     int8_t reac_b[kMaxReactions];        // second reactant or -1
     int8_t diff_species[kMaxSpecies];    // species of diffusion channel q

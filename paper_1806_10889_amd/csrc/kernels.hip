@@ -73,6 +73,8 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
         const DevTissue *T = tbl[uni(item.tissue)];
         const int S = uni(T->model.n_species);
         const int sp0 = uni(T->model.trans_n), sp1 = uni(T->model.trans_d), sp2 = uni(T->model.trans_i);
+        // first order: D_i -> I_j into the facing voxel, N unused (slot 0 idle)
+        const bool first_order = uni(T->model.signal_order) == 1;
         const double c = uni(T->model.trans_rate);
         const uint32_t first = uni(item.first), count = uni(item.count);
         const uint32_t step = uni(T->step_base) + kstep;
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
             for (int a = 0; a < kMaxFace; ++a)
                 if (a < mA) {
                     const long long g = (gi + A[a]) * S;
-                    fa[0][a][lane] = counts[g + sp0];
+                    if (!first_order) fa[0][a][lane] = counts[g + sp0];
                     fa[1][a][lane] = counts[g + sp1];
                     fa[2][a][lane] = counts[g + sp2];
                 }
@@ -108,12 +110,59 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
             for (int b = 0; b < kMaxFace; ++b)
                 if (b < mB) {
                     const long long g = (gj + B[b]) * S;
-                    fb[0][b][lane] = counts[g + sp0];
+                    if (!first_order) fb[0][b][lane] = counts[g + sp0];
                     fb[1][b][lane] = counts[g + sp1];
                     fb[2][b][lane] = counts[g + sp2];
                 }
             const int half = mA * mB;
+            // first order: channels c D_i(a) for a in A, then c D_j(b) for b
+            // in B; a Delta of face voxel k of one group becomes an NICD in
+            // voxel m' - 1 - floor(k m' / m) of the other (they run in
+            // opposite directions along the shared face)
+            while (first_order) {
+                double a0 = 0.0;
+                for (int a = 0; a < mA; ++a) a0 = a0 + c * (double)fa[1][a][lane];
+                for (int b = 0; b < mB; ++b) a0 = a0 + c * (double)fb[1][b][lane];
+                if (a0 == 0.0) break;
+                if (ev >= cap) {
+                    capped = true;
+                    break;
+                }
+                const tdev::Words4 wds = tdev::philox4x32_10(j, step, e, tagword, key0, key1);
+                ++j;
+                double u1, u2;
+                tdev::two_uniforms(wds, u1, u2);
+                const double tau = (-tdev::plog(u1)) / a0;
+                const double tn = t + tau;
+                if (tn >= dt) break;
+                t = tn;
+                const double r = u2 * a0;
+                double prefix = 0.0;
+                int sel = -1, last = -1;
+                for (int k = 0; k < mA + mB; ++k) {
+                    const double p = c * (double)(k < mA ? fa[1][k][lane] : fb[1][k - mA][lane]);
+                    const double next = prefix + p;
+                    if (p > 0.0) {
+                        if (sel < 0 && r < next) sel = k;
+                        last = k;
+                    }
+                    prefix = next;
+                }
+                if (sel < 0) sel = last;
+                int32_t nD, nI;
+                if (sel < mA) {
+                    nD = --fa[1][sel][lane];
+                    nI = ++fb[2][mB - 1 - (sel * mB) / mA][lane];
+                } else {
+                    const int kk = sel - mA;
+                    nD = --fb[1][kk][lane];
+                    nI = ++fa[2][mA - 1 - (kk * mA) / mB][lane];
+                }
+                overflow |= (nD < 0) | (nI >= kCountLimit);
+                ++ev;
+            }
             for (;;) {
+                if (first_order) break;
                 // channels: N_i(a) D_j(b) for a, b; then N_j(b) D_i(a) for b, a
                 double a0 = 0.0;
                 for (int a = 0; a < mA; ++a)
@@ -180,7 +229,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
             for (int a = 0; a < kMaxFace; ++a)
                 if (a < mA) {
                     const long long g = (gi + A[a]) * S;
-                    counts[g + sp0] = fa[0][a][lane];
+                    if (!first_order) counts[g + sp0] = fa[0][a][lane];
                     counts[g + sp1] = fa[1][a][lane];
                     counts[g + sp2] = fa[2][a][lane];
                 }
@@ -188,7 +237,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
             for (int b = 0; b < kMaxFace; ++b)
                 if (b < mB) {
                     const long long g = (gj + B[b]) * S;
-                    counts[g + sp0] = fb[0][b][lane];
+                    if (!first_order) counts[g + sp0] = fb[0][b][lane];
                     counts[g + sp1] = fb[1][b][lane];
                     counts[g + sp2] = fb[2][b][lane];
                 }

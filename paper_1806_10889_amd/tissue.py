@@ -25,6 +25,7 @@ OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EBUSY, ESTATE, ELIMIT = 0, -1, -2, -3, -
 FLAG_TRACE = 1
 FLAG_NO_JIT = 2
 FLAG_STRANG = 4
+FLAG_SIGNAL_FIRST_ORDER = 8
 STATS_BLOCK_BYTES = 64
 ABI_VERSION = 1
 
@@ -173,8 +174,12 @@ class _DescHolder:
         scheme = p.get("scheme", "lie")
         if scheme not in ("lie", "strang"):
             raise ValueError(f"scheme must be 'lie' or 'strang', not {scheme!r}")
+        signal = p.get("signal", "trans")
+        if signal not in ("trans", "first_order"):
+            raise ValueError(f"signal must be 'trans' or 'first_order', not {signal!r}")
         d.flags = ((FLAG_TRACE if trace_steps > 0 else 0) | (0 if jit else FLAG_NO_JIT) |
-                   (FLAG_STRANG if scheme == "strang" else 0))
+                   (FLAG_STRANG if scheme == "strang" else 0) |
+                   (FLAG_SIGNAL_FIRST_ORDER if signal == "first_order" else 0))
         d.trace_steps = int(trace_steps)
         self.desc = d
 

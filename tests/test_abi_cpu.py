@@ -26,6 +26,14 @@ def test_library_exports_every_declared_symbol():
     assert sorted(T.EXPORTS) == names
 
 
+def bad_of(p, mut):
+    from paper_1806_10889_amd import tissue as T
+    q = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    mut(q)
+    assert T.required_bytes(q) == 0, T.lib.tissue_last_error()
+    return T.lib.tissue_last_error().decode()
+
+
 def test_required_bytes_and_validation():
     from paper_1806_10889_amd import tissue as T
     p = W.config2(side=8)
@@ -63,9 +71,20 @@ def test_required_bytes_and_validation():
     # flags: unknown bits are refused; the Strang flag is accepted and does
     # not change the layout
     h = T._DescHolder(p)
-    h.desc.flags = 8
+    h.desc.flags = 16
     assert T.lib.tissue_required_bytes(T.C.byref(h.desc)) == 0
     assert "flags" in T.lib.tissue_last_error().decode()
+    # first-order signalling: trans_n unused, trans_d and trans_i distinct
+    n = W.config_notch(side=4, n_steps=1)
+    assert T._DescHolder(n).desc.flags & T.FLAG_SIGNAL_FIRST_ORDER
+    assert n["trans_n"] == -1 and T.required_bytes(n) > 0
+    assert "distinct" in bad_of(n, lambda q: q.__setitem__("trans_i", q["trans_d"]))
+    try:
+        T._DescHolder(dict(n, signal="second_order"))
+    except ValueError as e:
+        assert "signal" in str(e)
+    else:
+        raise AssertionError("expected a ValueError")
     q = dict(p)
     q["scheme"] = "strang"
     assert T.required_bytes(q) == T.required_bytes(p)

@@ -360,3 +360,62 @@ def test_strang_step_timed_two_chi_launches_per_step(oracle_lib):
     t.close()
     assert_same(g, _oracle(oracle_lib, p, 4, trace=False), trace=False)
     assert tm["chi_launches"] == 8
+
+
+# ---------------------------------------------------------------------------
+# The paper's Notch model: first-order signalling into the facing voxel
+# ---------------------------------------------------------------------------
+def _notch_uneven(seed, lattice, scheme="lie", n_steps=5):
+    """The paper's network on cells of 1..4 x 1..4 voxels (face groups of
+    different sizes on the two sides of an edge), Delta and NICD scattered,
+    one promoter per cell."""
+    rng = np.random.default_rng(seed)
+    nx, ny = 6, 5
+    w = rng.integers(1, 5, size=nx * ny)
+    h = rng.integers(1, 5, size=nx * ny)
+    nvox = int((w * h).sum())
+    x0 = np.zeros((nvox, 4), np.int32)
+    x0[:, 0] = rng.integers(0, 30, nvox)
+    x0[:, 1] = rng.integers(0, 5, nvox)
+    off = np.concatenate([[0], np.cumsum(w * h)[:-1]])
+    x0[off, 2] = 1
+    p = W.make_problem(W.model_notch_paper(), lattice=lattice, nx=nx, ny=ny, mesh_w=w, mesh_h=h,
+                       rates=[100.0, 64.0, 25.0, 1.0, 1.0], trans_rate=2.0,
+                       diffusion=[16.0, 16.0, 0.0, 0.0], init_counts=x0, seed=seed, dt=0.05,
+                       n_steps=n_steps)
+    p["scheme"] = scheme
+    return p
+
+
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("mode", MODES)
+def test_notch_paper_model(oracle_lib, mode, jit):
+    p = W.config_notch(side=7, n_steps=8)
+    o = _oracle(oracle_lib, p, 8)
+    assert o.s_events > 0 and o.chi_events > 10000
+    assert_same(gpu_run(p, 8, trace=True, chi_mode=mode, jit=jit), o)
+
+
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_notch_first_order_uneven_faces(oracle_lib, lattice, scheme):
+    p = _notch_uneven(80 + lattice, lattice, scheme)
+    o = _oracle(oracle_lib, p, 5)
+    assert o.s_events > 100
+    for mode in MODES:
+        assert_same(gpu_run(p, 5, trace=True, chi_mode=mode), o)
+
+
+def test_notch_and_trans_tissues_share_a_batch(oracle_lib):
+    from paper_1806_10889_amd import tissue as T
+    probs = [_notch_uneven(90, 0), W.config2(side=6, n_steps=5), _notch_uneven(91, 1)]
+    ts = [T.Tissue(p) for p in probs]
+    b = T.Batch(ts)
+    b.step(probs[0]["dt"], 5)
+    b.sync()
+    for p, t in zip(probs, ts):
+        o = _oracle(oracle_lib, p, 5, trace=False)
+        assert_same(dict(counts=t.read_counts(), stats=t.stats()), o, trace=False)
+    b.close()
+    for t in ts:
+        t.close()

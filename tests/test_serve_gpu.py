@@ -16,7 +16,7 @@ def test_served_results_equal_alone_and_oracle(oracle_lib):
         steps = 12 + (q % 5)
         p = W.config5_request(q, side_hi=20.0, n_steps=steps)
         reqs.append(serve.Request(rid=q, problem=p, n_steps=steps, arrival=0.002 * q))
-    be = serve.GpuBackend()
+    be = serve.GpuBackend(lanes=2)  # two lanes fit the default four hardware queues
     budget = sum(be.required_bytes(r.problem) for r in reqs) // 4
     srv = serve.Server(be, max_bytes=budget, max_active=12, quantum=5, keep_results=True)
     st, done = srv.run(reqs, real_time=False)
