@@ -406,6 +406,85 @@ def run_dt_study(args, torch, T, W):
             "rows": rows}
 
 
+def pattern_metrics(p, counts):
+    """Lateral inhibition in the paper's model: per cell, Delta and whether
+    the promoter is bound; the correlation of a cell's Delta with its
+    neighbours' mean (negative: neighbours inhibit each other, the
+    checkerboard tendency) and the share of cells whose Delta is on the
+    other side of the median from every neighbour's."""
+    import numpy as np
+    nx, ny = p["nx"], p["ny"]
+    c = counts.reshape(nx * ny, 16, 4)
+    d = c[:, :, 0].sum(axis=1).astype(np.float64).reshape(ny, nx)
+    bound = float(c[:, :, 3].sum()) / (nx * ny)
+    nb_sum = np.zeros_like(d)
+    nb_cnt = np.zeros_like(d)
+    for dy, dx in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        sh = np.roll(np.roll(d, dy, axis=0), dx, axis=1)
+        valid = np.ones_like(d, bool)
+        if dy == 1: valid[0, :] = False
+        if dy == -1: valid[-1, :] = False
+        if dx == 1: valid[:, 0] = False
+        if dx == -1: valid[:, -1] = False
+        nb_sum += np.where(valid, sh, 0.0)
+        nb_cnt += valid
+    nb_mean = nb_sum / nb_cnt
+    corr = float(np.corrcoef(d.ravel(), nb_mean.ravel())[0, 1])
+    med = np.median(d)
+    hi = d > med
+    alt = 0
+    for y in range(ny):
+        for x in range(nx):
+            nbs = [(y + a, x + b) for a, b in ((0, 1), (0, -1), (1, 0), (-1, 0))
+                   if 0 <= y + a < ny and 0 <= x + b < nx]
+            alt += all(hi[q] != hi[y, x] for q in nbs)
+    return {"delta_per_cell_mean": float(d.mean()), "promoter_bound_fraction": bound,
+            "neighbour_correlation": corr, "checkerboard_cells": alt / (nx * ny)}
+
+
+def run_notch(args, torch, T, W):
+    """The paper's model (Table I as an RDME network, first-order
+    signalling): the strong-scaling setup of the paper's Scaling section
+    (8 x 8 cells, 10 s, dt 1.0 / 0.5 / 0.1) and a 64 x 64 tissue, time to
+    solution on one GPU; then 100 s of the 64 x 64 tissue for its pattern."""
+    rows = []
+    for side in (8, 64):
+        for dt in (1.0, 0.5, 0.1):
+            n = int(round(10.0 / dt))
+            p = W.config_notch(side=side, dt=dt, n_steps=n)
+            t = T.Tissue(p, device="cuda:0")
+            t.set_chi_mode(2)
+            t.set_launch(False, 0)
+            t.set_graph_chunk(min(25, n))
+            t.step(dt, n)  # warm-up (graph capture)
+            t.restart(sim_id=3, start_step=0)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            t.step(dt, n)
+            st = t.stats()
+            el = time.perf_counter() - a
+            rows.append({"cells": side * side, "dt": dt, "steps": n, "ms": el * 1e3,
+                         "events": st["chi_events"] + st["s_events"],
+                         "s_events": st["s_events"],
+                         "events_per_s": (st["chi_events"] + st["s_events"]) / el})
+            log(f"notch: {rows[-1]}")
+            t.close()
+    p = W.config_notch(side=64, dt=0.1, n_steps=1000)
+    t = T.Tissue(p, device="cuda:0")
+    t.set_launch(False, 0)
+    t.set_graph_chunk(25)
+    a = time.perf_counter()
+    t.step(0.1, 1000)
+    st = t.stats()
+    el = time.perf_counter() - a
+    pat = pattern_metrics(p, t.read_counts())
+    t.close()
+    return {"model": "the paper's Notch model (Table I per voxel, d = 1/s), 4x4 voxels per cell, "
+                     "first-order signalling at k_N", "T": 10.0, "rows": rows,
+            "pattern_64x64_T100": dict(pat, ms=el * 1e3,
+                                       events_per_s=(st["chi_events"] + st["s_events"]) / el)}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -450,7 +529,7 @@ def main():
                     help="steps of the eagerly timed roofline pass (0: the whole horizon)")
     ap.add_argument("--dt-replicas", type=int, default=16384)
     ap.add_argument("--dt-T", type=float, default=20.0)
-    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt"],
+    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt", "notch"],
                     default="all",
                     help="run one leg only (profiling runs); the JSON line then carries that leg")
     ap.add_argument("--plain-only", action="store_true", help="same as --leg plain")
@@ -533,6 +612,8 @@ def main():
         out["batched"] = run_batched(args, torch, T, W)
     if leg == "dt":
         out["dt_study"] = run_dt_study(args, torch, T, W)
+    if leg == "notch":
+        out["notch"] = run_notch(args, torch, T, W)
     if leg == "serving" or (leg == "all" and not args.no_serve):
         out["serving"] = run_serving(args, torch)
     if leg == "all" and not args.no_cpu_baseline:
