@@ -206,14 +206,15 @@ int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in);
 int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu);
 
 /* Kernel of the chi operator.  0 = one lane per cell with the full sum tree
- * and 32-bit counts in LDS (every cell); 1 = one 16-lane row per cell;
+ * and 32-bit counts in LDS (every cell); 1 = one row of max(16, P) lanes per
+ * cell of P leaves, one lane per voxel (16, 32 or 64 lanes);
  * 3 = one lane per cell with the compact layout (16 FP64 leaves, 16-bit
  * counts, upper tree levels rebuilt in registers), cells that reach 2^16
  * molecules of a species handed to a full-width lane launch that redoes
  * their step; 2 = automatic (the default): for cells of 9 to 16 voxels,
  * rows when that class has fewer cells than 64 per SIMD of the device, else
- * the compact layout; mode 0 for all other cells.  Modes 1 and 3 apply to cells of at most
- * 16 voxels; larger cells always take mode 0.  Results are bit-identical
+ * the compact layout; mode 0 for all other cells.  Mode 3 applies to cells of
+ * at most 16 voxels (larger cells take mode 0).  Results are bit-identical
  * for every choice.  Other values: TISSUE_EINVAL. */
 int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 

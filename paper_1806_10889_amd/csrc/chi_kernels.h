@@ -575,12 +575,14 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
 }
 
 // ---------------------------------------------------------------------------
-// chi, one 16-lane row per cell (cells of at most 16 voxels): lane l of the
-// row holds voxel l's counts (as exact doubles) and leaf propensity.  The
-// sum tree is rebuilt in registers after every event by four in-row DPP
-// exchanges (pair, quad, half-row, row); the descent is evaluated by every
-// lane along the path to its own leaf, and exactly one lane finds all its
-// decisions consistent.  Draws are made 16 at a time, one per lane.
+// chi, one row of 16, 32 or 64 lanes per cell (cells of at most that many
+// voxels): lane l of the row holds voxel l's counts (as exact doubles) and
+// leaf propensity.  The sum tree is rebuilt in registers after every event
+// by four in-row DPP exchanges (pair, quad, half-row, row) and, for wider
+// rows, lane exchanges across rows; the descent is evaluated by every lane
+// along the path to its own leaf, and exactly one lane finds all its
+// decisions consistent.  Draws are made a row's width at a time, one per
+// lane.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -608,6 +610,14 @@ __device__ __forceinline__ uint32_t row_or(uint32_t x)
     return x;
 }
 
+// The value of lane (lane ^ mask), mask 16 or 32: the tree levels and the
+// word broadcast of rows wider than one 16-lane DPP row.
+__device__ __forceinline__ double xlane_f64(double v, int mask)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__shfl_xor(hi, mask, kWave), __shfl_xor(lo, mask, kWave));
+}
+
 // One descent level: children L (left) and R of the lane's ancestor, given
 // the lane's own subtree sum and its sibling's; bit = lane's side.
 __device__ __forceinline__ void descent_level(double own, double sib, int bit, double &r, bool &on)
@@ -629,16 +639,21 @@ struct RowShared {
     ChanEntry chan[kChanSlots];
 };
 
-template <class NET>
+// RW: lanes per row (16, 32 or 64), one voxel per lane, 64 / RW cells per
+// work item; rows of 32 and 64 lanes add one or two tree levels across the
+// 16-lane DPP rows.
+template <class NET, int RW>
 __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *const *tbl,
                                              const ChiItem *items, uint32_t n_items, uint32_t *queue,
                                              int persistent, double dt, uint32_t kstep, uint32_t tag)
 {
+    static_assert(RW == 16 || RW == 32 || RW == 64, "row width");
     constexpr int SM = NET::SM;
+    constexpr int LOG_RW = RW == 64 ? 6 : RW == 32 ? 5 : 4;
     ChanEntry *tab = sh.chan;
     double *rng_e = sh.rng_e;
     double *rng_u = sh.rng_u;
-    const int lane = threadIdx.x, row = lane >> 4, lv = lane & 15;
+    const int lane = threadIdx.x, row = lane >> LOG_RW, lv = lane & (RW - 1);
     uint32_t cursor = blockIdx.x;
     for (;;) {
         const uint32_t it = next_item(queue, persistent != 0, cursor);
@@ -687,9 +702,9 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         // Every running row has drawn exactly once per iteration so far, so
         // its draw ordinal j equals the wave-uniform iteration count.
         for (uint32_t iter = 0;; ++iter) {
-            const uint32_t slot = iter & 15u;
+            const uint32_t slot = iter & (uint32_t)(RW - 1);
             if (slot == 0u) {
-                // draws iter .. iter+15 of the row, one per lane
+                // draws iter .. iter+RW-1 of the row, one per lane
                 if (run) {
                     const tdev::Words4 wds = tdev::philox4x32_10(iter + (uint32_t)lv, c.step, cell,
                                                                  c.tagword, c.key0, c.key1);
@@ -702,8 +717,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             }
             // this iteration's draw of the row (read early: its latency hides
             // behind the tree rebuild)
-            const double e1 = rng_e[(row << 4) | (int)slot];
-            const double u2 = rng_u[(row << 4) | (int)slot];
+            const double e1 = rng_e[(row << LOG_RW) | (int)slot];
+            const double u2 = rng_u[(row << LOG_RW) | (int)slot];
             // the sum tree of the row, rebuilt from the leaves (full wave)
             const double p0 = dpp_f64<kDppPairSwap>(leaf);
             const double s1 = leaf + p0;
@@ -712,7 +727,18 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             const double p2 = dpp_f64<kDppHalfMirror>(s2);
             const double s3 = s2 + p2;
             const double p3 = dpp_f64<kDppRowMirror>(s3);
-            const double a0 = s3 + p3;
+            double a0 = s3 + p3;
+            double s4 = 0.0, p4 = 0.0, s5 = 0.0, p5 = 0.0;
+            if (RW >= 32) {
+                s4 = a0;
+                p4 = xlane_f64(s4, 16);
+                a0 = s4 + p4;
+            }
+            if (RW == 64) {
+                s5 = a0;
+                p5 = xlane_f64(s5, 32);
+                a0 = s5 + p5;
+            }
             if (run) {
                 if (a0 == 0.0) {
                     run = false;
@@ -737,6 +763,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             const int lvo = opaque(lv);
             double rr = u2 * a0;
             bool on = true;
+            if (RW == 64) descent_level(s5, p5, (lvo >> 5) & 1, rr, on);
+            if (RW >= 32) descent_level(s4, p4, (lvo >> 4) & 1, rr, on);
             descent_level(s3, p3, (lvo >> 3) & 1, rr, on);
             descent_level(s2, p2, (lvo >> 2) & 1, rr, on);
             descent_level(s1, p1, (lvo >> 1) & 1, rr, on);
@@ -758,8 +786,11 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             for (int k = 1; k < 4; ++k) dst = kdir == k ? nb[k] : dst;
             uint32_t word = (on && e.spec >= 0) ? (1u | ((uint32_t)e.spec << 4) | ((uint32_t)dst << 8)) : 0u;
             // the row's diffusion word reaches every lane of the row (it is
-            // zero outside the selected lane): OR over the 16-lane row
+            // zero outside the selected lane): OR over the 16-lane DPP row,
+            // then across DPP rows for wider rows
             word = row_or(word);
+            if (RW >= 32) word |= (uint32_t)__shfl_xor((int)word, 16, kWave);
+            if (RW == 64) word |= (uint32_t)__shfl_xor((int)word, 32, kWave);
             const bool recv = event && (word & 1u) && (int)(word >> 8) == lvo;
             const uint32_t rs = (word >> 4) & 15u;
             const uint32_t inc = recv ? (1u << (8u * (rs & 3u))) : 0u;

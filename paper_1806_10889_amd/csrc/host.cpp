@@ -352,9 +352,12 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         g.count = (uint32_t)it->second.size();
         p.cell_list.insert(p.cell_list.end(), it->second.begin(), it->second.end());
         p.chi.push_back(g);
-        // room for both cuts of the class
-        p.n_chi_items += (g.count + lane_cells_per_item(g.P, S) - 1) / lane_cells_per_item(g.P, S);
-        p.n_chi_items += (g.count + 3) / 4;
+        // room for every cut of the class (lane, row of max(16, P) lanes,
+        // compact lane layout), whichever the launch plan picks
+        const uint32_t lcpi = (uint32_t)lane_cells_per_item(g.P, S);
+        const uint32_t rcpi = (uint32_t)(kWave / std::max(16, g.P));
+        p.n_chi_items += (g.count + lcpi - 1) / lcpi + (g.count + rcpi - 1) / rcpi;
+        if (g.P <= 16) p.n_chi_items += g.count;
     }
 
     // edges, face groups, S passes
@@ -508,8 +511,8 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         uint64_t cells = 0;
         for (auto &m : G.cells) cells += m.second->count;
         int mode = kChiLane;
+        if (mode_req == kModeRow) mode = kChiRow;  // rows of max(16, P) lanes
         if (k.P <= 16) {
-            if (mode_req == kModeRow) mode = kChiRow;
             if (mode_req == kModeLane16) mode = kChiLane16;
             // automatic: cells of at most 8 leaves keep the full lane layout
             // (small in LDS, few tree levels; a row would idle most of its
@@ -526,7 +529,7 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         L.NDM = G.NDM;
         L.P = k.P;
         if (mode == kChiRow) {
-            L.cells_per_item = 4;
+            L.cells_per_item = kWave / std::max(16, k.P);
         } else if (mode == kChiLane16) {
             int cpi = 64;
             while (cpi > 1 && chi_lds_bytes(kChiLane16, 16, G.max_s, cpi) > kChiLdsBudget) cpi >>= 1;
@@ -620,7 +623,8 @@ struct LaunchPlan {
         } else if (L.mode == kChiRow) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.dt, &a.kstep,
                             &a.tag};
-            e = hipModuleLaunchKernel(L.jit->row, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
+            hipFunction_t f = L.P > 32 ? L.jit->row64 : L.P > 16 ? L.jit->row32 : L.jit->row;
+            e = hipModuleLaunchKernel(f, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
         } else if (L.mode == kChiLane16) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
                             &a.dt, &a.kstep, &a.tag, &a.retry_items, &a.retry_count};

@@ -112,14 +112,19 @@ std::string network_source(const DevModel &M)
       << "    tissue_impl::chi_lane16_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
       << "        persistent, cells_per_item, dt, kstep, tag, retry_items, retry_count);\n"
       << "}\n"
-      << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row(\n"
-      << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
-      << "    int persistent, double dt, uint32_t kstep, uint32_t tag)\n"
-      << "{\n"
-      << "    __shared__ tissue_impl::RowShared sh;\n"
-      << "    tissue_impl::chi_row_body<tissue_impl::NetCompiled>(sh, tbl, items, n_items, queue,\n"
-      << "        persistent, dt, kstep, tag);\n"
-      << "}\n";
+      ;
+    for (int rw : {16, 32, 64}) {
+        o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row"
+          << (rw == 16 ? std::string() : std::to_string(rw)) << "(\n"
+          << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
+          << "    int persistent, double dt, uint32_t kstep, uint32_t tag)\n"
+          << "{\n"
+          << "    __shared__ tissue_impl::RowShared sh;\n"
+          << "    tissue_impl::chi_row_body<tissue_impl::NetCompiled, " << rw
+          << ">(sh, tbl, items, n_items, queue,\n"
+          << "        persistent, dt, kstep, tag);\n"
+          << "}\n";
+    }
     return o.str();
 }
 
@@ -182,6 +187,8 @@ int jit_kernels(const DevModel &M, const JitKernels **out, std::string &err)
     hipError_t e = hipModuleLoadData(&k->module, code.data());
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane, k->module, "tissue_chi_lane");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->row, k->module, "tissue_chi_row");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->row32, k->module, "tissue_chi_row32");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->row64, k->module, "tissue_chi_row64");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16, k->module, "tissue_chi_lane16");
     if (e != hipSuccess) {
         err = std::string("loading the compiled network: ") + hipGetErrorString(e);

@@ -13,6 +13,8 @@ struct JitKernels {
     hipModule_t module = nullptr;
     hipFunction_t lane = nullptr;  // one lane per cell
     hipFunction_t row = nullptr;   // one 16-lane row per cell
+    hipFunction_t row32 = nullptr; // one 32-lane row per cell (17..32 voxels)
+    hipFunction_t row64 = nullptr; // one 64-lane row per cell (33..64 voxels)
     hipFunction_t lane16 = nullptr; // one lane per cell, compact LDS
 };
 

@@ -43,15 +43,15 @@ __global__ __launch_bounds__(kWave) void chi_lane16_kernel(const DevTissue *cons
                                              retry_count);
 }
 
-template <int SM, int RM, int NDM>
+template <int SM, int RM, int NDM, int RW>
 __global__ __launch_bounds__(kWave) void chi_row_kernel(const DevTissue *const *tbl,
                                                         const ChiItem *items, uint32_t n_items,
                                                         uint32_t *queue, int persistent, double dt,
                                                         uint32_t kstep, uint32_t tag)
 {
     __shared__ RowShared sh;
-    chi_row_body<NetGeneric<SM, RM, NDM>>(sh, tbl, items, n_items, queue, persistent, dt, kstep,
-                                          tag);
+    chi_row_body<NetGeneric<SM, RM, NDM>, RW>(sh, tbl, items, n_items, queue, persistent, dt,
+                                              kstep, tag);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,8 +293,14 @@ int log2_exact(int P)
 template <int SM, int RM, int NDM>
 hipError_t launch_variant(const ChiArgs &a)
 {
-    if (a.mode == kChiRow) {
-        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), 0, a.stream,
+    if (a.mode == kChiRow && a.P > 32) {
+        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 64>), dim3(a.grid), dim3(kWave), 0, a.stream,
+                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
+    } else if (a.mode == kChiRow && a.P > 16) {
+        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 32>), dim3(a.grid), dim3(kWave), 0, a.stream,
+                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
+    } else if (a.mode == kChiRow) {
+        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 16>), dim3(a.grid), dim3(kWave), 0, a.stream,
                            a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
     } else if (a.mode == kChiLane16) {
         hipLaunchKernelGGL((chi_lane16_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
