@@ -580,8 +580,35 @@ struct LaunchPlan {
     int graph_chunk = 50;
     hipStream_t capture_stream = nullptr;
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // side streams and fork/join events for running the leaf-count classes'
+    // chi launches of one step concurrently
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork_ev = nullptr;
 
-    ~LaunchPlan() { clear_graphs(); if (capture_stream) (void)hipStreamDestroy(capture_stream); }
+    ~LaunchPlan()
+    {
+        clear_graphs();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        for (hipStream_t s : side) (void)hipStreamDestroy(s);
+        for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+    }
+
+    // Streams and events for n concurrent chi launches (n - 1 side streams).
+    int ensure_side(size_t n)
+    {
+        if (!fork_ev) HIP_TRY(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+        while (side.size() + 1 < n) {
+            hipStream_t s = nullptr;
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            side.push_back(s);
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            joins.push_back(e);
+        }
+        return TISSUE_OK;
+    }
 
     void clear_graphs()
     {
@@ -678,8 +705,38 @@ struct LaunchPlan {
                 std::vector<int> *kind = nullptr)
     {
         size_t e = 0;
-        // the chi launches of one (half-)step, counter tag `tag`
+        // the chi launches of one (half-)step, counter tag `tag`.  Classes
+        // touch disjoint cells, so with one workgroup per item (no shared
+        // queue words) the captured step graph runs them as parallel
+        // branches: the first on `st`, the others on side streams forked from
+        // and joined back into it.  Eager launches (timed runs, serving) keep
+        // them in order on the caller's stream.
+        size_t active = 0;
+        for (const ChiLaunch &L : chi) active += L.n_items > 0;
+        const bool fork = !ev && !persistent && active > 1 && st == capture_stream;
+        if (fork) {
+            const int rc = ensure_side(active);
+            if (rc != TISSUE_OK) return rc;
+        }
         auto chi_pass = [&](double dchi, uint32_t k, uint32_t tag) -> int {
+            if (fork) {
+                HIP_TRY(hipEventRecord(fork_ev, st));
+                size_t b = 0;
+                for (const ChiLaunch &L : chi) {
+                    if (L.n_items == 0) continue;
+                    if (b == 0) {
+                        HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag));
+                    } else {
+                        hipStream_t ss = side[b - 1];
+                        HIP_TRY(hipStreamWaitEvent(ss, fork_ev, 0));
+                        HIP_TRY(launch_chi_any(L, chi_grid(L), ss, dchi, k, tag));
+                        HIP_TRY(hipEventRecord(joins[b - 1], ss));
+                    }
+                    ++b;
+                }
+                for (size_t i = 0; i + 1 < b; ++i) HIP_TRY(hipStreamWaitEvent(st, joins[i], 0));
+                return TISSUE_OK;
+            }
             for (const ChiLaunch &L : chi) {
                 if (L.n_items == 0) continue;
                 if (ev) HIP_TRY(hipEventRecord((*ev)[e++], st));
