@@ -419,3 +419,17 @@ def test_notch_and_trans_tissues_share_a_batch(oracle_lib):
     b.close()
     for t in ts:
         t.close()
+
+
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+def test_classes_in_parallel_graph_branches(oracle_lib, scheme, jit):
+    """One workgroup per item and captured graphs: the leaf-count classes'
+    chi launches run as parallel graph branches; same bits as the oracle
+    (uneven meshes: several classes, overlapping faces)."""
+    p = W.random_problem(37, lattice=1, nx=9, ny=7, model="nd5", uneven=True, dt=0.05, n_steps=6)
+    p["scheme"] = scheme
+    o = _oracle(oracle_lib, p, 6)
+    for mode in (0, 1, 2, 3):
+        g = gpu_run(p, 6, trace=True, persistent=False, graph_chunk=2, chi_mode=mode, jit=jit)
+        assert_same(g, o)
