@@ -54,15 +54,15 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # figures hold for the kernel sources whose digest is recorded with them; any
 # change to those sources makes `traffic` null until the counters are taken
 # again.
-FETCH_SCALE = 262144.0 / 131087.0
+FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC = {   # leg -> counters of its dominant chi kernel
     # hex 64x64 tissue, 4096 cells x 4x4 voxels: 400 dispatches of 200-step runs
-    "plain": {"digest": "3f0855f46b97c3846663a30906f5722117bc5b65", "kernel": "tissue_chi_row",
-              "fetch_kib": 936.51, "write_kib": 1344.0},
-    # 512 tissues, 3.12M cells, 20 steps: 60 dispatches
-    "batched": {"digest": "3f0855f46b97c3846663a30906f5722117bc5b65", "kernel": "tissue_chi_lane16",
-                "fetch_kib": 508703.0, "write_kib": 978937.0},
+    "plain": {"digest": "b883837ef5eb0edf9f9144278bebb36e002b5f4c", "kernel": "tissue_chi_row",
+              "fetch_kib": 931.509, "write_kib": 1344.0},
+    # 512 tissues, 3.12M cells, 200 steps: 450 dispatches
+    "batched": {"digest": "b883837ef5eb0edf9f9144278bebb36e002b5f4c", "kernel": "tissue_chi_lane16",
+                "fetch_kib": 508871.0, "write_kib": 979159.0},
 }
 
 
