@@ -58,6 +58,10 @@ class _Problem(C.Structure):
         ("trans_rate", C.c_double),
         ("seed", C.c_uint64), ("sim_id", C.c_uint32), ("start_step", C.c_uint32),
         ("event_cap", C.c_uint32), ("scheme", C.c_uint32),
+        ("n_models", C.c_int32), ("pad2", C.c_int32),
+        ("cell_model", C.POINTER(C.c_int32)), ("m_n_reactions", C.POINTER(C.c_int32)),
+        ("m_reactants", C.POINTER(C.c_int32)), ("m_stoich", C.POINTER(C.c_int32)),
+        ("m_rates", C.POINTER(C.c_double)), ("m_diffusion", C.POINTER(C.c_double)),
     ]
 
 
@@ -195,6 +199,37 @@ def run(problem: dict, dt: float, n_steps: int, counts=None, start_step=None,
     pr.scheme = 1 if p.get("scheme", "lie") == "strang" else 0
     pr.signal_order = 1 if p.get("signal", "trans") == "first_order" else 2
     ncell = pr.nx * pr.ny
+    keep = []
+    if p.get("models"):
+        # model 0 = the problem's own network, then problem["models"]; tables
+        # padded to 16 reactions
+        S = pr.n_species
+        allm = [dict(reactants=p["reactants"], stoich=p["stoich"], rates=p["rates"],
+                     diffusion=p["diffusion"])] + list(p["models"])
+        K = len(allm)
+        nr = np.zeros(K, np.int32)
+        mre = np.full((K, 16, 2), -1, np.int32)
+        mst = np.zeros((K, 16, S), np.int32)
+        mra = np.zeros((K, 16), np.float64)
+        mdi = np.zeros((K, S), np.float64)
+        for m, md in enumerate(allm):
+            r = np.asarray(md["reactants"], np.int32).reshape(-1, 2)
+            nr[m] = r.shape[0]
+            mre[m, :nr[m]] = r
+            mst[m, :nr[m]] = np.asarray(md["stoich"], np.int32).reshape(-1, S)
+            mra[m, :nr[m]] = np.asarray(md["rates"], np.float64)
+            mdi[m] = np.asarray(md["diffusion"], np.float64)
+        cm = np.ascontiguousarray(p["cell_model"], dtype=np.int32)
+        keep = [nr, mre, mst, mra, mdi, cm]
+        pr.n_models = K
+        pr.cell_model = _ptr(cm, C.c_int32)
+        pr.m_n_reactions = _ptr(nr, C.c_int32)
+        pr.m_reactants = _ptr(mre, C.c_int32)
+        pr.m_stoich = _ptr(mst, C.c_int32)
+        pr.m_rates = _ptr(mra, C.c_double)
+        pr.m_diffusion = _ptr(mdi, C.c_double)
+    else:
+        pr.n_models = 1
     E = lib().oracle_num_edges(C.byref(pr))
     st = _Stats()
     tr = [None] * 4

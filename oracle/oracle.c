@@ -258,7 +258,36 @@ typedef struct {
     uint32_t start_step;
     uint32_t event_cap;       /* events per unit-step before the unit stops */
     uint32_t scheme;          /* 0 Lie: S o chi; 1 Strang: chi/2 o S o chi/2 */
+    /* Per-cell networks (several models updating different cells, the
+     * multi-fidelity use the paper's Discussion describes): n_models > 1
+     * and cell_model[c] in [0, n_models).  Model m's tables, padded to 16
+     * reactions: m_n_reactions[m], m_reactants[m][16][2], m_stoich[m][16][S],
+     * m_rates[m][16], m_diffusion[m][S]; model 0 equals the fields above.
+     * S (the trans fields) is the same for every cell. */
+    int32_t n_models;
+    int32_t pad2;
+    const int32_t *cell_model;
+    const int32_t *m_n_reactions;
+    const int32_t *m_reactants;
+    const int32_t *m_stoich;
+    const double *m_rates;
+    const double *m_diffusion;
 } oracle_problem;
+
+/* The problem as seen by cell c: its own model's network. */
+static oracle_problem cell_view(const oracle_problem *p, int c)
+{
+    oracle_problem v = *p;
+    if (p->n_models > 1) {
+        const int m = p->cell_model[c], S = p->n_species;
+        v.n_reactions = p->m_n_reactions[m];
+        v.reactants = p->m_reactants + (size_t)m * 16 * 2;
+        v.stoich = p->m_stoich + (size_t)m * 16 * S;
+        v.rates = p->m_rates + (size_t)m * 16;
+        v.diffusion = p->m_diffusion + (size_t)m * S;
+    }
+    return v;
+}
 
 typedef struct {
     uint64_t chi_events, s_events, draws;
@@ -617,7 +646,8 @@ int oracle_run(const oracle_problem *p, double dt, int32_t n_steps, int32_t *cou
         for (int c = 0; c < ncell; ++c) {
             uint64_t ev, dr;
             double lt;
-            chi_cell_step(p, c, p->mesh_w[c], p->mesh_h[c], counts + off[c], dchi, step, 0u,
+            const oracle_problem pc = cell_view(p, c);
+            chi_cell_step(&pc, c, p->mesh_w[c], p->mesh_h[c], counts + off[c], dchi, step, 0u,
                           &ev, &dr, &lt, &st->overflow, &st->capped);
             chi_events += ev;
             draws += dr;
@@ -655,7 +685,8 @@ int oracle_run(const oracle_problem *p, double dt, int32_t n_steps, int32_t *cou
             for (int c = 0; c < ncell; ++c) {
                 uint64_t ev, dr;
                 double lt;
-                chi_cell_step(p, c, p->mesh_w[c], p->mesh_h[c], counts + off[c], dchi, step, 2u,
+                const oracle_problem pc = cell_view(p, c);
+                chi_cell_step(&pc, c, p->mesh_w[c], p->mesh_h[c], counts + off[c], dchi, step, 2u,
                               &ev, &dr, &lt, &st->overflow, &st->capped);
                 chi_events += ev;
                 draws += dr;

@@ -157,6 +157,38 @@ def config_notch(side: int = 64, dt: float = 0.1, n_steps: int = 200, seed: int 
                         name=f"notch (paper's model): square {side}x{side}, 4x4 voxels")
 
 
+def config_multifidelity(side: int = 64, rim: int = 4, dt: float = 0.1, n_steps: int = 200,
+                         seed: int = 7, params: dict | None = None) -> dict:
+    """The paper's multi-fidelity use (Discussion): detailed modules where
+    cells signal, coarse ones where little happens.  Cells within `rim` of
+    the tissue's border run the paper's model on 4 x 4 voxels (model 0); the
+    interior cells are well mixed (one voxel of the cell's whole volume,
+    16 h^3), so their NICD-promoter binding constant per voxel is k_a / 16h^3
+    (model 1) and there is no intra-cell diffusion.  The signalling rate is
+    the same for every cell."""
+    m = model_notch_paper()
+    c = dict(NOTCH_PAPER, **(params or {}))
+    ncell = side * side
+    yy, xx = np.divmod(np.arange(ncell), side)
+    edge = np.minimum(np.minimum(xx, side - 1 - xx), np.minimum(yy, side - 1 - yy))
+    fine = edge < rim
+    w = np.where(fine, 4, 1).astype(np.int32)
+    x0 = []
+    for f in fine:
+        v = np.zeros((16 if f else 1, 4), np.int32)
+        v[10 if f else 0, 2] = 1  # the promoter: voxel (2, 2), or the single voxel
+        x0.append(v)
+    rates = [c["t_D"], c["k_a"], c["k_d"], c["d"], c["d"]]
+    p = make_problem(m, lattice=0, nx=side, ny=side, mesh_w=w, mesh_h=w, rates=rates,
+                     trans_rate=c["k_N"], diffusion=[c["D"], c["D"], 0.0, 0.0],
+                     init_counts=np.concatenate(x0), seed=seed, dt=dt, n_steps=n_steps,
+                     name=f"multi-fidelity notch: square {side}x{side}, 4x4 rim of {rim}, 1x1 inside")
+    coarse = dict(reactants=m["reactants"], stoich=m["stoich"],
+                  rates=[c["t_D"], c["k_a"] / 16.0, c["k_d"], c["d"], c["d"]],
+                  diffusion=[0.0, 0.0, 0.0, 0.0])
+    return with_models(p, [coarse], np.where(fine, 0, 1))
+
+
 def make_problem(model: dict, *, lattice: int, nx: int, ny: int, mesh_w, mesh_h,
                  rates, trans_rate: float, diffusion, init_counts, seed: int,
                  sim_id: int = 0, start_step: int = 0, dt: float = 0.1,
@@ -181,6 +213,24 @@ def make_problem(model: dict, *, lattice: int, nx: int, ny: int, mesh_w, mesh_h,
         start_step=int(start_step), event_cap=int(event_cap),
         dt=float(dt), n_steps=int(n_steps),
         species=model["species"], signal=model.get("signal", "trans"))
+
+
+def with_models(problem: dict, models: list, cell_model) -> dict:
+    """Per-cell networks: `models` are networks 1..K-1 over the problem's
+    species (dicts with reactants, stoich, rates, diffusion; model 0 is the
+    problem's own network and its S reaction serves every cell) and
+    cell_model[c] picks each cell's."""
+    S = problem["n_species"]
+    p = dict(problem)
+    p["models"] = [dict(reactants=np.asarray(m["reactants"], np.int32).reshape(-1, 2),
+                        stoich=np.asarray(m["stoich"], np.int32).reshape(-1, S),
+                        rates=np.asarray(m["rates"], np.float64).reshape(-1),
+                        diffusion=np.broadcast_to(np.asarray(m["diffusion"], np.float64), (S,)).copy())
+                   for m in models]
+    p["cell_model"] = np.asarray(cell_model, dtype=np.int32).reshape(-1).copy()
+    assert p["cell_model"].size == p["nx"] * p["ny"]
+    assert p["cell_model"].min() >= 0 and p["cell_model"].max() <= len(models)
+    return p
 
 
 def n_voxels(problem: dict) -> int:

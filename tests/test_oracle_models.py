@@ -1,0 +1,76 @@
+"""Pins for the oracle's per-cell models (different networks updating
+different cells: detailed modules where cells signal, coarser ones where
+little happens; Discussion).  CPU only."""
+import math
+
+import numpy as np
+from scipy import stats
+
+import refmath
+from paper_1806_10889_amd import workloads as W
+
+
+def _bd_law(k, gamma, x0, t, n=160):
+    q = math.exp(-gamma * t)
+    pmf = np.convolve(stats.binom.pmf(np.arange(0, x0 + 1), x0, q),
+                      stats.poisson.pmf(np.arange(0, n), (k / gamma) * (1 - q)))[:n]
+    return pmf
+
+
+def test_equal_models_give_the_single_model_bits(oracle_lib):
+    p = W.config2(side=7, n_steps=6)
+    cm = np.random.default_rng(1).integers(0, 3, 49)
+    same = dict(reactants=p["reactants"], stoich=p["stoich"], rates=p["rates"],
+                diffusion=p["diffusion"])
+    q = W.with_models(p, [same, same], cm)
+    a = oracle_lib.run(p, p["dt"], 6, trace=True)
+    b = oracle_lib.run(q, p["dt"], 6, trace=True)
+    assert np.array_equal(a.counts, b.counts)
+    assert np.array_equal(a.chi_trace_t, b.chi_trace_t) and a.draws == b.draws
+
+
+def test_each_cell_follows_its_own_models_law(oracle_lib):
+    """Birth-death cells with three models (two rate sets and a pure death
+    with one reaction): each group's counts follow its own transient law;
+    swapping the models' rates is rejected."""
+    k0, g0, k1, g1, g2 = 5.0, 0.5, 20.0, 2.0, 1.0
+    x0, dt, n, side = 20, 0.1, 15, 90
+    p = W.birth_death(k0, g0, x0, nx=side, ny=side, dt=dt, n_steps=n, seed=19)
+    m = W.model_bd()
+    m1 = dict(reactants=m["reactants"], stoich=m["stoich"], rates=[k1, g1], diffusion=[0.0])
+    m2 = dict(reactants=m["reactants"][1:], stoich=m["stoich"][1:], rates=[g2], diffusion=[0.0])
+    cm = np.arange(side * side) % 3
+    q = W.with_models(p, [m1, m2], cm)
+    x = oracle_lib.run(q, dt, n).counts.astype(np.int64)
+    t = dt * n
+    for g, (k, gamma) in enumerate([(k0, g0), (k1, g1), (0.0, g2)]):
+        xs = x[cm == g]
+        pmf = _bd_law(k, gamma, x0, t)
+        pval, _, _ = refmath.chisquare_pvalue(np.bincount(xs, minlength=160)[:160], pmf * xs.size)
+        assert pval > 0.01, g
+        # the other models' laws do not fit this group
+        for h, (kk, gg) in enumerate([(k0, g0), (k1, g1), (0.0, g2)]):
+            if h != g:
+                other = _bd_law(kk, gg, x0, t)
+                pv, _, _ = refmath.chisquare_pvalue(np.bincount(xs, minlength=160)[:160],
+                                                    other * xs.size)
+                assert pv < 1e-6, (g, h)
+    # pure death never grows
+    assert (x[cm == 2] <= x0).all()
+
+
+def test_multi_fidelity_notch_conservation(oracle_lib):
+    """The paper's model with detailed (4x4) cells at the tissue's rim and
+    well-mixed (1x1) cells inside: with transcription and decay off, D + I + B
+    is conserved across the resolutions (signalling between a 4x4 and a 1x1
+    cell included) and every cell keeps one promoter."""
+    p = W.config_multifidelity(side=8, rim=2, n_steps=6, params=dict(t_D=0.0, d=0.0))
+    rng = np.random.default_rng(4)
+    x = p["init_counts"]
+    x[:, 0] = rng.integers(0, 15, size=x.shape[0])
+    x[:, 1] = rng.integers(0, 4, size=x.shape[0])
+    r = oracle_lib.run(p, p["dt"], 6)
+    assert r.s_events > 0 and r.chi_events > 0
+    c = r.counts.reshape(-1, 4)
+    assert c[:, [0, 1, 3]].sum() == x[:, [0, 1, 3]].sum()
+    assert c[:, 2].sum() + c[:, 3].sum() == 64
