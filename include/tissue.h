@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define TISSUE_ABI_VERSION 1u
+#define TISSUE_ABI_VERSION 2u
 
 enum {
     TISSUE_OK = 0,
@@ -96,6 +96,26 @@ typedef struct tissue tissue_t;
 typedef struct tissue_batch tissue_batch_t;
 
 /*
+ * One more intracellular network over the tissue's species, for per-cell
+ * models (the paper's Discussion: detailed modules where cells signal,
+ * coarser ones where little happens; in the network file each cell names
+ * its own model, Fig. 2).  The tables follow the descriptor's own reaction
+ * tables below, with the same rules and limits; the channel order of a cell
+ * is its own network's (reactions, then its diffusing species in species
+ * order).  S, the seed and the counters are the tissue's, whatever the
+ * cells' networks.
+ */
+typedef struct {
+    uint32_t n_reactions;     /* 0..TISSUE_MAX_REACTIONS                        */
+    const int32_t *reactants; /* [n_reactions][2]                               */
+    const int32_t *stoich;    /* [n_reactions][n_species]                       */
+    const double *rates;      /* [n_reactions]                                  */
+    const double *diffusion;  /* [n_species]                                    */
+} tissue_model_t;
+
+#define TISSUE_MAX_MODELS 7   /* extra networks per tissue (8 with its own)     */
+
+/*
  * Tissue descriptor.  Cells: i = y*nx + x (hex: axial q = x, r = y, rhombus).
  * Square directions 0 +x, 1 +y, 2 -x, 3 -y; hex 0 E(+1,0), 1 SE(0,+1),
  * 2 SW(-1,+1), 3 W(-1,0), 4 NW(0,-1), 5 NE(+1,-1); open boundaries.
@@ -128,6 +148,11 @@ typedef struct {
     uint32_t start_step;      /* global index of the next step (resume)         */
     uint32_t event_cap;       /* events per unit-step; 0 = TISSUE_DEFAULT_EVENT_CAP */
     uint32_t trace_steps;     /* steps of trace kept when TISSUE_FLAG_TRACE     */
+    uint32_t n_models;        /* 0..TISSUE_MAX_MODELS extra networks; 0: every
+                                 cell runs the network above                    */
+    const tissue_model_t *models; /* [n_models]: network m is models[m - 1]     */
+    const uint8_t *cell_model;    /* [nx*ny] each cell's network, 0..n_models
+                                     (0: the network above); NULL: all 0        */
 } tissue_desc_t;
 
 typedef struct {
@@ -138,10 +163,11 @@ typedef struct {
     uint32_t overflow;        /* nonzero: a count left [0, 2^26)                */
     uint32_t capped;          /* nonzero: a unit-step hit event_cap             */
     uint32_t n_cells, n_edges, n_voxels; /* n_edges: edges of the S operator (0 without S) */
-    uint32_t jit;             /* nonzero: chi runs kernels compiled for this network */
+    uint32_t jit;             /* nonzero: chi runs kernels compiled for the tissue's
+                                 networks (every one of them)                   */
 } tissue_stats_t;
 
-/* Validate d and compile the chi kernels for its network's structure
+/* Validate d and compile the chi kernels for its networks' structures
  * without loading them (needs no device).  TISSUE_EDEVICE with the compiler
  * log in tissue_last_error() if the compilation fails. */
 int tissue_network_check(const tissue_desc_t *d);

@@ -366,6 +366,7 @@ __device__ __forceinline__ int jump_direction(double resid, double a1, int deg)
 // Per-item uniform data of a tissue.
 struct ItemCtx {
     const DevTissue *T;
+    const DevModel *M;   // the item's network
     int32_t *counts;
     int S;
     uint32_t first, count, step, key0, key1, tagword, cap;
@@ -376,6 +377,7 @@ __device__ __forceinline__ ItemCtx item_ctx(const DevTissue *const *tbl, const C
 {
     ItemCtx c;
     c.T = tbl[uni(item.tissue)];
+    c.M = c.T->models + uni(item.model);
     c.counts = c.T->counts;
     c.S = uni(c.T->model.n_species);
     c.first = uni(item.first);
@@ -432,8 +434,8 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
         const ChiItem item = items[it];
         const ItemCtx c = item_ctx(tbl, item, kstep, tag);
         NET net;
-        net.load(c.T->model);
-        load_channel_table<NET>(tab, c.T->model);
+        net.load(*c.M);
+        load_channel_table<NET>(tab, *c.M);
         const int S = NET::kFixedSpecies ? NET::SM : c.S;
         double *tree = reinterpret_cast<double *>(lds) + lane;  // [2P][stride]
         int32_t *cnt = reinterpret_cast<int32_t *>(lds + (size_t)2 * P * stride * 8) + lane;
@@ -661,8 +663,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         const ChiItem item = items[it];
         const ItemCtx c = item_ctx(tbl, item, kstep, tag);
         NET net;
-        net.load(c.T->model);
-        load_channel_table<NET>(tab, c.T->model);
+        net.load(*c.M);
+        load_channel_table<NET>(tab, *c.M);
         const int S = NET::kFixedSpecies ? NET::SM : c.S;
 
         const bool has_cell = row < (int)c.count;
@@ -863,8 +865,8 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
         const ChiItem item = items[it];
         const ItemCtx c = item_ctx(tbl, item, kstep, tag);
         NET net;
-        net.load(c.T->model);
-        load_channel_table<NET>(tab, c.T->model);
+        net.load(*c.M);
+        load_channel_table<NET>(tab, *c.M);
         const int S = NET::kFixedSpecies ? NET::SM : c.S;
         // leaf pairs: pair k of this lane at lds + (k * stride + lane) * 16
         double *leafp = reinterpret_cast<double *>(lds) + 2 * lane;
@@ -1027,7 +1029,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
         }
         if (active && retry) {
             const uint32_t at = atomicAdd(retry_count, 1u);
-            retry_items[at] = ChiItem{item.tissue, c.first + (uint32_t)lane, 1u, 0u};
+            retry_items[at] = ChiItem{item.tissue, c.first + (uint32_t)lane, 1u, item.model};
         } else if (active) {
             const int n = V * S;
             for (int i = 0; i < n; ++i) c.counts[gbase + i] = (int32_t)cnt[i * stride];

@@ -171,9 +171,10 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0 && x <= kMaxR
 // plan: everything tissue_create derives from the descriptor on the host
 // ---------------------------------------------------------------------------
 
-// cells of one leaf-count class P: cell_list[first, first + count)
+// cells of one leaf-count class P and one network: cell_list[first, first + count)
 struct ChiGroupHost {
     int P;
+    int model;
     uint32_t first, count;
 };
 
@@ -186,11 +187,13 @@ int lane_cells_per_item(int P, int S)
     return cpi;
 }
 
-// items of a class: up to cpi cells each, tagged with the tissue index
-void cut_items(uint32_t tissue, uint32_t first, uint32_t count, int cpi, std::vector<ChiItem> &out)
+// items of a class: up to cpi cells each, tagged with the tissue index and
+// the cells' network
+void cut_items(uint32_t tissue, const ChiGroupHost &g, int cpi, std::vector<ChiItem> &out)
 {
-    for (uint32_t o = 0; o < count; o += (uint32_t)cpi)
-        out.push_back(ChiItem{tissue, first + o, std::min<uint32_t>((uint32_t)cpi, count - o), 0});
+    for (uint32_t o = 0; o < g.count; o += (uint32_t)cpi)
+        out.push_back(ChiItem{tissue, g.first + o, std::min<uint32_t>((uint32_t)cpi, g.count - o),
+                              (uint32_t)g.model});
 }
 
 struct Plan {
@@ -204,67 +207,48 @@ struct Plan {
     bool has_s = false;
     std::vector<ChiGroupHost> chi;
     std::vector<std::vector<SItem>> s_passes;
-    DevModel model{};
-    std::string net_key;                // structure of the network (cache key)
-    const JitKernels *jit = nullptr;    // compiled-network chi kernels, if any
+    // the cells' networks: [0] is the descriptor's own (with the S reaction),
+    // then the extra models; per network its structure (cache key) and its
+    // compiled chi kernels, if any
+    std::vector<DevModel> models;
+    std::vector<std::string> net_keys;
+    std::vector<const JitKernels *> jits;
+    bool all_jit = false;               // every network has compiled kernels
     uint32_t trace_steps = 0;
     bool strang = false;                // TISSUE_FLAG_STRANG
     // byte offsets inside dev_buf
     size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
-           off_cells = 0, off_edges = 0, off_chi = 0, off_s = 0, off_ctl = 0, off_trace = 0,
+           off_cells = 0, off_edges = 0, off_models = 0, off_chi = 0, off_s = 0, off_ctl = 0,
+           off_trace = 0,
            off_retry = 0, bytes = 0;
     size_t n_chi_items = 0, n_s_items = 0;
 };
 
-int build_plan(const tissue_desc_t *d, Plan &p)
+// One network's reaction and diffusion tables, validated and packed into M
+// (n_species S; the S-reaction fields are left to the caller).
+int build_model(int S, uint32_t n_reactions, const int32_t *reactants, const int32_t *stoich,
+                const double *rates, const double *diffusion, DevModel &M)
 {
-    if (!d) return fail(TISSUE_EINVAL, "null descriptor");
-    if (d->abi_version != TISSUE_ABI_VERSION) return fail(TISSUE_EINVAL, "abi_version mismatch");
-    if (d->lattice != TISSUE_LATTICE_SQUARE && d->lattice != TISSUE_LATTICE_HEX)
-        return fail(TISSUE_EINVAL, "lattice must be 0 (square) or 1 (hex)");
-    if (d->nx < 1 || d->ny < 1 || (uint64_t)d->nx * d->ny > (1u << 24))
-        return fail(TISSUE_EINVAL, "nx, ny must be >= 1 with nx*ny <= 2^24");
-    if (d->n_species < 1 || d->n_species > TISSUE_MAX_SPECIES)
-        return fail(TISSUE_EINVAL, "n_species must be in 1..8");
-    if (d->n_reactions > TISSUE_MAX_REACTIONS) return fail(TISSUE_EINVAL, "n_reactions must be <= 16");
-    if (d->sim_id >= (1u << 30)) return fail(TISSUE_EINVAL, "sim_id must be < 2^30");
-    if (!d->init_counts) return fail(TISSUE_EINVAL, "init_counts is null");
-    if ((d->mesh_w == nullptr) != (d->mesh_h == nullptr))
-        return fail(TISSUE_EINVAL, "mesh_w and mesh_h must both be given or both be null");
-    if (d->flags & ~(TISSUE_FLAG_TRACE | TISSUE_FLAG_NO_JIT | TISSUE_FLAG_STRANG |
-                     TISSUE_FLAG_SIGNAL_FIRST_ORDER))
-        return fail(TISSUE_EINVAL, "unknown bits in flags");
-    if ((d->flags & TISSUE_FLAG_TRACE) && d->trace_steps < 1)
-        return fail(TISSUE_EINVAL, "trace needs trace_steps >= 1");
-    const int S = (int)d->n_species, R = (int)d->n_reactions;
-    if (R > 0 && (!d->reactants || !d->stoich || !d->rates))
-        return fail(TISSUE_EINVAL, "reaction tables are null");
-    if (!d->diffusion) return fail(TISSUE_EINVAL, "diffusion is null");
-
-    p.lattice = d->lattice;
-    p.nx = d->nx;
-    p.ny = d->ny;
-    p.ncell = d->nx * d->ny;
-    p.S = (uint32_t)S;
-
-    // model
-    DevModel &M = p.model;
+    if (n_reactions > TISSUE_MAX_REACTIONS) return fail(TISSUE_EINVAL, "n_reactions must be <= 16");
+    const int R = (int)n_reactions;
+    if (R > 0 && (!reactants || !stoich || !rates)) return fail(TISSUE_EINVAL, "reaction tables are null");
+    if (!diffusion) return fail(TISSUE_EINVAL, "diffusion is null");
     M.n_species = S;
     M.n_reactions = R;
     for (int r = 0; r < R; ++r) {
-        const int a = d->reactants[2 * r], b = d->reactants[2 * r + 1];
+        const int a = reactants[2 * r], b = reactants[2 * r + 1];
         if (a < -1 || a >= S || b < -1 || b >= S) return fail(TISSUE_EINVAL, "reactant index out of range");
-        if (!finite_nonneg(d->rates[r])) return fail(TISSUE_EINVAL, "rates must be finite, >= 0 and <= 1e12");
+        if (!finite_nonneg(rates[r])) return fail(TISSUE_EINVAL, "rates must be finite, >= 0 and <= 1e12");
         // canonical order: a first reactant, b second or -1
         int ra = a, rb = b;
         if (ra < 0) std::swap(ra, rb);
         M.reac_a[r] = (int8_t)ra;
         M.reac_b[r] = (int8_t)rb;
-        M.rates[r] = d->rates[r];
+        M.rates[r] = rates[r];
         uint32_t lo = 0, hi = 0;
         int nchg = 0;
         for (int s = 0; s < S; ++s) {
-            const int delta = d->stoich[r * S + s];
+            const int delta = stoich[r * S + s];
             if (delta == 0) continue;
             if (delta < -15 || delta > 15) return fail(TISSUE_EINVAL, "stoich entries must be in -15..15");
             const int supplied = (a == s) + (b == s);
@@ -287,10 +271,10 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     }
     M.n_diff = 0;
     for (int s = 0; s < S; ++s) {
-        if (!finite_nonneg(d->diffusion[s])) return fail(TISSUE_EINVAL, "diffusion must be finite, >= 0 and <= 1e12");
-        if (d->diffusion[s] > 0.0) {
+        if (!finite_nonneg(diffusion[s])) return fail(TISSUE_EINVAL, "diffusion must be finite, >= 0 and <= 1e12");
+        if (diffusion[s] > 0.0) {
             M.diff_species[M.n_diff] = (int8_t)s;
-            M.diff_rate[M.n_diff] = d->diffusion[s];
+            M.diff_rate[M.n_diff] = diffusion[s];
             ++M.n_diff;
         }
     }
@@ -298,6 +282,50 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         M.diff_species[q] = 0;
         M.diff_rate[q] = 0.0;
     }
+    return TISSUE_OK;
+}
+
+int build_plan(const tissue_desc_t *d, Plan &p)
+{
+    if (!d) return fail(TISSUE_EINVAL, "null descriptor");
+    if (d->abi_version != TISSUE_ABI_VERSION) return fail(TISSUE_EINVAL, "abi_version mismatch");
+    if (d->lattice != TISSUE_LATTICE_SQUARE && d->lattice != TISSUE_LATTICE_HEX)
+        return fail(TISSUE_EINVAL, "lattice must be 0 (square) or 1 (hex)");
+    if (d->nx < 1 || d->ny < 1 || (uint64_t)d->nx * d->ny > (1u << 24))
+        return fail(TISSUE_EINVAL, "nx, ny must be >= 1 with nx*ny <= 2^24");
+    if (d->n_species < 1 || d->n_species > TISSUE_MAX_SPECIES)
+        return fail(TISSUE_EINVAL, "n_species must be in 1..8");
+    if (d->sim_id >= (1u << 30)) return fail(TISSUE_EINVAL, "sim_id must be < 2^30");
+    if (!d->init_counts) return fail(TISSUE_EINVAL, "init_counts is null");
+    if ((d->mesh_w == nullptr) != (d->mesh_h == nullptr))
+        return fail(TISSUE_EINVAL, "mesh_w and mesh_h must both be given or both be null");
+    if (d->flags & ~(TISSUE_FLAG_TRACE | TISSUE_FLAG_NO_JIT | TISSUE_FLAG_STRANG |
+                     TISSUE_FLAG_SIGNAL_FIRST_ORDER))
+        return fail(TISSUE_EINVAL, "unknown bits in flags");
+    if ((d->flags & TISSUE_FLAG_TRACE) && d->trace_steps < 1)
+        return fail(TISSUE_EINVAL, "trace needs trace_steps >= 1");
+    const int S = (int)d->n_species;
+    if (d->n_models > TISSUE_MAX_MODELS) return fail(TISSUE_EINVAL, "n_models must be <= 7");
+    if (d->n_models > 0 && !d->models) return fail(TISSUE_EINVAL, "models is null");
+
+    p.lattice = d->lattice;
+    p.nx = d->nx;
+    p.ny = d->ny;
+    p.ncell = d->nx * d->ny;
+    p.S = (uint32_t)S;
+
+    // networks: the descriptor's own, then the extra models
+    p.models.assign(1 + d->n_models, DevModel{});
+    int rc = build_model(S, d->n_reactions, d->reactants, d->stoich, d->rates, d->diffusion,
+                         p.models[0]);
+    if (rc != TISSUE_OK) return rc;
+    for (uint32_t m = 0; m < d->n_models; ++m) {
+        const tissue_model_t &md = d->models[m];
+        rc = build_model(S, md.n_reactions, md.reactants, md.stoich, md.rates, md.diffusion,
+                         p.models[1 + m]);
+        if (rc != TISSUE_OK) return fail(rc, "model " + std::to_string(m + 1) + ": " + g_last_error);
+    }
+    DevModel &M = p.models[0];
     const bool first_order = (d->flags & TISSUE_FLAG_SIGNAL_FIRST_ORDER) != 0;
     p.has_s = first_order ? d->trans_d >= 0 : d->trans_n >= 0;
     M.signal_order = first_order ? 1 : 2;
@@ -319,7 +347,16 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         M.trans_rate = 0.0;
     }
 
-    p.net_key = network_key(M);
+    for (size_t m = 1; m < p.models.size(); ++m) {  // the S reaction is the tissue's
+        DevModel &X = p.models[m];
+        X.trans_n = M.trans_n;
+        X.trans_d = M.trans_d;
+        X.trans_i = M.trans_i;
+        X.signal_order = M.signal_order;
+        X.trans_rate = M.trans_rate;
+    }
+    for (const DevModel &X : p.models) p.net_keys.push_back(network_key(X));
+    p.jits.assign(p.models.size(), nullptr);
 
     // cells and voxels
     p.wh.resize(2 * (size_t)p.ncell);
@@ -343,11 +380,16 @@ int build_plan(const tissue_desc_t *d, Plan &p)
 
     // chi: cells grouped by leaf count P (largest cells first); work items
     // are cut per launch mode when a launch plan is made
-    std::map<int, std::vector<int32_t>> by_p;
-    for (uint32_t c = 0; c < p.ncell; ++c) by_p[pow2_at_least(p.wh[2 * c] * p.wh[2 * c + 1])].push_back((int32_t)c);
+    std::map<std::pair<int, int>, std::vector<int32_t>> by_p;  // (P, network) -> cells
+    for (uint32_t c = 0; c < p.ncell; ++c) {
+        const int m = d->cell_model ? d->cell_model[c] : 0;
+        if (m > (int)d->n_models) return fail(TISSUE_EINVAL, "cell_model entries must be <= n_models");
+        by_p[{pow2_at_least(p.wh[2 * c] * p.wh[2 * c + 1]), -m}].push_back((int32_t)c);
+    }
     for (auto it = by_p.rbegin(); it != by_p.rend(); ++it) {
         ChiGroupHost g;
-        g.P = it->first;
+        g.P = it->first.first;
+        g.model = -it->first.second;
         g.first = (uint32_t)p.cell_list.size();
         g.count = (uint32_t)it->second.size();
         p.cell_list.insert(p.cell_list.end(), it->second.begin(), it->second.end());
@@ -436,6 +478,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     p.off_wh = take((size_t)p.ncell * 2);
     p.off_cells = take((size_t)p.ncell * 4);
     p.off_edges = take((size_t)p.nedge * sizeof(EdgeRec));
+    p.off_models = take(p.models.size() * sizeof(DevModel));
     p.off_chi = take(p.n_chi_items * sizeof(ChiItem));
     p.off_s = take(p.n_s_items * sizeof(SItem));
     p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue words u32[8]
@@ -488,14 +531,16 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
     std::map<Key, Group> groups;
     for (size_t i = 0; i < members.size(); ++i) {
         const Plan &p = *members[i];
-        int SM, RM, NDM;
-        chi_variant((int)p.S, p.model.n_reactions, p.model.n_diff, SM, RM, NDM);
-        const std::string net = p.jit ? "J" + p.net_key
-                                      : "G" + std::to_string(SM) + "," + std::to_string(RM) + "," +
-                                            std::to_string(NDM);
         for (const ChiGroupHost &g : p.chi) {
+            const DevModel &M = p.models[(size_t)g.model];
+            const JitKernels *jit = p.jits[(size_t)g.model];
+            int SM, RM, NDM;
+            chi_variant((int)p.S, M.n_reactions, M.n_diff, SM, RM, NDM);
+            const std::string net = jit ? "J" + p.net_keys[(size_t)g.model]
+                                        : "G" + std::to_string(SM) + "," + std::to_string(RM) + "," +
+                                              std::to_string(NDM);
             Group &G = groups[Key{g.P, net}];
-            G.jit = p.jit;
+            G.jit = jit;
             G.SM = SM;
             G.RM = RM;
             G.NDM = NDM;
@@ -540,7 +585,7 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         L.lds = chi_lds_bytes(mode, k.P, G.max_s, L.cells_per_item);
         L.retry_lds = chi_lds_bytes(kChiLane, k.P, G.max_s, 1);
         const size_t off = items_out.size();
-        for (auto &m : G.cells) cut_items(m.first, m.second->first, m.second->count, L.cells_per_item, items_out);
+        for (auto &m : G.cells) cut_items(m.first, *m.second, L.cells_per_item, items_out);
         L.items = reinterpret_cast<const ChiItem *>(off);
         L.n_items = (uint32_t)(items_out.size() - off);
         launches.push_back(L);
@@ -708,22 +753,29 @@ struct LaunchPlan {
         // the chi launches of one (half-)step, counter tag `tag`.  Classes
         // touch disjoint cells, so with one workgroup per item (no shared
         // queue words) the captured step graph runs them as parallel
-        // branches: the first on `st`, the others on side streams forked from
-        // and joined back into it.  Eager launches (timed runs, serving) keep
-        // them in order on the caller's stream.
-        size_t active = 0;
-        for (const ChiLaunch &L : chi) active += L.n_items > 0;
-        const bool fork = !ev && !persistent && active > 1 && st == capture_stream;
+        // branches: one branch on `st`, the others on side streams forked
+        // from and joined back into it.  The compact-layout launches share
+        // the redo list and its queue words, so they all stay in order on
+        // `st`.  Eager launches (timed runs, serving) keep every launch in
+        // order on the caller's stream.
+        size_t n16 = 0, nother = 0;
+        for (const ChiLaunch &L : chi)
+            if (L.n_items > 0) (L.mode == kChiLane16 ? n16 : nother)++;
+        const size_t branches = nother + (n16 > 0);
+        const bool fork = !ev && !persistent && branches > 1 && st == capture_stream;
         if (fork) {
-            const int rc = ensure_side(active);
+            const int rc = ensure_side(branches);
             if (rc != TISSUE_OK) return rc;
         }
         auto chi_pass = [&](double dchi, uint32_t k, uint32_t tag) -> int {
             if (fork) {
                 HIP_TRY(hipEventRecord(fork_ev, st));
-                size_t b = 0;
+                for (const ChiLaunch &L : chi)
+                    if (L.n_items > 0 && L.mode == kChiLane16)
+                        HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag));
+                size_t b = n16 > 0;  // branch 0 (`st`) is taken when it ran the compact launches
                 for (const ChiLaunch &L : chi) {
-                    if (L.n_items == 0) continue;
+                    if (L.n_items == 0 || L.mode == kChiLane16) continue;
                     if (b == 0) {
                         HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag));
                     } else {
@@ -950,7 +1002,8 @@ int tissue_network_check(const tissue_desc_t *d)
     const int rc = build_plan(d, p);
     if (rc != TISSUE_OK) return rc;
     std::string err;
-    if (jit_compile_check(p.model, err) != 0) return fail(TISSUE_EDEVICE, err);
+    for (const DevModel &M : p.models)
+        if (jit_compile_check(M, err) != 0) return fail(TISSUE_EDEVICE, err);
     return TISSUE_OK;
 }
 
@@ -980,9 +1033,15 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     const int cus = device_cus();
     if (cus <= 0) return fail(TISSUE_EDEVICE, "no HIP device");
     if (!(d->flags & TISSUE_FLAG_NO_JIT)) {
-        // the network's own chi kernels; the generic ones serve if that fails
+        // each network's own chi kernels; the generic ones serve a network
+        // whose compilation fails
         std::string err;
-        if (jit_kernels(p.model, &p.jit, err) != 0) p.jit = nullptr;
+        p.all_jit = true;
+        for (size_t m = 0; m < p.models.size(); ++m)
+            if (jit_kernels(p.models[m], &p.jits[m], err) != 0) {
+                p.jits[m] = nullptr;
+                p.all_jit = false;
+            }
     }
 
     unsigned char *base = t->dev;
@@ -1009,7 +1068,8 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     R.step_base = d->start_step;
     R.event_cap = d->event_cap ? d->event_cap : TISSUE_DEFAULT_EVENT_CAP;
     R.trace_steps = p.trace_steps ? p.trace_steps : 1;
-    R.model = p.model;
+    R.models = reinterpret_cast<const DevModel *>(base + p.off_models);
+    R.model = p.models[0];
     t->steps_done = d->start_step;
 
     // upload (synchronous on the tissue's stream): the buffer's image up to
@@ -1032,6 +1092,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
         std::memcpy(h + p.off_wh, p.wh.data(), p.wh.size());
         std::memcpy(h + p.off_cells, p.cell_list.data(), p.cell_list.size() * 4);
         if (p.nedge) std::memcpy(h + p.off_edges, p.edges.data(), p.edges.size() * sizeof(EdgeRec));
+        std::memcpy(h + p.off_models, p.models.data(), p.models.size() * sizeof(DevModel));
         std::memset(h + p.off_chi, 0, p.off_s - p.off_chi);
         if (!s_all.empty()) std::memcpy(h + p.off_s, s_all.data(), s_all.size() * sizeof(SItem));
         std::memset(h + p.off_ctl, 0, 64);
@@ -1156,7 +1217,7 @@ int tissue_stats_decode(tissue_t *t, const void *block, tissue_stats_t *out)
     out->n_cells = t->plan.ncell;
     out->n_edges = t->plan.nedge;
     out->n_voxels = t->plan.nvox;
-    out->jit = t->plan.jit != nullptr;
+    out->jit = t->plan.all_jit;
     return TISSUE_OK;
 }
 

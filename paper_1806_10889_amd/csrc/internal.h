@@ -64,22 +64,23 @@ struct DevTissue {
     unsigned long long *tr_chi_t;
     uint32_t *tr_s_ev;            // [trace_steps][n_edges] or null
     unsigned long long *tr_s_t;
+    const DevModel *models;       // [n_models] chi networks of the cells; [0] equals `model`
     uint64_t seed;
     uint32_t n_cells, n_edges;
     uint32_t sim_id;
     uint32_t step_base;           // global index of step k = 0 of the next launch group
     uint32_t event_cap;
     uint32_t trace_steps;
-    DevModel model;
+    DevModel model;               // the tissue's own network and the S reaction
 };
 
-// up to 64 cells of one tissue, all with the same leaf count P:
-// cells cell_list[first .. first + count)
+// up to 64 cells of one tissue, all with the same leaf count P and the same
+// network models[model]: cells cell_list[first .. first + count)
 struct ChiItem {
     uint32_t tissue;
     uint32_t first;
     uint32_t count;
-    uint32_t pad;
+    uint32_t model;
 };
 
 // chi kernel variants: one lane per cell (any P); one 16-lane row per cell

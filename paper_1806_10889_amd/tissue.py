@@ -27,7 +27,7 @@ FLAG_NO_JIT = 2
 FLAG_STRANG = 4
 FLAG_SIGNAL_FIRST_ORDER = 8
 STATS_BLOCK_BYTES = 64
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class TissueError(RuntimeError):
@@ -50,6 +50,16 @@ class Desc(C.Structure):
         ("init_counts", C.POINTER(C.c_int32)),
         ("seed", C.c_uint64), ("sim_id", C.c_uint32), ("start_step", C.c_uint32),
         ("event_cap", C.c_uint32), ("trace_steps", C.c_uint32),
+        ("n_models", C.c_uint32), ("models", C.c_void_p), ("cell_model", C.POINTER(C.c_uint8)),
+    ]
+
+
+class Model(C.Structure):
+    """One more intracellular network (per-cell models)."""
+    _fields_ = [
+        ("n_reactions", C.c_uint32),
+        ("reactants", C.POINTER(C.c_int32)), ("stoich", C.POINTER(C.c_int32)),
+        ("rates", C.POINTER(C.c_double)), ("diffusion", C.POINTER(C.c_double)),
     ]
 
 
@@ -181,6 +191,28 @@ class _DescHolder:
                    (FLAG_STRANG if scheme == "strang" else 0) |
                    (FLAG_SIGNAL_FIRST_ORDER if signal == "first_order" else 0))
         d.trace_steps = int(trace_steps)
+        models = p.get("models") or []
+        if models:
+            # networks 1..K-1 over the problem's species; cell_model picks each cell's
+            self.m_tables = []
+            self.m_structs = (Model * len(models))()
+            for m, md in enumerate(models):
+                t = [np.ascontiguousarray(np.asarray(md["reactants"], np.int32).reshape(-1)),
+                     np.ascontiguousarray(np.asarray(md["stoich"], np.int32).reshape(-1)),
+                     np.ascontiguousarray(md["rates"], dtype=np.float64).reshape(-1),
+                     np.ascontiguousarray(md["diffusion"], dtype=np.float64).reshape(-1)]
+                self.m_tables.append(t)
+                ms = self.m_structs[m]
+                ms.n_reactions = int(t[2].size)
+                ms.reactants, ms.stoich = _p(t[0], C.c_int32), _p(t[1], C.c_int32)
+                ms.rates, ms.diffusion = _p(t[2], C.c_double), _p(t[3], C.c_double)
+            cm = np.asarray(p["cell_model"]).reshape(-1)
+            if cm.size != d.nx * d.ny or cm.min() < 0 or cm.max() > 255:
+                raise ValueError("cell_model must give each cell a network index in 0..255")
+            self.cell_model = np.ascontiguousarray(cm, dtype=np.uint8)
+            d.n_models = len(models)
+            d.models = C.cast(self.m_structs, C.c_void_p)
+            d.cell_model = _p(self.cell_model, C.c_uint8)
         self.desc = d
 
 

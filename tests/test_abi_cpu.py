@@ -112,3 +112,40 @@ def test_network_kernels_compile(model):
     from paper_1806_10889_amd import tissue as T
     p = W.random_problem(1, lattice=0, nx=2, ny=2, model=model, mesh=(2, 2))
     T.network_check(p)
+
+
+def test_per_cell_model_validation():
+    """Per-cell models: the extra networks obey the same table rules (the
+    message names the model), cell_model entries stay within n_models, at
+    most 7 extra networks; each extra network adds its table to the buffer."""
+    from paper_1806_10889_amd import tissue as T
+    p = W.config_multifidelity(side=6, rim=1, n_steps=2)
+    base = W.config_notch(side=6, n_steps=2)
+    assert T.required_bytes(p) > 0
+    one = dict(reactants=p["reactants"], stoich=p["stoich"], rates=p["rates"],
+               diffusion=p["diffusion"])
+    assert "cell_model" in bad_of(p, lambda q: q["cell_model"].__setitem__(0, 2))
+    assert "n_models" in bad_of(p, lambda q: q.__setitem__("models", [one] * 8))
+
+    def bad_model(q):
+        m = dict(q["models"][0])
+        r = np.array(m["reactants"]).copy()
+        r[1, 0] = 9
+        m["reactants"] = r
+        q["models"] = [m]
+    assert "model 1" in bad_of(p, bad_model)
+
+    def neg_rate(q):
+        m = dict(q["models"][0])
+        m["rates"] = np.array(m["rates"]) * -1.0
+        q["models"] = [m]
+    assert "model 1" in bad_of(p, neg_rate)
+    # a model's table in the device buffer (aligned, so at least 256 bytes more)
+    q = W.with_models(base, [one], np.zeros(36, np.int32))
+    assert T.required_bytes(q) >= T.required_bytes(base) + 256
+
+
+def test_per_cell_models_compile():
+    """Every network of a multi-fidelity tissue gets compiled chi kernels."""
+    from paper_1806_10889_amd import tissue as T
+    T.network_check(W.config_multifidelity(side=4, rim=1, n_steps=2))

@@ -433,3 +433,25 @@ def test_classes_in_parallel_graph_branches(oracle_lib, scheme, jit):
     for mode in (0, 1, 2, 3):
         g = gpu_run(p, 6, trace=True, persistent=False, graph_chunk=2, chi_mode=mode, jit=jit)
         assert_same(g, o)
+
+
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+def test_compact_launches_with_redo_in_forked_graphs(oracle_lib, scheme):
+    """Compact-layout launches of several leaf-count classes, each handing
+    cells back for the full-width redo, inside step graphs that fork the
+    other classes into parallel branches: the compact launches share the
+    redo list, so they stay in order; same bits as the oracle."""
+    p = W.random_problem(39, lattice=0, nx=9, ny=7, model="nd5", uneven=True, dt=0.05, n_steps=4)
+    p["scheme"] = scheme
+    P = [1 << int(np.ceil(np.log2(w * h))) for w, h in zip(p["mesh_w"], p["mesh_h"])]
+    off = np.concatenate([[0], np.cumsum(p["mesh_w"].astype(np.int64) * p["mesh_h"])])
+    x = p["init_counts"]
+    wide = {}
+    for c, pc in enumerate(P):
+        if pc <= 16 and wide.get(pc, 0) < 2:
+            x[off[c], 0] = 65535
+            wide[pc] = wide.get(pc, 0) + 1
+    assert len(wide) >= 3 and any(pc > 16 for pc in P)
+    o = _oracle(oracle_lib, p, 4)
+    g = gpu_run(p, 4, trace=True, persistent=False, graph_chunk=2, chi_mode=3)
+    assert_same(g, o)
