@@ -62,6 +62,7 @@ class _Problem(C.Structure):
         ("cell_model", C.POINTER(C.c_int32)), ("m_n_reactions", C.POINTER(C.c_int32)),
         ("m_reactants", C.POINTER(C.c_int32)), ("m_stoich", C.POINTER(C.c_int32)),
         ("m_rates", C.POINTER(C.c_double)), ("m_diffusion", C.POINTER(C.c_double)),
+        ("m_signal_rate", C.POINTER(C.c_double)),
     ]
 
 
@@ -212,6 +213,8 @@ def run(problem: dict, dt: float, n_steps: int, counts=None, start_step=None,
         mst = np.zeros((K, 16, S), np.int32)
         mra = np.zeros((K, 16), np.float64)
         mdi = np.zeros((K, S), np.float64)
+        msr = np.array([float(p["trans_rate"])] +
+                       [float(md.get("signal_rate", p["trans_rate"])) for md in p["models"]])
         for m, md in enumerate(allm):
             r = np.asarray(md["reactants"], np.int32).reshape(-1, 2)
             nr[m] = r.shape[0]
@@ -220,7 +223,7 @@ def run(problem: dict, dt: float, n_steps: int, counts=None, start_step=None,
             mra[m, :nr[m]] = np.asarray(md["rates"], np.float64)
             mdi[m] = np.asarray(md["diffusion"], np.float64)
         cm = np.ascontiguousarray(p["cell_model"], dtype=np.int32)
-        keep = [nr, mre, mst, mra, mdi, cm]
+        keep = [nr, mre, mst, mra, mdi, msr, cm]
         pr.n_models = K
         pr.cell_model = _ptr(cm, C.c_int32)
         pr.m_n_reactions = _ptr(nr, C.c_int32)
@@ -228,6 +231,7 @@ def run(problem: dict, dt: float, n_steps: int, counts=None, start_step=None,
         pr.m_stoich = _ptr(mst, C.c_int32)
         pr.m_rates = _ptr(mra, C.c_double)
         pr.m_diffusion = _ptr(mdi, C.c_double)
+        pr.m_signal_rate = _ptr(msr, C.c_double)
     else:
         pr.n_models = 1
     E = lib().oracle_num_edges(C.byref(pr))

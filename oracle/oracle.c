@@ -263,7 +263,9 @@ typedef struct {
      * and cell_model[c] in [0, n_models).  Model m's tables, padded to 16
      * reactions: m_n_reactions[m], m_reactants[m][16][2], m_stoich[m][16][S],
      * m_rates[m][16], m_diffusion[m][S]; model 0 equals the fields above.
-     * S (the trans fields) is the same for every cell. */
+     * The S reaction's species are the same for every cell; under
+     * first-order signalling each molecule signals at its own cell's
+     * model's rate, m_signal_rate[m] (m_signal_rate[0] = trans_rate). */
     int32_t n_models;
     int32_t pad2;
     const int32_t *cell_model;
@@ -272,7 +274,14 @@ typedef struct {
     const int32_t *m_stoich;
     const double *m_rates;
     const double *m_diffusion;
+    const double *m_signal_rate;
 } oracle_problem;
+
+/* First-order signalling rate of cell c's molecules. */
+static double cell_signal_rate(const oracle_problem *p, int c)
+{
+    return p->n_models > 1 ? p->m_signal_rate[p->cell_model[c]] : p->trans_rate;
+}
 
 /* The problem as seen by cell c: its own model's network. */
 static oracle_problem cell_view(const oracle_problem *p, int c)
@@ -498,13 +507,14 @@ static int facing_voxel(int k, int m_from, int m_to)
  * (order 1, the paper's Delta turning into the neighbour's NICD at k_N,
  * Results, Model): c D_i(a) for a in A, then c D_j(b) for b in B. */
 static int edge_channels(const oracle_problem *p, const int32_t *ci, const int32_t *cj,
-                         const int *A, int mA, const int *B, int mB, double *a)
+                         const int *A, int mA, const int *B, int mB, double ki, double kj,
+                         double *a)
 {
     const int S = p->n_species;
     int K = 0;
-    if (p->signal_order == 1) {
-        for (int ia = 0; ia < mA; ++ia) a[K++] = p->trans_rate * (double)ci[A[ia] * S + p->trans_d];
-        for (int ib = 0; ib < mB; ++ib) a[K++] = p->trans_rate * (double)cj[B[ib] * S + p->trans_d];
+    if (p->signal_order == 1) {  /* ki, kj: the rates of cell i's and cell j's molecules */
+        for (int ia = 0; ia < mA; ++ia) a[K++] = ki * (double)ci[A[ia] * S + p->trans_d];
+        for (int ib = 0; ib < mB; ++ib) a[K++] = kj * (double)cj[B[ib] * S + p->trans_d];
         return K;
     }
     for (int ia = 0; ia < mA; ++ia)
@@ -522,7 +532,7 @@ static int edge_channels(const oracle_problem *p, const int32_t *ci, const int32
 
 /* One S step of one edge (i, j) over [0, dt). */
 static void s_edge_step(const oracle_problem *p, int e, int32_t *ci, int32_t *cj,
-                        const int *A, int mA, const int *B, int mB,
+                        const int *A, int mA, const int *B, int mB, double ki, double kj,
                         double dt, uint32_t step,
                         uint64_t *events_out, uint64_t *draws_out, double *last_t_out,
                         uint32_t *overflow, uint32_t *capped)
@@ -533,7 +543,7 @@ static void s_edge_step(const oracle_problem *p, int e, int32_t *ci, int32_t *cj
     uint64_t events = 0;
     for (;;) {
         double a[2 * 64];
-        int K = edge_channels(p, ci, cj, A, mA, B, mB, a);
+        int K = edge_channels(p, ci, cj, A, mA, B, mB, ki, kj, a);
         double a0 = 0.0;
         for (int k = 0; k < K; ++k) a0 = a0 + a[k];
         if (a0 == 0.0) break;
@@ -669,6 +679,7 @@ int oracle_run(const oracle_problem *p, double dt, int32_t n_steps, int32_t *cou
                     uint64_t ev, dr;
                     double lt;
                     s_edge_step(p, e, counts + off[i], counts + off[jj], A, mA, B, mB,
+                                cell_signal_rate(p, i), cell_signal_rate(p, jj),
                                 dt, step, &ev, &dr, &lt, &st->overflow, &st->capped);
                     s_events += ev;
                     draws += dr;

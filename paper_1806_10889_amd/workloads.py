@@ -164,8 +164,12 @@ def config_multifidelity(side: int = 64, rim: int = 4, dt: float = 0.1, n_steps:
     the tissue's border run the paper's model on 4 x 4 voxels (model 0); the
     interior cells are well mixed (one voxel of the cell's whole volume,
     16 h^3), so their NICD-promoter binding constant per voxel is k_a / 16h^3
-    (model 1) and there is no intra-cell diffusion.  The signalling rate is
-    the same for every cell."""
+    (model 1) and there is no intra-cell diffusion.  Signalling: a molecule
+    of a 4 x 4 cell signals to a neighbour only from the 3 voxels of the
+    face group towards it, 3/16 of the cell's volume, while the single voxel
+    of a well-mixed cell is in every face group; so its molecules signal at
+    k_N * 3/16 per face, the fine cell's per-face rate with Delta spread
+    evenly (fast diffusion, D/h^2 = 16 k_N)."""
     m = model_notch_paper()
     c = dict(NOTCH_PAPER, **(params or {}))
     ncell = side * side
@@ -185,7 +189,7 @@ def config_multifidelity(side: int = 64, rim: int = 4, dt: float = 0.1, n_steps:
                      name=f"multi-fidelity notch: square {side}x{side}, 4x4 rim of {rim}, 1x1 inside")
     coarse = dict(reactants=m["reactants"], stoich=m["stoich"],
                   rates=[c["t_D"], c["k_a"] / 16.0, c["k_d"], c["d"], c["d"]],
-                  diffusion=[0.0, 0.0, 0.0, 0.0])
+                  diffusion=[0.0, 0.0, 0.0, 0.0], signal_rate=c["k_N"] * 3.0 / 16.0)
     return with_models(p, [coarse], np.where(fine, 0, 1))
 
 
@@ -217,15 +221,18 @@ def make_problem(model: dict, *, lattice: int, nx: int, ny: int, mesh_w, mesh_h,
 
 def with_models(problem: dict, models: list, cell_model) -> dict:
     """Per-cell networks: `models` are networks 1..K-1 over the problem's
-    species (dicts with reactants, stoich, rates, diffusion; model 0 is the
-    problem's own network and its S reaction serves every cell) and
-    cell_model[c] picks each cell's."""
+    species (dicts with reactants, stoich, rates, diffusion and optionally
+    signal_rate; model 0 is the problem's own network) and cell_model[c]
+    picks each cell's.  The S reaction's species are the problem's; under
+    first-order signalling a cell's molecules signal at its model's
+    signal_rate (default: the problem's trans_rate)."""
     S = problem["n_species"]
     p = dict(problem)
     p["models"] = [dict(reactants=np.asarray(m["reactants"], np.int32).reshape(-1, 2),
                         stoich=np.asarray(m["stoich"], np.int32).reshape(-1, S),
                         rates=np.asarray(m["rates"], np.float64).reshape(-1),
-                        diffusion=np.broadcast_to(np.asarray(m["diffusion"], np.float64), (S,)).copy())
+                        diffusion=np.broadcast_to(np.asarray(m["diffusion"], np.float64), (S,)).copy(),
+                        signal_rate=float(m.get("signal_rate", problem["trans_rate"])))
                    for m in models]
     p["cell_model"] = np.asarray(cell_model, dtype=np.int32).reshape(-1).copy()
     assert p["cell_model"].size == p["nx"] * p["ny"]

@@ -74,3 +74,59 @@ def test_multi_fidelity_notch_conservation(oracle_lib):
     c = r.counts.reshape(-1, 4)
     assert c[:, [0, 1, 3]].sum() == x[:, [0, 1, 3]].sum()
     assert c[:, 2].sum() + c[:, 3].sum() == 64
+
+
+def test_first_order_signal_rate_is_the_senders_models():
+    """Two well-mixed cells on different models, decay inside, first-order
+    signalling: each Delta leaves at its own cell's model's rate.  The
+    sample follows that split law; the law with the two rates swapped
+    (receiver's rate) is rejected."""
+    from scipy import linalg
+    import oracle
+
+    kd, ki, k0, k1 = 0.3, 0.5, 1.6, 0.4
+    m = W.model_notch_paper()
+    x0 = np.zeros((2, 4), np.int32)
+    x0[:, 0] = (4, 3)
+    p = W.make_problem(m, lattice=0, nx=2, ny=1, mesh_w=1, mesh_h=1,
+                       rates=[0.0, 0.0, 0.0, kd, ki], trans_rate=k0,
+                       diffusion=[0.0] * 4, init_counts=x0, seed=73)
+    p = W.with_models(p, [dict(reactants=p["reactants"], stoich=p["stoich"], rates=p["rates"],
+                               diffusion=p["diffusion"], signal_rate=k1)], [0, 1])
+
+    def law(kk, dt, n):
+        def chi(s):
+            out = []
+            for c in range(2):
+                D, I = s[4 * c], s[4 * c + 1]
+                if D:
+                    ns = list(s); ns[4 * c] -= 1; out.append((kd * D, tuple(ns)))
+                if I:
+                    ns = list(s); ns[4 * c + 1] -= 1; out.append((ki * I, tuple(ns)))
+            return out
+
+        def sig(s):
+            out = []
+            for c in range(2):
+                if s[4 * c]:
+                    ns = list(s); ns[4 * c] -= 1; ns[4 * (1 - c) + 1] += 1
+                    out.append((kk[c] * s[4 * c], tuple(ns)))
+            return out
+        x = tuple(int(v) for v in x0.ravel())
+        states, index = refmath.enumerate_states(x, lambda s: chi(s) + sig(s))
+        Ec = linalg.expm(refmath.generator(states, index, chi) * dt)
+        Es = linalg.expm(refmath.generator(states, index, sig) * dt)
+        pv = np.zeros(len(states)); pv[index[x]] = 1.0
+        for _ in range(n):
+            pv = Es @ (Ec @ pv)
+        return states, index, pv
+
+    dt, n, N = 0.5, 3, 20000
+    states, index, pv = law((k0, k1), dt, n)
+    _, _, pw = law((k1, k0), dt, n)
+    obs = np.zeros(len(states))
+    for sim in range(N):
+        p["sim_id"] = sim
+        obs[index[tuple(int(v) for v in oracle.run(p, dt, n).counts)]] += 1
+    assert refmath.chisquare_pvalue(obs, pv * N)[0] > 0.01
+    assert refmath.chisquare_pvalue(obs, pw * N)[0] < 1e-6
