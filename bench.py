@@ -15,7 +15,7 @@ FP64 oracle's rate on a bounded sample on the host cores, the batched form
 (512 tissues in one batch, with its own roofline) and the serving loop
 (Poisson arrivals, continuous batching, p50/p99 latency).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--leg all|plain|batched|serving]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--leg all|plain|uneven|batched|serving|dt|notch|multifidelity]
 """
 from __future__ import annotations
 
@@ -485,6 +485,66 @@ def run_notch(args, torch, T, W):
                                        events_per_s=(st["chi_events"] + st["s_events"]) / el)}
 
 
+def run_multifidelity(args, torch, T, W):
+    """Per-cell models on the paper's model: square tissues whose rim of 4
+    cells keeps 4 x 4 voxels per cell while the interior cells are well
+    mixed (one voxel), against the same tissue with 4 x 4 voxels everywhere.
+    Time to solution over T = 10 s (dt 0.1) on 64 x 64 cells (one step's
+    cost is the rim cells' event chains: latency-bound) and 256 x 256 cells
+    (throughput-bound); over T = 100 s on 64 x 64, how Delta and the
+    promoter state of rim and interior cells compare."""
+    import numpy as np
+
+    def per_cell(p, counts, s):
+        sz = p["mesh_w"].astype(np.int64) * p["mesh_h"]
+        off = np.concatenate([[0], np.cumsum(sz)[:-1]])
+        return np.add.reduceat(counts.reshape(-1, 4)[:, s].astype(np.int64), off)
+
+    rim = 4
+    res = {"rows": []}
+    for side in (64, 256):
+        yy, xx = np.divmod(np.arange(side * side), side)
+        edge = np.minimum(np.minimum(xx, side - 1 - xx), np.minimum(yy, side - 1 - yy))
+        on_rim = edge < rim
+        row = {"cells": side * side, "rim_cells": int(on_rim.sum())}
+        for name, make in (("all_rdme", lambda n: W.config_notch(side=side, dt=0.1, n_steps=n)),
+                           ("multi_fidelity", lambda n: W.config_multifidelity(
+                               side=side, rim=rim, dt=0.1, n_steps=n))):
+            p = make(100)
+            t = T.Tissue(p, device="cuda:0")
+            t.set_launch(False, 0)
+            t.set_graph_chunk(25)
+            t.step(0.1, 100)  # warm-up (graph capture)
+            t.restart(sim_id=1, start_step=0)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            t.step(0.1, 100)
+            st = t.stats()
+            el = time.perf_counter() - a
+            ev = st["chi_events"] + st["s_events"]
+            r = {"voxels": int(W.n_voxels(p)), "ms_T10": el * 1e3, "events_T10": ev,
+                 "events_per_s": ev / el}
+            if side == 64:
+                t.restart(sim_id=2, start_step=0)
+                t.step(0.1, 1000)
+                c = t.read_counts()
+                d = per_cell(p, c, 0).astype(np.float64)
+                bound = per_cell(p, c, 3)
+                r.update({"rim_delta_mean_T100": float(d[on_rim].mean()),
+                          "interior_delta_mean_T100": float(d[~on_rim].mean()),
+                          "rim_bound_share_T100": float(bound[on_rim].mean()),
+                          "interior_bound_share_T100": float(bound[~on_rim].mean())})
+            t.close()
+            row[name] = r
+            log(f"multi-fidelity {side}x{side}: {name} {r}")
+        row["speedup_T10"] = row["all_rdme"]["ms_T10"] / row["multi_fidelity"]["ms_T10"]
+        res["rows"].append(row)
+    res["setup"] = (f"square tissues, rim of {rim} cells at 4x4 voxels, interior cells well "
+                    "mixed (1 voxel; binding constant k_a/16 per voxel; first-order signalling "
+                    "at k_N*3/16 per face); dt 0.1")
+    return res
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -529,7 +589,8 @@ def main():
                     help="steps of the eagerly timed roofline pass (0: the whole horizon)")
     ap.add_argument("--dt-replicas", type=int, default=16384)
     ap.add_argument("--dt-T", type=float, default=20.0)
-    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt", "notch"],
+    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt", "notch",
+                                      "multifidelity"],
                     default="all",
                     help="run one leg only (profiling runs); the JSON line then carries that leg")
     ap.add_argument("--plain-only", action="store_true", help="same as --leg plain")
@@ -614,6 +675,8 @@ def main():
         out["dt_study"] = run_dt_study(args, torch, T, W)
     if leg == "notch":
         out["notch"] = run_notch(args, torch, T, W)
+    if leg == "multifidelity":
+        out["multifidelity"] = run_multifidelity(args, torch, T, W)
     if leg == "serving" or (leg == "all" and not args.no_serve):
         out["serving"] = run_serving(args, torch)
     if leg == "all" and not args.no_cpu_baseline:

@@ -83,7 +83,8 @@ enum { TISSUE_LATTICE_SQUARE = 0, TISSUE_LATTICE_HEX = 1 };
  * is the facing one: face groups are slices of the cells' membrane rings,
  * traversed the same way round, so the k-th voxel of a group of m faces the
  * (m' - 1 - floor(k m' / m))-th of the neighbour's group of m'.  Channels in
- * order: trans_rate * D_i(a) for a in A, then trans_rate * D_j(b) for b in B. */
+ * order: k_i * D_i(a) for a in A, then k_j * D_j(b) for b in B, where k_c is
+ * trans_rate, or the signal_rate of cell c's network under per-cell models. */
 #define TISSUE_FLAG_SIGNAL_FIRST_ORDER 8u
 
 #define TISSUE_MAX_SPECIES 8
@@ -111,6 +112,12 @@ typedef struct {
     const int32_t *stoich;    /* [n_reactions][n_species]                       */
     const double *rates;      /* [n_reactions]                                  */
     const double *diffusion;  /* [n_species]                                    */
+    double signal_rate;       /* under TISSUE_FLAG_SIGNAL_FIRST_ORDER: the rate per
+                                 trans_d molecule of this network's cells (a
+                                 sender's own network sets it; trans_rate plays
+                                 this part for network 0), in [0, 1e12]; with
+                                 the second-order reaction it must equal
+                                 trans_rate                                     */
 } tissue_model_t;
 
 #define TISSUE_MAX_MODELS 7   /* extra networks per tissue (8 with its own)     */

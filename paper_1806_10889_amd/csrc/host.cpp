@@ -201,6 +201,7 @@ struct Plan {
     std::vector<uint8_t> wh;
     std::vector<int32_t> vox_off;
     std::vector<int32_t> cell_list;
+    std::vector<uint8_t> cell_model;    // [ncell] each cell's network
     std::vector<EdgeRec> edges;
     std::vector<uint32_t> class_start;  // [n_colours + 1] edge ranges per colour
     bool disjoint = true;               // every cell's face groups pairwise disjoint
@@ -347,13 +348,26 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         M.trans_rate = 0.0;
     }
 
-    for (size_t m = 1; m < p.models.size(); ++m) {  // the S reaction is the tissue's
+    // the S reaction's species are the tissue's; under first-order
+    // signalling each network carries its cells' signalling rate
+    for (size_t m = 1; m < p.models.size(); ++m) {
         DevModel &X = p.models[m];
+        const double k = d->models[m - 1].signal_rate;
         X.trans_n = M.trans_n;
         X.trans_d = M.trans_d;
         X.trans_i = M.trans_i;
         X.signal_order = M.signal_order;
         X.trans_rate = M.trans_rate;
+        if (!p.has_s) continue;
+        if (first_order) {
+            if (!finite_nonneg(k))
+                return fail(TISSUE_EINVAL, "model " + std::to_string(m) +
+                                               ": signal_rate must be finite, >= 0 and <= 1e12");
+            X.trans_rate = k;
+        } else if (k != M.trans_rate) {
+            return fail(TISSUE_EINVAL, "model " + std::to_string(m) +
+                                           ": signal_rate must equal trans_rate under the second-order reaction");
+        }
     }
     for (const DevModel &X : p.models) p.net_keys.push_back(network_key(X));
     p.jits.assign(p.models.size(), nullptr);
@@ -361,6 +375,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     // cells and voxels
     p.wh.resize(2 * (size_t)p.ncell);
     p.vox_off.resize(p.ncell);
+    p.cell_model.assign(p.ncell, 0);
     uint64_t nvox = 0;
     for (uint32_t c = 0; c < p.ncell; ++c) {
         const uint32_t w = d->mesh_w ? d->mesh_w[c] : d->mesh_w0;
@@ -384,6 +399,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     for (uint32_t c = 0; c < p.ncell; ++c) {
         const int m = d->cell_model ? d->cell_model[c] : 0;
         if (m > (int)d->n_models) return fail(TISSUE_EINVAL, "cell_model entries must be <= n_models");
+        p.cell_model[c] = (uint8_t)m;
         by_p[{pow2_at_least(p.wh[2 * c] * p.wh[2 * c + 1]), -m}].push_back((int32_t)c);
     }
     for (auto it = by_p.rbegin(); it != by_p.rend(); ++it) {
@@ -437,6 +453,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
                 return fail(TISSUE_EINVAL, "face group larger than supported");
             r.m_a = (uint8_t)gi.size();
             r.m_b = (uint8_t)gj.size();
+            r.model_i = p.cell_model[ed.i];
+            r.model_j = p.cell_model[ed.j];
             for (size_t q = 0; q < gi.size(); ++q) r.A[q] = (uint8_t)gi[q];
             for (size_t q = 0; q < gj.size(); ++q) r.B[q] = (uint8_t)gj[q];
             p.edges[e] = r;

@@ -38,7 +38,7 @@ struct DevModel {
     uint32_t delta_hi[kMaxReactions];
     double rates[kMaxReactions];
     double diff_rate[kMaxSpecies];       // D of diffusion channel q
-    double trans_rate;
+    double trans_rate;                   // S rate; first order: of this network's cells' molecules
 };
 
 // One lattice edge (i < j) and the facing membrane groups A of cell i and
@@ -46,7 +46,8 @@ struct DevModel {
 struct EdgeRec {
     int32_t vox_i;         // first voxel of cell i (global voxel index)
     int32_t vox_j;
-    uint8_t m_a, m_b, pad0, pad1;
+    uint8_t m_a, m_b;
+    uint8_t model_i, model_j;  // the two cells' networks (first-order signalling rates)
     uint8_t A[kMaxFace];
     uint8_t B[kMaxFace];
 };

@@ -91,6 +91,10 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
         if (active) {
             const EdgeRec *er = T->edges + e;
             const int mA = er->m_a, mB = er->m_b;
+            // first order: each side's molecules signal at their own
+            // cell's network's rate (the tissue's rate without per-cell models)
+            const double ci = T->models[er->model_i].trans_rate;
+            const double cj = T->models[er->model_j].trans_rate;
             const long long gi = (long long)er->vox_i, gj = (long long)er->vox_j;
             uint8_t A[kMaxFace], B[kMaxFace];
 #pragma unroll
@@ -115,14 +119,14 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                     fb[2][b][lane] = counts[g + sp2];
                 }
             const int half = mA * mB;
-            // first order: channels c D_i(a) for a in A, then c D_j(b) for b
-            // in B; a Delta of face voxel k of one group becomes an NICD in
+            // first order: channels ci D_i(a) for a in A, then cj D_j(b) for
+            // b in B; a Delta of face voxel k of one group becomes an NICD in
             // voxel m' - 1 - floor(k m' / m) of the other (they run in
             // opposite directions along the shared face)
             while (first_order) {
                 double a0 = 0.0;
-                for (int a = 0; a < mA; ++a) a0 = a0 + c * (double)fa[1][a][lane];
-                for (int b = 0; b < mB; ++b) a0 = a0 + c * (double)fb[1][b][lane];
+                for (int a = 0; a < mA; ++a) a0 = a0 + ci * (double)fa[1][a][lane];
+                for (int b = 0; b < mB; ++b) a0 = a0 + cj * (double)fb[1][b][lane];
                 if (a0 == 0.0) break;
                 if (ev >= cap) {
                     capped = true;
@@ -140,7 +144,8 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 double prefix = 0.0;
                 int sel = -1, last = -1;
                 for (int k = 0; k < mA + mB; ++k) {
-                    const double p = c * (double)(k < mA ? fa[1][k][lane] : fb[1][k - mA][lane]);
+                    const double p = k < mA ? ci * (double)fa[1][k][lane]
+                                            : cj * (double)fb[1][k - mA][lane];
                     const double next = prefix + p;
                     if (p > 0.0) {
                         if (sel < 0 && r < next) sel = k;

@@ -60,6 +60,7 @@ class Model(C.Structure):
         ("n_reactions", C.c_uint32),
         ("reactants", C.POINTER(C.c_int32)), ("stoich", C.POINTER(C.c_int32)),
         ("rates", C.POINTER(C.c_double)), ("diffusion", C.POINTER(C.c_double)),
+        ("signal_rate", C.c_double),
     ]
 
 
@@ -206,6 +207,7 @@ class _DescHolder:
                 ms.n_reactions = int(t[2].size)
                 ms.reactants, ms.stoich = _p(t[0], C.c_int32), _p(t[1], C.c_int32)
                 ms.rates, ms.diffusion = _p(t[2], C.c_double), _p(t[3], C.c_double)
+                ms.signal_rate = float(md.get("signal_rate", p["trans_rate"]))
             cm = np.asarray(p["cell_model"]).reshape(-1)
             if cm.size != d.nx * d.ny or cm.min() < 0 or cm.max() > 255:
                 raise ValueError("cell_model must give each cell a network index in 0..255")

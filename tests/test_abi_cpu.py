@@ -149,3 +149,23 @@ def test_per_cell_models_compile():
     """Every network of a multi-fidelity tissue gets compiled chi kernels."""
     from paper_1806_10889_amd import tissue as T
     T.network_check(W.config_multifidelity(side=4, rim=1, n_steps=2))
+
+
+def test_per_cell_signal_rate_validation():
+    """A network's first-order signalling rate is checked like trans_rate;
+    under the second-order reaction it has to equal trans_rate."""
+    p = W.config_multifidelity(side=5, rim=1, n_steps=2)
+
+    def rate(v):
+        def mut(q):
+            q["models"] = [dict(q["models"][0], signal_rate=v)]
+        return mut
+    assert "signal_rate" in bad_of(p, rate(-1.0))
+    assert "signal_rate" in bad_of(p, rate(float("nan")))
+    q = W.config2(side=5, n_steps=2)
+    one = dict(reactants=q["reactants"], stoich=q["stoich"], rates=q["rates"],
+               diffusion=q["diffusion"])
+    q2 = W.with_models(q, [dict(one, signal_rate=q["trans_rate"] * 2)], np.arange(25) % 2)
+    assert "second-order" in bad_of(q2, lambda r: None)
+    from paper_1806_10889_amd import tissue as T
+    assert T.required_bytes(W.with_models(q, [one], np.arange(25) % 2)) > 0

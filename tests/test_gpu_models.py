@@ -5,7 +5,7 @@ bit for bit on counts, traces and totals."""
 import numpy as np
 import pytest
 
-from gpu_helpers import assert_same, gpu_run
+from gpu_helpers import assert_same, gpu_run, notch_uneven
 from paper_1806_10889_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -91,3 +91,22 @@ def test_model_tissues_share_a_batch(oracle_lib):
     b.close()
     for t in ts:
         t.close()
+
+
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_first_order_rates_per_network(oracle_lib, lattice, scheme):
+    """The paper's network on uneven meshes with three networks whose cells
+    signal at different first-order rates (one of them zero): each side of
+    an edge at its own cell's rate; every chi mode."""
+    p = notch_uneven(70 + lattice, lattice, scheme)
+    base = dict(reactants=p["reactants"], stoich=p["stoich"], rates=p["rates"],
+                diffusion=p["diffusion"])
+    rng = np.random.default_rng(lattice)
+    p = W.with_models(p, [dict(base, signal_rate=7.5),
+                          dict(base, rates=[60.0, 10.0, 5.0, 2.0, 0.5], signal_rate=0.0)],
+                      rng.integers(0, 3, 30))
+    o = oracle_lib.run(p, p["dt"], 5, trace=True)
+    assert o.s_events > 100
+    for mode in MODES:
+        assert_same(gpu_run(p, 5, trace=True, chi_mode=mode), o)

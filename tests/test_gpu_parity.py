@@ -9,7 +9,7 @@ configuration the benchmark times.
 import numpy as np
 import pytest
 
-from gpu_helpers import assert_same, gpu_run
+from gpu_helpers import assert_same, gpu_run, notch_uneven as _notch_uneven
 from paper_1806_10889_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -365,28 +365,6 @@ def test_strang_step_timed_two_chi_launches_per_step(oracle_lib):
 # ---------------------------------------------------------------------------
 # The paper's Notch model: first-order signalling into the facing voxel
 # ---------------------------------------------------------------------------
-def _notch_uneven(seed, lattice, scheme="lie", n_steps=5):
-    """The paper's network on cells of 1..4 x 1..4 voxels (face groups of
-    different sizes on the two sides of an edge), Delta and NICD scattered,
-    one promoter per cell."""
-    rng = np.random.default_rng(seed)
-    nx, ny = 6, 5
-    w = rng.integers(1, 5, size=nx * ny)
-    h = rng.integers(1, 5, size=nx * ny)
-    nvox = int((w * h).sum())
-    x0 = np.zeros((nvox, 4), np.int32)
-    x0[:, 0] = rng.integers(0, 30, nvox)
-    x0[:, 1] = rng.integers(0, 5, nvox)
-    off = np.concatenate([[0], np.cumsum(w * h)[:-1]])
-    x0[off, 2] = 1
-    p = W.make_problem(W.model_notch_paper(), lattice=lattice, nx=nx, ny=ny, mesh_w=w, mesh_h=h,
-                       rates=[100.0, 64.0, 25.0, 1.0, 1.0], trans_rate=2.0,
-                       diffusion=[16.0, 16.0, 0.0, 0.0], init_counts=x0, seed=seed, dt=0.05,
-                       n_steps=n_steps)
-    p["scheme"] = scheme
-    return p
-
-
 @pytest.mark.parametrize("jit", [True, False])
 @pytest.mark.parametrize("mode", MODES)
 def test_notch_paper_model(oracle_lib, mode, jit):
