@@ -58,11 +58,11 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC = {   # leg -> counters of its dominant chi kernel
     # hex 64x64 tissue, 4096 cells x 4x4 voxels: 400 dispatches of 200-step runs
-    "plain": {"digest": "b883837ef5eb0edf9f9144278bebb36e002b5f4c", "kernel": "tissue_chi_row",
-              "fetch_kib": 931.509, "write_kib": 1344.0},
+    "plain": {"digest": "75522784b51f5a6e7159c4bdae366a6aeb9ae163", "kernel": "tissue_chi_row",
+              "fetch_kib": 927.508, "write_kib": 1344.0},
     # 512 tissues, 3.12M cells, 200 steps: 450 dispatches
-    "batched": {"digest": "b883837ef5eb0edf9f9144278bebb36e002b5f4c", "kernel": "tissue_chi_lane16",
-                "fetch_kib": 508871.0, "write_kib": 979159.0},
+    "batched": {"digest": "75522784b51f5a6e7159c4bdae366a6aeb9ae163", "kernel": "tissue_chi_lane16",
+                "fetch_kib": 508879.0, "write_kib": 979152.0},
 }
 
 

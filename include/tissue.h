@@ -240,7 +240,9 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
 
 /* Kernel of the chi operator.  0 = one lane per cell with the full sum tree
  * and 32-bit counts in LDS (every cell); 1 = one row of max(16, P) lanes per
- * cell of P leaves, one lane per voxel (16, 32 or 64 lanes);
+ * cell of P leaves, one lane per voxel (16, 32 or 64 lanes); 4 = rows of
+ * max(32, P) lanes (the same kernel with at most two cells per wavefront:
+ * twice the wavefronts of mode 1 for cells of at most 16 voxels);
  * 3 = one lane per cell with the compact layout (16 FP64 leaves, 16-bit
  * counts, upper tree levels rebuilt in registers), cells that reach 2^16
  * molecules of a species handed to a full-width lane launch that redoes
@@ -256,7 +258,7 @@ int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
 
 /* Per-kernel device time of the last tissue_step_timed call, in ms.
  * chi_ms brackets each chi launch (for mode 3 with its redo launch);
- * chi_kernel is the mode (0, 1 or 3, as in tissue_set_chi_mode) of the chi
+ * chi_kernel is the mode (0, 1, 3 or 4, as in tissue_set_chi_mode) of the chi
  * launch group that took the most time. */
 typedef struct {
     double chi_ms, s_ms, total_ms;

@@ -38,9 +38,10 @@ def signature(problems) -> str:
 
 def candidates(max_voxels: int):
     out = []
-    # rows and the compact layout apply to cells of at most 16 voxels (larger
-    # cells keep the full lane layout); auto mixes them per leaf-count class
-    modes = [0, 1, 3, 2] if max_voxels <= 16 else [0, 2, 1, 3]
+    # the compact layout applies to cells of at most 16 voxels (larger cells
+    # keep the full lane layout); rows (16 or 32 lanes for the small cells)
+    # cover every class; auto mixes them per leaf-count class
+    modes = [0, 1, 4, 3, 2] if max_voxels <= 16 else [0, 2, 1, 4, 3]
     for mode in modes:
         for persistent, wpc in [(1, 0), (0, 0), (1, 2), (1, 8)]:
             for chunk in (25, 100):

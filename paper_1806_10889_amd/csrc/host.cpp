@@ -410,12 +410,14 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         g.count = (uint32_t)it->second.size();
         p.cell_list.insert(p.cell_list.end(), it->second.begin(), it->second.end());
         p.chi.push_back(g);
-        // room for every cut of the class (lane, row of max(16, P) lanes,
-        // compact lane layout), whichever the launch plan picks
+        // room for the largest cut of the class, whichever the launch plan
+        // picks: lane layout, rows of max(16, P) or max(32, P) lanes, or the
+        // compact lane layout (at most one item per cell)
         const uint32_t lcpi = (uint32_t)lane_cells_per_item(g.P, S);
-        const uint32_t rcpi = (uint32_t)(kWave / std::max(16, g.P));
-        p.n_chi_items += (g.count + lcpi - 1) / lcpi + (g.count + rcpi - 1) / rcpi;
-        if (g.P <= 16) p.n_chi_items += g.count;
+        const uint32_t wcpi = (uint32_t)(kWave / std::max(32, g.P));  // wide rows: fewest cells per item
+        uint32_t most = std::max((g.count + lcpi - 1) / lcpi, (g.count + wcpi - 1) / wcpi);
+        if (g.P <= 16) most = std::max(most, g.count);
+        p.n_chi_items += most;
     }
 
     // edges, face groups, S passes
@@ -512,6 +514,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
 
 struct ChiLaunch {
     int mode;                // kChiLane, kChiRow or kChiLane16
+    int rw;                  // kChiRow: lanes per cell (16, 32 or 64)
     size_t retry_lds;        // lane16: LDS of the full-width redo launch
     const JitKernels *jit;   // compiled-network kernels, or null: generic ones
     int SM, RM, NDM;         // generic kernel instantiation (table sizes)
@@ -521,10 +524,12 @@ struct ChiLaunch {
     uint32_t n_items;
 };
 
-// chi mode request: lane, row, automatic, or lane16.  Automatic: for classes
-// of at most 16 voxels, row mode when one lane per cell would not give every
-// SIMD a wavefront, else the compact lane16 layout; larger cells: lane mode.
-enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2, kModeLane16 = 3 };
+// chi mode request: lane, row, automatic, lane16, or wide rows.  Automatic:
+// for classes of at most 16 voxels, row mode when one lane per cell would
+// not give every SIMD a wavefront, else the compact lane16 layout; larger
+// cells: lane mode.  Wide rows: rows of max(32, P) lanes, half as many cells
+// per wavefront as rows of 16 for the small cells, so twice the wavefronts.
+enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2, kModeLane16 = 3, kModeRowWide = 4 };
 
 // Work items and launches of the chi operator over a set of tissues: one
 // launch per (leaf class, kernel instantiation).  Items are written to
@@ -574,7 +579,12 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         uint64_t cells = 0;
         for (auto &m : G.cells) cells += m.second->count;
         int mode = kChiLane;
+        int rw = std::max(16, k.P);
         if (mode_req == kModeRow) mode = kChiRow;  // rows of max(16, P) lanes
+        if (mode_req == kModeRowWide) {
+            mode = kChiRow;
+            rw = std::max(32, k.P);
+        }
         if (k.P <= 16) {
             if (mode_req == kModeLane16) mode = kChiLane16;
             // automatic: cells of at most 8 leaves keep the full lane layout
@@ -586,13 +596,14 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         }
         ChiLaunch L;
         L.mode = mode;
+        L.rw = rw;
         L.jit = G.jit;
         L.SM = G.SM;
         L.RM = G.RM;
         L.NDM = G.NDM;
         L.P = k.P;
         if (mode == kChiRow) {
-            L.cells_per_item = kWave / std::max(16, k.P);
+            L.cells_per_item = kWave / rw;
         } else if (mode == kChiLane16) {
             int cpi = 64;
             while (cpi > 1 && chi_lds_bytes(kChiLane16, 16, G.max_s, cpi) > kChiLdsBudget) cpi >>= 1;
@@ -693,6 +704,7 @@ struct LaunchPlan {
         ChiArgs a{};
         a.mode = L.mode;
         a.P = L.P;
+        a.rw = L.rw;
         a.grid = grid;
         a.lds = L.lds;
         a.stream = st;
@@ -713,7 +725,7 @@ struct LaunchPlan {
         } else if (L.mode == kChiRow) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.dt, &a.kstep,
                             &a.tag};
-            hipFunction_t f = L.P > 32 ? L.jit->row64 : L.P > 16 ? L.jit->row32 : L.jit->row;
+            hipFunction_t f = L.rw == 64 ? L.jit->row64 : L.rw == 32 ? L.jit->row32 : L.jit->row;
             e = hipModuleLaunchKernel(f, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
         } else if (L.mode == kChiLane16) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
@@ -940,7 +952,7 @@ struct LaunchPlan {
         for (size_t g = 0; g < chi.size(); ++g) {
             if (chi[g].n_items == 0 || per_group[g] <= longest) continue;
             longest = per_group[g];
-            T.chi_kernel = chi[g].mode == kChiRow ? kModeRow
+            T.chi_kernel = chi[g].mode == kChiRow ? (chi[g].rw > std::max(16, chi[g].P) ? kModeRowWide : kModeRow)
                          : chi[g].mode == kChiLane16 ? kModeLane16 : kModeLane;
         }
         float tot = 0.f;
@@ -1316,7 +1328,7 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
 
 int tissue_set_chi_mode(tissue_t *t, int32_t mode)
 {
-    if (!t || mode < kModeLane || mode > kModeLane16) return fail(TISSUE_EINVAL, "chi mode must be 0..3");
+    if (!t || mode < kModeLane || mode > kModeRowWide) return fail(TISSUE_EINVAL, "chi mode must be 0..4");
     return t->lp.set_chi_mode(mode);
 }
 
@@ -1357,7 +1369,7 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
     for (int32_t i = 1; i < n; ++i)
         if (ts[i]->plan.strang != ts[0]->plan.strang)
             return fail(TISSUE_EINVAL, "batch members must share the splitting scheme");
-    // chi items: room for both cuts of every member's classes
+    // chi items: room for the largest cut of every member's classes
     for (int32_t i = 0; i < n; ++i) B.chi_cap += ts[i]->plan.n_chi_items;
     // S: pass 0 holds all edges of members with disjoint faces and class 0
     // of the others; pass c > 0 holds class c of the others
@@ -1518,7 +1530,7 @@ int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph)
 
 int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode)
 {
-    if (!b || mode < kModeLane || mode > kModeLane16) return fail(TISSUE_EINVAL, "chi mode must be 0..3");
+    if (!b || mode < kModeLane || mode > kModeRowWide) return fail(TISSUE_EINVAL, "chi mode must be 0..4");
     return b->lp.set_chi_mode(mode);
 }
 

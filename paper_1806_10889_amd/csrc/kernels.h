@@ -15,6 +15,7 @@ size_t chi_lds_bytes(int mode, int P, int S, int cells_per_item);
 // Arguments of one chi launch.
 struct ChiArgs {
     int mode, P;
+    int rw;                  // row mode: lanes per cell (16, 32 or 64)
     uint32_t grid;
     size_t lds;
     hipStream_t stream;

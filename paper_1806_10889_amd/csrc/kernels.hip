@@ -298,10 +298,10 @@ int log2_exact(int P)
 template <int SM, int RM, int NDM>
 hipError_t launch_variant(const ChiArgs &a)
 {
-    if (a.mode == kChiRow && a.P > 32) {
+    if (a.mode == kChiRow && a.rw == 64) {
         hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 64>), dim3(a.grid), dim3(kWave), 0, a.stream,
                            a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
-    } else if (a.mode == kChiRow && a.P > 16) {
+    } else if (a.mode == kChiRow && a.rw == 32) {
         hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 32>), dim3(a.grid), dim3(kWave), 0, a.stream,
                            a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
     } else if (a.mode == kChiRow) {

@@ -10,7 +10,7 @@ from paper_1806_10889_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-MODES = [0, 1, 2, 3]
+MODES = [0, 1, 2, 3, 4]
 
 
 def _nd5_mixed(seed, *, uneven=True, lattice=1, nx=9, ny=7, n_steps=5):

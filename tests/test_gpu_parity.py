@@ -19,8 +19,9 @@ def _oracle(oracle_lib, p, n, trace=True, **kw):
     return oracle_lib.run(p, p["dt"], n, trace=trace, **kw)
 
 
-# chi kernel: one lane per cell / one 16-lane row per cell / compact lane16
-MODES = [0, 1, 3]
+# chi kernel: one lane per cell / one 16-lane row per cell / compact lane16 /
+# rows of 32 lanes for the small cells
+MODES = [0, 1, 3, 4]
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -281,7 +282,7 @@ def test_lane16_redo_of_wide_counts(oracle_lib, jit):
     assert_same(gpu_run(p, 4, trace=True, chi_mode=3, jit=jit), o)
 
 
-@pytest.mark.parametrize("mode,expect", [(0, 0), (1, 1), (3, 3), (2, 1)])
+@pytest.mark.parametrize("mode,expect", [(0, 0), (1, 1), (3, 3), (2, 1), (4, 4)])
 def test_step_timed_same_bits_and_reports_kernel(oracle_lib, mode, expect):
     """The eagerly launched, event-bracketed steps give the oracle's bits, one
     chi launch and the same S passes per step, and name the chi layout that ran (auto
@@ -408,7 +409,7 @@ def test_classes_in_parallel_graph_branches(oracle_lib, scheme, jit):
     p = W.random_problem(37, lattice=1, nx=9, ny=7, model="nd5", uneven=True, dt=0.05, n_steps=6)
     p["scheme"] = scheme
     o = _oracle(oracle_lib, p, 6)
-    for mode in (0, 1, 2, 3):
+    for mode in (0, 1, 2, 3, 4):
         g = gpu_run(p, 6, trace=True, persistent=False, graph_chunk=2, chi_mode=mode, jit=jit)
         assert_same(g, o)
 
