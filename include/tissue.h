@@ -243,14 +243,15 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
  * cell of P leaves, one lane per voxel (16, 32 or 64 lanes); 4 = rows of
  * max(32, P) lanes (the same kernel with at most two cells per wavefront:
  * twice the wavefronts of mode 1 for cells of at most 16 voxels);
- * 3 = one lane per cell with the compact layout (16 FP64 leaves, 16-bit
- * counts, upper tree levels rebuilt in registers), cells that reach 2^16
- * molecules of a species handed to a full-width lane launch that redoes
+ * 3 = the compact layout: one lane per 16 voxels of a cell (1, 2 or 4
+ * lanes per cell of P = 16, 32 or 64 leaves), each holding its voxels' 16
+ * FP64 leaves and 16-bit counts, the tree levels above them rebuilt in
+ * registers and combined across the cell's lanes; cells that reach 2^16
+ * molecules of a species are handed to a full-width lane launch that redoes
  * their step; 2 = automatic (the default): for cells of 9 to 16 voxels,
  * rows when that class has fewer cells than 64 per SIMD of the device, else
- * the compact layout; mode 0 for all other cells.  Mode 3 applies to cells of
- * at most 16 voxels (larger cells take mode 0).  Results are bit-identical
- * for every choice.  Other values: TISSUE_EINVAL. */
+ * the compact layout; mode 0 for all other cells.  Results are
+ * bit-identical for every choice.  Other values: TISSUE_EINVAL. */
 int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 
 /* Steps captured per HIP graph launch (0 disables graphs). */
@@ -259,11 +260,13 @@ int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
 /* Per-kernel device time of the last tissue_step_timed call, in ms.
  * chi_ms brackets each chi launch (for mode 3 with its redo launch);
  * chi_kernel is the mode (0, 1, 3 or 4, as in tissue_set_chi_mode) of the chi
- * launch group that took the most time. */
+ * launch group that took the most time, chi_leaves that group's leaf count
+ * P (next power of two >= its cells' voxel count). */
 typedef struct {
     double chi_ms, s_ms, total_ms;
     uint32_t chi_launches, s_launches;
     int32_t chi_kernel;
+    int32_t chi_leaves;
 } tissue_timing_t;
 
 /* tissue_step, launched eagerly with a HIP event pair around every kernel;

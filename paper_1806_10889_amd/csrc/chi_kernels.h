@@ -827,12 +827,21 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
 
 
 // ---------------------------------------------------------------------------
-// chi, one lane per cell of at most 16 voxels, compact LDS: per cell only the
-// 16 leaf propensities (FP64, stored as pairs so one 16-byte read fetches
-// two) and the counts as uint16 -- 288 B for 16 voxels x 5 species, half of
-// the full layout, so twice the wavefronts fit a CU.  The levels of the
-// 16-leaf sum tree are rebuilt in registers every event (the same pairwise
-// sums as the heap, so the same bits) and the descent selects among them.
+// chi, compact LDS: G = 1, 2 or 4 lanes per cell of at most 16 G voxels.
+// Lane k of a cell's group holds voxels 16k .. 16k+15: their 16 leaf
+// propensities (FP64, stored as pairs so one 16-byte read fetches two) and
+// their counts as uint16 -- 304 B per lane for 5 species, whatever the cell
+// size, so a wavefront holds 64 / G cells and eight wavefronts fit a CU.
+// Every event each lane rebuilds the four levels of its own 16-leaf subtree
+// in registers; the G subtree sums are combined by one or two DPP exchanges
+// inside the group (pair, then quad), which are the heap's upper nodes, so
+// every node carries the bits of the P-leaf heap tree (addition is
+// commutative, so both lanes of an exchange hold the same sum).  The group's
+// lanes draw the same numbers and take the same decisions up to the
+// descent; the descent's upper levels pick the one lane whose subtree holds
+// the event, which selects and applies the channel in its voxel and
+// broadcasts a diffusion jump's destination to the group; the lane holding
+// the destination voxel (the same or another) adds the molecule.
 // A cell whose count would reach 2^16 abandons its step without writing
 // anything back and is queued (retry_items, *retry_count); a follow-up
 // launch of the full-width lane kernel redoes that cell-step from the
@@ -842,22 +851,42 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
 constexpr int kLane16Leaves = 16;
 constexpr int32_t kLane16Limit = 1 << 16;
 
+// LDS of a compact launch: `stride` lanes holding data (cells per item x G).
 __host__ __device__ inline size_t lane16_lds_bytes(int S, int stride)
 {
     return (size_t)stride * ((size_t)kLane16Leaves * 8 + ((size_t)kLane16Leaves * S + kMaxSpecies) * 2);
 }
 
-template <class NET>
+namespace {
+
+// OR of a 32-bit value over the lane's group of G lanes (G = 2: lane pair,
+// G = 4: lane quad); every lane of the group must be active.
+template <int G>
+__device__ __forceinline__ uint32_t group_or(uint32_t x)
+{
+    if (G >= 2) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppPairSwap, 0xF, 0xF, false);
+    if (G >= 4) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppQuadSwap, 0xF, 0xF, false);
+    return x;
+}
+
+}  // namespace
+
+template <class NET, int G>
 __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTissue *const *tbl,
                                                 const ChiItem *items, uint32_t n_items,
                                                 uint32_t *queue, int persistent, int cells_per_item,
                                                 double dt, uint32_t kstep, uint32_t tag,
                                                 ChiItem *retry_items, uint32_t *retry_count)
 {
+    static_assert(G == 1 || G == 2 || G == 4, "lanes per cell");
     constexpr int SM = NET::SM;
+    constexpr int LOG_G = G == 4 ? 2 : G == 2 ? 1 : 0;
     __shared__ ChanEntry tab[kChanSlots];
     const int lane = threadIdx.x;
-    const int stride = cells_per_item;
+    const int slot = lane >> LOG_G;   // the lane's cell within the item
+    const int sub = lane & (G - 1);   // which 16 voxels of the cell it holds
+    const int v0 = kLane16Leaves * sub;
+    const int stride = cells_per_item * G;
     uint32_t cursor = blockIdx.x;
     for (;;) {
         const uint32_t it = next_item(queue, persistent != 0, cursor);
@@ -872,25 +901,27 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
         double *leafp = reinterpret_cast<double *>(lds) + 2 * lane;
         uint16_t *cnt = reinterpret_cast<uint16_t *>(lds + (size_t)stride * kLane16Leaves * 8) + lane;
 
-        const bool active = lane < (int)c.count;
+        const bool active = slot < (int)c.count;
         uint32_t cell = 0;
         Mesh g{1, 1, 65537};
-        long long gbase = 0;
+        long long gbase = 0;  // the lane's first count in HBM
+        int nloc = 0;         // voxels the lane holds
         bool retry = false;
         if (active) {
-            cell = (uint32_t)c.T->cell_list[c.first + lane];
+            cell = (uint32_t)c.T->cell_list[c.first + slot];
             g.w = c.T->wh[2 * cell];
             g.h = c.T->wh[2 * cell + 1];
             g.inv_w = 65536 / g.w + 1;
-            gbase = (long long)c.T->vox_off[cell] * S;
-            const int n = g.w * g.h * S;
+            nloc = min(max(g.w * g.h - v0, 0), kLane16Leaves);
+            gbase = ((long long)c.T->vox_off[cell] + v0) * S;
+            const int n = nloc * S;
             for (int i = 0; i < n; ++i) {
                 const int32_t x = c.counts[gbase + i];
                 retry |= x >= kLane16Limit;
                 cnt[i * stride] = (uint16_t)x;
             }
         }
-        const int V = g.w * g.h;
+        if (G > 1) retry = group_or<G>(retry ? 1u : 0u) != 0u;
         double xd[SM];
         if (active && !retry) {
 #pragma unroll
@@ -900,21 +931,21 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 for (int h = 0; h < 2; ++h) {
                     const int v = 2 * k + h;
                     two[h] = 0.0;
-                    if (v < V) {
+                    if (v < nloc) {
 #pragma unroll
                         for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(v * S + q) * stride];
-                        two[h] = voxel_fold(net, xd, (double)voxel_degree(g, v));
+                        two[h] = voxel_fold(net, xd, (double)voxel_degree(g, v0 + v));
                     }
                 }
-                double *slot = leafp + (size_t)k * stride * 2;
-                slot[0] = two[0];
-                slot[1] = two[1];
+                double *sl = leafp + (size_t)k * stride * 2;
+                sl[0] = two[0];
+                sl[1] = two[1];
             }
         }
 
         double t = 0.0;
         uint32_t j = 0, ev = 0;
-        bool overflow = false, capped = false;
+        bool capped = false;
         if (active && !retry) {
             double e1, u2;
             {
@@ -924,13 +955,13 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 e1 = -tdev::plog(u1);
             }
             for (;;) {
-                // the 16 leaves and the levels of the tree above them
+                // the lane's 16 leaves and the levels of its subtree
                 double l[kLane16Leaves];
 #pragma unroll
                 for (int k = 0; k < kLane16Leaves / 2; ++k) {
-                    const double *slot = leafp + (size_t)k * stride * 2;
-                    l[2 * k] = slot[0];
-                    l[2 * k + 1] = slot[1];
+                    const double *sl = leafp + (size_t)k * stride * 2;
+                    l[2 * k] = sl[0];
+                    l[2 * k + 1] = sl[1];
                 }
                 double q1[8], q2[4], q3[2];
 #pragma unroll
@@ -939,7 +970,19 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 for (int k = 0; k < 4; ++k) q2[k] = q1[2 * k] + q1[2 * k + 1];
 #pragma unroll
                 for (int k = 0; k < 2; ++k) q3[k] = q2[2 * k] + q2[2 * k + 1];
-                const double a0 = q3[0] + q3[1];
+                // the heap's nodes above the lanes' subtrees: the pair's sum
+                // (G >= 2), then the quad's (G = 4)
+                const double s = q3[0] + q3[1];
+                double a0 = s, p1 = 0.0, hs = s, p2 = 0.0;
+                if (G >= 2) {
+                    p1 = dpp_f64<kDppPairSwap>(s);
+                    hs = s + p1;
+                    a0 = hs;
+                }
+                if (G == 4) {
+                    p2 = dpp_f64<kDppQuadSwap>(hs);
+                    a0 = hs + p2;
+                }
                 if (a0 == 0.0) break;
                 if (ev >= c.cap) {
                     capped = true;
@@ -956,7 +999,13 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     tdev::two_uniforms(wds, u1, u2);
                     e1 = -tdev::plog(u1);
                 }
-                // descent: left if r < L or R == 0, else r -= L and right
+                // descent through the group's levels: only the lane whose
+                // subtree the path enters stays `on`
+                bool on = true;
+                if (G == 4) descent_level(hs, p2, sub >> 1, r, on);
+                if (G >= 2) descent_level(s, p1, sub & 1, r, on);
+                // descent inside the subtree: left if r < L or R == 0, else
+                // r -= L and right
                 int v = 0;
                 {
                     double L = q3[0], R = q3[1];
@@ -988,59 +1037,70 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 }
 
                 const Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
-                uint16_t *x = cnt + v * S * stride;
+                bool wide = false;
+                uint32_t word = 0;  // a jump: 1 | species << 4 | destination voxel << 8
+                if (on) {
+                    uint16_t *x = cnt + v * S * stride;
 #pragma unroll
-                for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
-                const int deg = voxel_degree(go, v);
-                double resid, a1;
-                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
-                const ChanEntry e = tab[sel];
+                    for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
+                    const int deg = voxel_degree(go, v0 + v);
+                    double resid, a1;
+                    const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
+                    const ChanEntry e = tab[sel];
 #pragma unroll
-                for (int q = 0; q < SM; ++q) {
-                    if (q < S) {
-                        xd[q] += entry_delta(e, q);
-                        x[q * stride] = (uint16_t)(int32_t)xd[q];
+                    for (int q = 0; q < SM; ++q) {
+                        if (q < S) {
+                            xd[q] += entry_delta(e, q);
+                            x[q * stride] = (uint16_t)(int32_t)xd[q];
+                        }
                     }
+                    wide = out_of_range<SM>(xd, S, (double)kLane16Limit);
+                    if (e.spec >= 0) {
+                        const int dst = neighbour_at(go, v0 + v, jump_direction(resid, a1, deg));
+                        word = 1u | ((uint32_t)e.spec << 4) | ((uint32_t)dst << 8);
+                    }
+                    leafp[(size_t)(v >> 1) * stride * 2 + (v & 1)] = voxel_fold(net, xd, (double)deg);
                 }
-                bool wide = out_of_range<SM>(xd, S, (double)kLane16Limit);
-                int dst = v;
-                if (e.spec >= 0) {
-                    dst = neighbour_at(go, v, jump_direction(resid, a1, deg));
-                    uint16_t *xdst = cnt + (dst * S + e.spec) * stride;
+                if (G > 1) word = group_or<G>(word);
+                // the lane holding the jump's destination voxel adds the
+                // molecule and refolds that voxel
+                const int dv = (int)(word >> 8) - v0;
+                if ((word & 1u) && dv >= 0 && dv < kLane16Leaves) {
+                    const int spec = (int)((word >> 4) & 15u);
+                    uint16_t *xdst = cnt + (dv * S + spec) * stride;
                     const int32_t nd = (int32_t)*xdst + 1;
                     wide |= nd >= kLane16Limit;
                     *xdst = (uint16_t)nd;
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(dv * S + q) * stride];
+                    leafp[(size_t)(dv >> 1) * stride * 2 + (dv & 1)] =
+                        voxel_fold(net, xd, (double)voxel_degree(go, v0 + dv));
                 }
+                if (G > 1) wide = group_or<G>(wide ? 1u : 0u) != 0u;
                 if (wide) {  // redo this cell-step at full width
                     retry = true;
                     break;
-                }
-                // new leaves of v (and dst)
-                const double lv = voxel_fold(net, xd, (double)deg);
-                leafp[(size_t)(v >> 1) * stride * 2 + (v & 1)] = lv;
-                if (dst != v) {
-#pragma unroll
-                    for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(dst * S + q) * stride];
-                    leafp[(size_t)(dst >> 1) * stride * 2 + (dst & 1)] =
-                        voxel_fold(net, xd, (double)voxel_degree(go, dst));
                 }
                 ++ev;
             }
         }
         if (active && retry) {
-            const uint32_t at = atomicAdd(retry_count, 1u);
-            retry_items[at] = ChiItem{item.tissue, c.first + (uint32_t)lane, 1u, item.model};
+            if (sub == 0) {
+                const uint32_t at = atomicAdd(retry_count, 1u);
+                retry_items[at] = ChiItem{item.tissue, c.first + (uint32_t)slot, 1u, item.model};
+            }
         } else if (active) {
-            const int n = V * S;
+            const int n = nloc * S;
             for (int i = 0; i < n; ++i) c.counts[gbase + i] = (int32_t)cnt[i * stride];
-            if (c.T->tr_chi_ev) {
+            if (sub == 0 && c.T->tr_chi_ev) {
                 const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
-                const size_t slot = (size_t)(c.step % ts) * nc + cell;
-                c.T->tr_chi_ev[slot] = tag ? c.T->tr_chi_ev[slot] + ev : ev;  // 2nd half adds
-                c.T->tr_chi_t[slot] = (unsigned long long)__double_as_longlong(t);
+                const size_t at = (size_t)(c.step % ts) * nc + cell;
+                c.T->tr_chi_ev[at] = tag ? c.T->tr_chi_ev[at] + ev : ev;  // 2nd half adds
+                c.T->tr_chi_t[at] = (unsigned long long)__double_as_longlong(t);
             }
         }
-        item_stats(c, retry ? 0u : ev, retry ? 0u : j, overflow && !retry, capped && !retry, 0);
+        const bool counted = active && !retry && sub == 0;
+        item_stats(c, counted ? ev : 0u, counted ? j : 0u, false, capped && counted, 0);
     }
     leave_queue(queue, persistent != 0);
 }

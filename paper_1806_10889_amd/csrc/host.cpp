@@ -51,6 +51,11 @@ int hip_fail(hipError_t e, const char *what)
 
 constexpr size_t kAlign = 256;
 constexpr size_t kChiLdsBudget = 40 * 1024;  // per workgroup: >= 4 resident per CU
+// chi launches of one plan (leaf classes x networks) and their queue words:
+// each launch owns a block of 8 words (item queue, exit count, redo count,
+// redo queue) so that launches of different classes can run concurrently
+constexpr int kMaxChiLaunches = 64;
+constexpr size_t kLaunchQueueBytes = (size_t)kMaxChiLaunches * 8 * sizeof(uint32_t);
 constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kChiStaticLds = 512;  // the chi kernels' static LDS (channel table), rounded up
 
@@ -220,7 +225,7 @@ struct Plan {
     // byte offsets inside dev_buf
     size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
            off_cells = 0, off_edges = 0, off_models = 0, off_chi = 0, off_s = 0, off_ctl = 0,
-           off_trace = 0,
+           off_trace = 0, off_lq = 0,
            off_retry = 0, bytes = 0;
     size_t n_chi_items = 0, n_s_items = 0;
 };
@@ -416,7 +421,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         const uint32_t lcpi = (uint32_t)lane_cells_per_item(g.P, S);
         const uint32_t wcpi = (uint32_t)(kWave / std::max(32, g.P));  // wide rows: fewest cells per item
         uint32_t most = std::max((g.count + lcpi - 1) / lcpi, (g.count + wcpi - 1) / wcpi);
-        if (g.P <= 16) most = std::max(most, g.count);
+        if (g.P <= 64) most = std::max(most, g.count);
         p.n_chi_items += most;
     }
 
@@ -502,6 +507,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     p.off_chi = take(p.n_chi_items * sizeof(ChiItem));
     p.off_s = take(p.n_s_items * sizeof(SItem));
     p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue words u32[8]
+    p.off_lq = take(kLaunchQueueBytes);  // per-launch queue words of the chi launches
     p.off_retry = take((size_t)p.ncell * sizeof(ChiItem));  // lane16 cells to redo
     p.off_trace = take((size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12));
     p.bytes = o;
@@ -522,13 +528,16 @@ struct ChiLaunch {
     size_t lds;
     const ChiItem *items;
     uint32_t n_items;
+    uint32_t retry_off;      // compact layout: this launch's part of the redo list
 };
 
-// chi mode request: lane, row, automatic, lane16, or wide rows.  Automatic:
-// for classes of at most 16 voxels, row mode when one lane per cell would
-// not give every SIMD a wavefront, else the compact lane16 layout; larger
-// cells: lane mode.  Wide rows: rows of max(32, P) lanes, half as many cells
-// per wavefront as rows of 16 for the small cells, so twice the wavefronts.
+// chi mode request: lane, row, automatic, compact (lane16), or wide rows.
+// Automatic: for classes of at most 16 voxels, row mode when one lane per
+// cell would not give every SIMD a wavefront, else the compact layout;
+// larger cells: lane mode.  Compact: every class in the compact layout
+// (P / 16 lanes per cell above 16 leaves).  Wide rows: rows of max(32, P)
+// lanes, half as many cells per wavefront as rows of 16 for the small
+// cells, so twice the wavefronts.
 enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2, kModeLane16 = 3, kModeRowWide = 4 };
 
 // Work items and launches of the chi operator over a set of tissues: one
@@ -573,6 +582,7 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
     }
     items_out.clear();
     launches.clear();
+    uint64_t retry_cells = 0;  // cells of the compact launches so far
     for (auto &kv : groups) {
         const Key &k = kv.first;
         const Group &G = kv.second;
@@ -585,8 +595,8 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
             mode = kChiRow;
             rw = std::max(32, k.P);
         }
+        if (mode_req == kModeLane16 && k.P <= 64) mode = kChiLane16;
         if (k.P <= 16) {
-            if (mode_req == kModeLane16) mode = kChiLane16;
             // automatic: cells of at most 8 leaves keep the full lane layout
             // (small in LDS, few tree levels; a row would idle most of its
             // lanes); 16-leaf cells take rows when one lane per cell would
@@ -605,8 +615,8 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         if (mode == kChiRow) {
             L.cells_per_item = kWave / rw;
         } else if (mode == kChiLane16) {
-            int cpi = 64;
-            while (cpi > 1 && chi_lds_bytes(kChiLane16, 16, G.max_s, cpi) > kChiLdsBudget) cpi >>= 1;
+            int cpi = kWave / compact_lanes(k.P);
+            while (cpi > 1 && chi_lds_bytes(kChiLane16, k.P, G.max_s, cpi) > kChiLdsBudget) cpi >>= 1;
             L.cells_per_item = cpi;
         } else {
             L.cells_per_item = lane_cells_per_item(k.P, G.max_s);
@@ -617,6 +627,8 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         for (auto &m : G.cells) cut_items(m.first, *m.second, L.cells_per_item, items_out);
         L.items = reinterpret_cast<const ChiItem *>(off);
         L.n_items = (uint32_t)(items_out.size() - off);
+        L.retry_off = (uint32_t)retry_cells;
+        if (mode == kChiLane16) retry_cells += cells;
         launches.push_back(L);
     }
 }
@@ -641,7 +653,8 @@ struct LaunchPlan {
     std::vector<const Plan *> members;
     ChiItem *chi_items = nullptr;  // device region for chi work items
     size_t chi_items_cap = 0;
-    ChiItem *retry_items = nullptr;  // device region: lane16 cells to redo (one per cell)
+    ChiItem *retry_items = nullptr;  // device region: compact-layout cells to redo (one per cell)
+    uint32_t *lq = nullptr;     // device: 8 queue words per chi launch
     int chi_mode = kModeAuto;
     std::vector<ChiLaunch> chi;
     std::vector<SLaunch> s;
@@ -693,12 +706,14 @@ struct LaunchPlan {
         graphs.clear();
     }
 
-    // One chi launch of a group; for lane16 also the full-width redo of the
-    // cells it handed back (a persistent launch that reads the count from
-    // device memory and exits at once when it is zero).
+    // One chi launch of a group; for the compact layout also the full-width
+    // redo of the cells it handed back (a persistent launch that reads the
+    // count from device memory and exits at once when it is zero).  Each
+    // launch uses its own queue words and its own part of the redo list.
     hipError_t launch_chi_any(const ChiLaunch &L, uint32_t grid, hipStream_t st, double dt,
                               uint32_t kstep, uint32_t tag)
     {
+        uint32_t *const q = lq + 8 * (size_t)(&L - chi.data());
         int log2p = 0;
         while ((1 << log2p) < L.P) ++log2p;
         ChiArgs a{};
@@ -711,14 +726,14 @@ struct LaunchPlan {
         a.tbl = tbl;
         a.items = L.items;
         a.n_items = L.n_items;
-        a.queue = queue + kQNext;
+        a.queue = q + kQNext;
         a.persistent = persistent;
         a.cells_per_item = L.cells_per_item;
         a.dt = dt;
         a.kstep = kstep;
         a.tag = tag;
-        a.retry_items = retry_items;
-        a.retry_count = queue + kQRetry;
+        a.retry_items = retry_items + L.retry_off;
+        a.retry_count = q + kQRetry;
         hipError_t e = hipSuccess;
         if (!L.jit) {
             e = launch_chi(L.SM, L.RM, L.NDM, a);
@@ -730,8 +745,8 @@ struct LaunchPlan {
         } else if (L.mode == kChiLane16) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
                             &a.dt, &a.kstep, &a.tag, &a.retry_items, &a.retry_count};
-            e = hipModuleLaunchKernel(L.jit->lane16, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st,
-                                      args, nullptr);
+            hipFunction_t f = L.P == 64 ? L.jit->lane16x4 : L.P == 32 ? L.jit->lane16x2 : L.jit->lane16;
+            e = hipModuleLaunchKernel(f, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st, args, nullptr);
         } else {
             uint32_t *none = nullptr;
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
@@ -745,12 +760,12 @@ struct LaunchPlan {
         r.mode = kChiLane;
         r.grid = (uint32_t)std::max(1, cus);
         r.lds = L.retry_lds;
-        r.items = retry_items;
+        r.items = retry_items + L.retry_off;
         r.n_items = 0;
-        r.queue = queue + kQRetryNext;
+        r.queue = q + kQRetryNext;
         r.persistent = 1;
         r.cells_per_item = 1;
-        r.n_items_dev = queue + kQRetry;
+        r.n_items_dev = q + kQRetry;
         if (!L.jit) return launch_chi(L.SM, L.RM, L.NDM, r);
         void *args[] = {&r.tbl, &r.items, &r.n_items, &r.queue, &r.persistent, &r.cells_per_item,
                         &log2p, &r.dt, &r.kstep, &r.tag, &r.n_items_dev};
@@ -781,17 +796,14 @@ struct LaunchPlan {
     {
         size_t e = 0;
         // the chi launches of one (half-)step, counter tag `tag`.  Classes
-        // touch disjoint cells, so with one workgroup per item (no shared
-        // queue words) the captured step graph runs them as parallel
-        // branches: one branch on `st`, the others on side streams forked
-        // from and joined back into it.  The compact-layout launches share
-        // the redo list and its queue words, so they all stay in order on
-        // `st`.  Eager launches (timed runs, serving) keep every launch in
-        // order on the caller's stream.
-        size_t n16 = 0, nother = 0;
-        for (const ChiLaunch &L : chi)
-            if (L.n_items > 0) (L.mode == kChiLane16 ? n16 : nother)++;
-        const size_t branches = nother + (n16 > 0);
+        // touch disjoint cells and every launch has its own queue words and
+        // redo list, so with one workgroup per item the captured step graph
+        // runs them as parallel branches: one branch on `st`, the others on
+        // side streams forked from and joined back into it.  Eager launches
+        // (timed runs, serving) keep every launch in order on the caller's
+        // stream.
+        size_t branches = 0;
+        for (const ChiLaunch &L : chi) branches += L.n_items > 0;
         const bool fork = !ev && !persistent && branches > 1 && st == capture_stream;
         if (fork) {
             const int rc = ensure_side(branches);
@@ -800,12 +812,9 @@ struct LaunchPlan {
         auto chi_pass = [&](double dchi, uint32_t k, uint32_t tag) -> int {
             if (fork) {
                 HIP_TRY(hipEventRecord(fork_ev, st));
-                for (const ChiLaunch &L : chi)
-                    if (L.n_items > 0 && L.mode == kChiLane16)
-                        HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag));
-                size_t b = n16 > 0;  // branch 0 (`st`) is taken when it ran the compact launches
+                size_t b = 0;
                 for (const ChiLaunch &L : chi) {
-                    if (L.n_items == 0 || L.mode == kChiLane16) continue;
+                    if (L.n_items == 0) continue;
                     if (b == 0) {
                         HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag));
                     } else {
@@ -860,6 +869,7 @@ struct LaunchPlan {
         std::vector<ChiLaunch> launches;
         plan_chi(members, mode, cus * 4, items, launches);
         if (items.size() > chi_items_cap) return fail(TISSUE_EINVAL, "chi item region too small");
+        if (launches.size() > (size_t)kMaxChiLaunches) return fail(TISSUE_EINVAL, "too many chi launch groups");
         HIP_TRY(hipStreamSynchronize(stream));
         if (!items.empty()) {
             std::unique_lock<std::mutex> lk;
@@ -954,6 +964,7 @@ struct LaunchPlan {
             longest = per_group[g];
             T.chi_kernel = chi[g].mode == kChiRow ? (chi[g].rw > std::max(16, chi[g].P) ? kModeRowWide : kModeRow)
                          : chi[g].mode == kChiLane16 ? kModeLane16 : kModeLane;
+            T.chi_leaves = chi[g].P;
         }
         float tot = 0.f;
         HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
@@ -1112,7 +1123,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     {
         std::unique_lock<std::mutex> lk;
         unsigned char *h = nullptr;
-        const size_t up = p.off_ctl + 64;
+        const size_t up = p.off_lq + kLaunchQueueBytes;
         HIP_TRY(staging_acquire(lk, up, &h));
         std::memcpy(h + p.off_tissue, &R, sizeof(DevTissue));
         std::memcpy(h + p.off_tbl, &d_rec, sizeof(DevTissue *));
@@ -1125,7 +1136,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
         std::memcpy(h + p.off_models, p.models.data(), p.models.size() * sizeof(DevModel));
         std::memset(h + p.off_chi, 0, p.off_s - p.off_chi);
         if (!s_all.empty()) std::memcpy(h + p.off_s, s_all.data(), s_all.size() * sizeof(SItem));
-        std::memset(h + p.off_ctl, 0, 64);
+        std::memset(h + p.off_ctl, 0, up - p.off_ctl);
         HIP_TRY(hipMemcpyAsync(base, h, up, hipMemcpyHostToDevice, st));
         if (p.trace_steps)
             HIP_TRY(hipMemsetAsync(base + p.off_trace, 0,
@@ -1139,6 +1150,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     L.tbl = reinterpret_cast<DevTissue **>(base + p.off_tbl);
     L.n_tissues = 1;
     L.queue = reinterpret_cast<uint32_t *>(base + p.off_ctl + 32);
+    L.lq = reinterpret_cast<uint32_t *>(base + p.off_lq);
     L.stream = st;
     L.cus = cus;
     L.strang = p.strang;
@@ -1356,7 +1368,7 @@ int tissue_destroy(tissue_t *t)
 namespace {
 
 struct BatchLayout {
-    size_t off_tbl = 0, off_queue = 0, off_chi = 0, off_s = 0, off_retry = 0, bytes = 0;
+    size_t off_tbl = 0, off_queue = 0, off_lq = 0, off_chi = 0, off_s = 0, off_retry = 0, bytes = 0;
     size_t chi_cap = 0;
     std::vector<std::vector<SItem>> s_passes;
 };
@@ -1404,6 +1416,7 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
     };
     B.off_tbl = take((size_t)n * sizeof(DevTissue *));
     B.off_queue = take(64);
+    B.off_lq = take(kLaunchQueueBytes);
     B.off_chi = take(B.chi_cap * sizeof(ChiItem));
     B.off_s = take(n_s * sizeof(SItem));
     size_t cells = 0;
@@ -1451,7 +1464,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
         const size_t up = B.off_s + s_all.size() * sizeof(SItem);
         HIP_TRY(staging_acquire(lk, up, &h));
         std::memcpy(h + B.off_tbl, tbl.data(), tbl.size() * sizeof(DevTissue *));
-        std::memset(h + B.off_queue, 0, 64);
+        std::memset(h + B.off_queue, 0, B.off_chi - B.off_queue);
         if (!s_all.empty()) std::memcpy(h + B.off_s, s_all.data(), s_all.size() * sizeof(SItem));
         HIP_TRY(hipMemcpyAsync(b->dev, h, up, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -1460,6 +1473,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     L.tbl = reinterpret_cast<DevTissue **>(b->dev + B.off_tbl);
     L.n_tissues = (uint32_t)n;
     L.queue = reinterpret_cast<uint32_t *>(b->dev + B.off_queue);
+    L.lq = reinterpret_cast<uint32_t *>(b->dev + B.off_lq);
     L.stream = st;
     L.cus = cus;
     L.strang = ts[0]->plan.strang;

@@ -103,16 +103,20 @@ std::string network_source(const DevModel &M)
       << "    tissue_impl::chi_lane_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
       << "        persistent, cells_per_item, log2p, dt, kstep, tag, n_items_dev);\n"
       << "}\n"
-      << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane16(\n"
-      << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
-      << "    int persistent, int cells_per_item, double dt, uint32_t kstep, uint32_t tag,\n"
-      << "    ChiItem *retry_items, uint32_t *retry_count)\n"
-      << "{\n"
-      << "    extern __shared__ __align__(16) unsigned char lds[];\n"
-      << "    tissue_impl::chi_lane16_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
-      << "        persistent, cells_per_item, dt, kstep, tag, retry_items, retry_count);\n"
-      << "}\n"
       ;
+    for (int gl : {1, 2, 4}) {
+        o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane16"
+          << (gl == 1 ? std::string() : "x" + std::to_string(gl)) << "(\n"
+          << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
+          << "    int persistent, int cells_per_item, double dt, uint32_t kstep, uint32_t tag,\n"
+          << "    ChiItem *retry_items, uint32_t *retry_count)\n"
+          << "{\n"
+          << "    extern __shared__ __align__(16) unsigned char lds[];\n"
+          << "    tissue_impl::chi_lane16_body<tissue_impl::NetCompiled, " << gl
+          << ">(lds, tbl, items, n_items,\n"
+          << "        queue, persistent, cells_per_item, dt, kstep, tag, retry_items, retry_count);\n"
+          << "}\n";
+    }
     for (int rw : {16, 32, 64}) {
         o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row"
           << (rw == 16 ? std::string() : std::to_string(rw)) << "(\n"
@@ -190,6 +194,8 @@ int jit_kernels(const DevModel &M, const JitKernels **out, std::string &err)
     if (e == hipSuccess) e = hipModuleGetFunction(&k->row32, k->module, "tissue_chi_row32");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->row64, k->module, "tissue_chi_row64");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16, k->module, "tissue_chi_lane16");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16x2, k->module, "tissue_chi_lane16x2");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16x4, k->module, "tissue_chi_lane16x4");
     if (e != hipSuccess) {
         err = std::string("loading the compiled network: ") + hipGetErrorString(e);
         return -1;

@@ -16,6 +16,8 @@ struct JitKernels {
     hipFunction_t row32 = nullptr; // one 32-lane row per cell (17..32 voxels)
     hipFunction_t row64 = nullptr; // one 64-lane row per cell (33..64 voxels)
     hipFunction_t lane16 = nullptr; // one lane per cell, compact LDS
+    hipFunction_t lane16x2 = nullptr; // compact, 2 lanes per cell (17..32 voxels)
+    hipFunction_t lane16x4 = nullptr; // compact, 4 lanes per cell (33..64 voxels)
 };
 
 // Cache key of a network's structure (not its rates).

@@ -8,9 +8,13 @@
 namespace tissue_impl {
 
 // Dynamic LDS bytes of one chi workgroup (lane mode: per cell 2P FP64 tree
-// nodes and P*S int32 counts; lane16: 16 FP64 leaves and 16*S uint16 counts;
-// row mode: none).
+// nodes and P*S int32 counts; compact (lane16) mode: per lane 16 FP64 leaves
+// and 16*S uint16 counts, P / 16 lanes for cells of P > 16 leaves; row mode:
+// none).
 size_t chi_lds_bytes(int mode, int P, int S, int cells_per_item);
+
+// Lanes per cell of the compact layout for cells of P leaves (P <= 64).
+inline int compact_lanes(int P) { return P > 16 ? P / 16 : 1; }
 
 // Arguments of one chi launch.
 struct ChiArgs {
@@ -36,6 +40,14 @@ struct ChiArgs {
 // diffusing species.
 void chi_variant(int S, int R, int ND, int &SM, int &RM, int &NDM);
 hipError_t launch_chi(int SM, int RM, int NDM, const ChiArgs &a);
+// The generic chi kernels of one row of table sizes (chi_generic.hip, one
+// translation unit per row): species slots x diffusion slots 4x0, 4x4, 8x0,
+// 8x4, 8x8, for reaction slots RM = 4, 8, 12 or 16.
+hipError_t launch_chi_part0(int RM, const ChiArgs &a);
+hipError_t launch_chi_part1(int RM, const ChiArgs &a);
+hipError_t launch_chi_part2(int RM, const ChiArgs &a);
+hipError_t launch_chi_part3(int RM, const ChiArgs &a);
+hipError_t launch_chi_part4(int RM, const ChiArgs &a);
 hipError_t launch_s(uint32_t grid, hipStream_t stream, const DevTissue *const *tbl,
                     const SItem *items, uint32_t n_items, uint32_t *queue, int persistent,
                     double dt, uint32_t kstep);

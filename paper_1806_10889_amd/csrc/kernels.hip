@@ -1,6 +1,7 @@
 // kernels.hip -- the device kernels of one splitting step on gfx950, compiled
-// ahead of time: chi with the generic network policy (chi_kernels.h), the
-// signalling operator S, and the step-counter advance.
+// ahead of time: the signalling operator S and the step-counter advance,
+// and the launchers (the chi kernels with the generic network policy are
+// compiled from chi_generic.hip).
 //
 // S (cell signalling; paper: "Cell signaling module" and the translation
 // scripts, Results > Model: Delta within reach of a single shared face turns
@@ -14,45 +15,6 @@
 #include "kernels.h"
 
 namespace tissue_impl {
-
-// chi with the generic (runtime-table) network policy
-template <int SM, int RM, int NDM>
-__global__ __launch_bounds__(kWave) void chi_lane_kernel(const DevTissue *const *tbl,
-                                                         const ChiItem *items, uint32_t n_items,
-                                                         uint32_t *queue, int persistent,
-                                                         int cells_per_item, int log2p, double dt,
-                                                         uint32_t kstep, uint32_t tag,
-                                                         uint32_t *n_items_dev)
-{
-    extern __shared__ __align__(16) unsigned char lds[];
-    chi_lane_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
-                                           cells_per_item, log2p, dt, kstep, tag, n_items_dev);
-}
-
-template <int SM, int RM, int NDM>
-__global__ __launch_bounds__(kWave) void chi_lane16_kernel(const DevTissue *const *tbl,
-                                                           const ChiItem *items, uint32_t n_items,
-                                                           uint32_t *queue, int persistent,
-                                                           int cells_per_item, double dt,
-                                                           uint32_t kstep, uint32_t tag,
-                                                           ChiItem *retry_items, uint32_t *retry_count)
-{
-    extern __shared__ __align__(16) unsigned char lds[];
-    chi_lane16_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
-                                             cells_per_item, dt, kstep, tag, retry_items,
-                                             retry_count);
-}
-
-template <int SM, int RM, int NDM, int RW>
-__global__ __launch_bounds__(kWave) void chi_row_kernel(const DevTissue *const *tbl,
-                                                        const ChiItem *items, uint32_t n_items,
-                                                        uint32_t *queue, int persistent, double dt,
-                                                        uint32_t kstep, uint32_t tag)
-{
-    __shared__ RowShared sh;
-    chi_row_body<NetGeneric<SM, RM, NDM>, RW>(sh, tbl, items, n_items, queue, persistent, dt,
-                                              kstep, tag);
-}
 
 // ---------------------------------------------------------------------------
 // S: one lane per edge
@@ -280,46 +242,13 @@ __global__ void advance_kernel(DevTissue *const *tbl, uint32_t n_tissues, uint32
 size_t chi_lds_bytes(int mode, int P, int S, int cells_per_item)
 {
     if (mode == kChiRow) return 0;  // static LDS only
-    if (mode == kChiLane16) return lane16_lds_bytes(S, cells_per_item);
+    // compact: cells of P > 16 leaves take P / 16 lanes each
+    if (mode == kChiLane16) return lane16_lds_bytes(S, cells_per_item * compact_lanes(P));
     // per cell: the tree (2P doubles) and P*S counts, plus slack for the
     // species-slot reads past the last voxel
     return (size_t)cells_per_item * ((size_t)2 * P * 8 + ((size_t)P * S + kMaxSpecies) * 4);
 }
 
-namespace {
-
-int log2_exact(int P)
-{
-    int l = 0;
-    while ((1 << l) < P) ++l;
-    return l;
-}
-
-template <int SM, int RM, int NDM>
-hipError_t launch_variant(const ChiArgs &a)
-{
-    if (a.mode == kChiRow && a.rw == 64) {
-        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 64>), dim3(a.grid), dim3(kWave), 0, a.stream,
-                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
-    } else if (a.mode == kChiRow && a.rw == 32) {
-        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 32>), dim3(a.grid), dim3(kWave), 0, a.stream,
-                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
-    } else if (a.mode == kChiRow) {
-        hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 16>), dim3(a.grid), dim3(kWave), 0, a.stream,
-                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
-    } else if (a.mode == kChiLane16) {
-        hipLaunchKernelGGL((chi_lane16_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
-                           a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count);
-    } else {
-        hipLaunchKernelGGL((chi_lane_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
-                           a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, log2_exact(a.P), a.dt, a.kstep, a.tag, a.n_items_dev);
-    }
-    return hipGetLastError();
-}
-
-}  // namespace
 
 // table sizes of a network: species slots 4 or 8, reactions rounded up to a
 // multiple of 4, diffusion channels 0, 4 or 8
@@ -333,18 +262,13 @@ void chi_variant(int S, int R, int ND, int &SM, int &RM, int &NDM)
 
 hipError_t launch_chi(int SM, int RM, int NDM, const ChiArgs &a)
 {
-#define TISSUE_VARIANT(sm, rm, nd) \
-    if (SM == sm && RM == rm && NDM == nd) return launch_variant<sm, rm, nd>(a);
-#define TISSUE_VARIANTS_R(sm, nd)                                                               \
-    TISSUE_VARIANT(sm, 4, nd) TISSUE_VARIANT(sm, 8, nd) TISSUE_VARIANT(sm, 12, nd)              \
-    TISSUE_VARIANT(sm, 16, nd)
-    TISSUE_VARIANTS_R(4, 0)
-    TISSUE_VARIANTS_R(4, 4)
-    TISSUE_VARIANTS_R(8, 0)
-    TISSUE_VARIANTS_R(8, 4)
-    TISSUE_VARIANTS_R(8, 8)
-#undef TISSUE_VARIANTS_R
-#undef TISSUE_VARIANT
+    // each (species slots, diffusion slots) row of variants is compiled in
+    // its own translation unit (chi_generic.hip built once per part)
+    if (SM == 4 && NDM == 0) return launch_chi_part0(RM, a);
+    if (SM == 4 && NDM == 4) return launch_chi_part1(RM, a);
+    if (SM == 8 && NDM == 0) return launch_chi_part2(RM, a);
+    if (SM == 8 && NDM == 4) return launch_chi_part3(RM, a);
+    if (SM == 8 && NDM == 8) return launch_chi_part4(RM, a);
     return hipErrorInvalidValue;
 }
 

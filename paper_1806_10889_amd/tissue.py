@@ -74,7 +74,7 @@ class Stats(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("chi_ms", C.c_double), ("s_ms", C.c_double), ("total_ms", C.c_double),
                 ("chi_launches", C.c_uint32), ("s_launches", C.c_uint32),
-                ("chi_kernel", C.c_int32)]
+                ("chi_kernel", C.c_int32), ("chi_leaves", C.c_int32)]
 
 
 EXPORTS = [
@@ -269,7 +269,7 @@ class Tissue:
         _check(lib.tissue_step_timed(self.handle, float(dt), int(n_steps), C.byref(t)), "tissue_step_timed")
         return dict(chi_ms=t.chi_ms, s_ms=t.s_ms, total_ms=t.total_ms,
                     chi_launches=t.chi_launches, s_launches=t.s_launches,
-                    chi_kernel=t.chi_kernel)
+                    chi_kernel=t.chi_kernel, chi_leaves=t.chi_leaves)
 
     def read_counts(self, allow_flags: bool = False) -> np.ndarray:
         out = np.empty(self.n_values, dtype=np.int32)
@@ -370,7 +370,7 @@ class Batch:
                "tissue_batch_step_timed")
         return dict(chi_ms=t.chi_ms, s_ms=t.s_ms, total_ms=t.total_ms,
                     chi_launches=t.chi_launches, s_launches=t.s_launches,
-                    chi_kernel=t.chi_kernel)
+                    chi_kernel=t.chi_kernel, chi_leaves=t.chi_leaves)
 
     def set_launch(self, persistent: bool, workgroups_per_cu: int = 0):
         _check(lib.tissue_batch_set_launch(self.handle, int(bool(persistent)), int(workgroups_per_cu)),

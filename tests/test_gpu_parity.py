@@ -19,8 +19,8 @@ def _oracle(oracle_lib, p, n, trace=True, **kw):
     return oracle_lib.run(p, p["dt"], n, trace=trace, **kw)
 
 
-# chi kernel: one lane per cell / one 16-lane row per cell / compact lane16 /
-# rows of 32 lanes for the small cells
+# chi kernel: one lane per cell / one 16-lane row per cell / the compact
+# layout (1, 2 or 4 lanes per cell) / rows of 32 lanes for the small cells
 MODES = [0, 1, 3, 4]
 
 
@@ -57,7 +57,7 @@ def test_uneven_meshes_overlapping_faces(oracle_lib, lattice, mode, jit):
 
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("mesh", [(1, 1), (2, 2), (2, 1), (3, 5), (8, 8), (7, 3), (1, 8), (4, 4),
-                                  (2, 8)])
+                                  (2, 8), (5, 5), (5, 7), (6, 6), (8, 4)])
 def test_mesh_shapes(oracle_lib, mesh, mode):
     p = W.random_problem(40 + mesh[0] * 8 + mesh[1], lattice=1, nx=5, ny=4, model="nd5",
                          mesh=mesh, dt=0.05, n_steps=4)
@@ -282,6 +282,27 @@ def test_lane16_redo_of_wide_counts(oracle_lib, jit):
     assert_same(gpu_run(p, 4, trace=True, chi_mode=3, jit=jit), o)
 
 
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("mesh", [(5, 5), (8, 8), (5, 7)])
+def test_compact_wide_cells_redo_of_wide_counts(oracle_lib, mesh, jit):
+    """Cells of 17..64 voxels in the compact layout (2 or 4 lanes per cell):
+    counts that reach 2^16 in a voxel held by any lane of the group (during
+    a step, or from the start) hand the cell to the full-width redo; jumps
+    cross the lanes' voxel ranges; same bits as the oracle."""
+    w, h = mesh
+    V = w * h
+    p = W.random_problem(96 + V, lattice=1, nx=9, ny=8, model="nd5", mesh=mesh, dt=0.05,
+                         n_steps=4)
+    x = p["init_counts"].reshape(72, V, 5)
+    x[3, V - 1, 0] = 65530       # the cell's last lane crosses 2^16 under production
+    x[17, 16, 0] = 65534         # first voxel of the second lane
+    x[40, 2, 4] = 70000          # starts above 2^16 in the first lane
+    x[41, ::16, 1] = 65535       # the first voxel of every lane
+    p["rates"][0] = 50.0
+    o = _oracle(oracle_lib, p, 4)
+    assert_same(gpu_run(p, 4, trace=True, chi_mode=3, jit=jit), o)
+
+
 @pytest.mark.parametrize("mode,expect", [(0, 0), (1, 1), (3, 3), (2, 1), (4, 4)])
 def test_step_timed_same_bits_and_reports_kernel(oracle_lib, mode, expect):
     """The eagerly launched, event-bracketed steps give the oracle's bits, one
@@ -416,10 +437,10 @@ def test_classes_in_parallel_graph_branches(oracle_lib, scheme, jit):
 
 @pytest.mark.parametrize("scheme", ["lie", "strang"])
 def test_compact_launches_with_redo_in_forked_graphs(oracle_lib, scheme):
-    """Compact-layout launches of several leaf-count classes, each handing
-    cells back for the full-width redo, inside step graphs that fork the
-    other classes into parallel branches: the compact launches share the
-    redo list, so they stay in order; same bits as the oracle."""
+    """Compact-layout launches of several leaf-count classes (1, 2 and 4
+    lanes per cell), each handing cells back for the full-width redo, as
+    parallel branches of the step graphs (each launch with its own queue
+    words and part of the redo list); same bits as the oracle."""
     p = W.random_problem(39, lattice=0, nx=9, ny=7, model="nd5", uneven=True, dt=0.05, n_steps=4)
     p["scheme"] = scheme
     P = [1 << int(np.ceil(np.log2(w * h))) for w, h in zip(p["mesh_w"], p["mesh_h"])]
@@ -427,10 +448,10 @@ def test_compact_launches_with_redo_in_forked_graphs(oracle_lib, scheme):
     x = p["init_counts"]
     wide = {}
     for c, pc in enumerate(P):
-        if pc <= 16 and wide.get(pc, 0) < 2:
-            x[off[c], 0] = 65535
+        if wide.get(pc, 0) < 2:
+            x[off[c + 1] - 1, 0] = 65535
             wide[pc] = wide.get(pc, 0) + 1
-    assert len(wide) >= 3 and any(pc > 16 for pc in P)
+    assert len(wide) >= 5 and 32 in wide and 64 in wide
     o = _oracle(oracle_lib, p, 4)
     g = gpu_run(p, 4, trace=True, persistent=False, graph_chunk=2, chi_mode=3)
     assert_same(g, o)
