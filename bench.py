@@ -85,8 +85,12 @@ def traffic_bytes(leg: str, kernel: str):
     return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
 
 
-def chi_kernel_name(mode: int, jit: bool) -> str:
-    base = {0: "lane", 1: "row", 3: "lane16"}.get(mode, "unknown")
+def chi_kernel_name(mode: int, jit: bool, leaves: int = 16) -> str:
+    base = {0: "lane", 1: "row", 3: "lane16", 4: "row"}.get(mode, "unknown")
+    if base == "lane16" and leaves > 16:
+        base += f"x{leaves // 16}"  # the compact layout with 2 or 4 lanes per cell
+    if base == "row" and jit and (leaves > 16 or mode == 4):
+        base += str(max(leaves, 32) if mode == 4 else leaves)
     return f"tissue_chi_{base}" if jit else f"chi_{base}_kernel"
 
 
@@ -157,7 +161,7 @@ def run_single(args, torch, T, p, leg, sims, warmup):
     chi_avg_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
     s_avg_ms = tm["s_ms"] / max(tm["s_launches"], 1)
     achieved = chi_per_launch * OPS_PER_CHI_EVENT / (chi_avg_ms * 1e-3)
-    kernel = chi_kernel_name(tm["chi_kernel"], bool(st["jit"]))
+    kernel = chi_kernel_name(tm["chi_kernel"], bool(st["jit"]), tm["chi_leaves"])
     roof = {
         "bound": "alu", "kernel": kernel,
         "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
@@ -217,7 +221,7 @@ def run_batched(args, torch, T, W):
     chi_ev = sum(t.stats()["chi_events"] for t in ts)
     per_launch_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
     achieved = chi_ev / max(tm["chi_launches"], 1) * OPS_PER_CHI_EVENT / (per_launch_ms * 1e-3)
-    kernel = chi_kernel_name(tm["chi_kernel"], bool(ts[0].stats()["jit"]))
+    kernel = chi_kernel_name(tm["chi_kernel"], bool(ts[0].stats()["jit"]), tm["chi_leaves"])
     out["roofline"] = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
                        "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                        "frac": achieved / PEAK_LANE_OPS,

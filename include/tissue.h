@@ -248,10 +248,11 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
  * FP64 leaves and 16-bit counts, the tree levels above them rebuilt in
  * registers and combined across the cell's lanes; cells that reach 2^16
  * molecules of a species are handed to a full-width lane launch that redoes
- * their step; 2 = automatic (the default): for cells of 9 to 16 voxels,
- * rows when that class has fewer cells than 64 per SIMD of the device, else
- * the compact layout; mode 0 for all other cells.  Results are
- * bit-identical for every choice.  Other values: TISSUE_EINVAL. */
+ * their step; 2 = automatic (the default): cells of at most 8 voxels take
+ * mode 0; a class of cells of 9 to 64 voxels takes the compact layout when
+ * it holds at least 16 lanes of it per SIMD of the device (cells x P / 16),
+ * else rows.  Results are bit-identical for every choice.  Other values:
+ * TISSUE_EINVAL. */
 int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 
 /* Steps captured per HIP graph launch (0 disables graphs). */

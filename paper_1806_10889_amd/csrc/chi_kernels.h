@@ -871,6 +871,19 @@ __device__ __forceinline__ uint32_t group_or(uint32_t x)
 
 }  // namespace
 
+// The value of lane k of the lane's group of G lanes (a pair or a quad), for
+// a wave-uniform k < G.
+template <int G>
+__device__ __forceinline__ double group_bcast_f64(double v, uint32_t k)
+{
+    if (G == 2)
+        return k == 0 ? dpp_f64<0xA0>(v) : dpp_f64<0xF5>(v);  // quad_perm [0,0,2,2] / [1,1,3,3]
+    if (k == 0) return dpp_f64<0x00>(v);                     // quad_perm [0,0,0,0]
+    if (k == 1) return dpp_f64<0x55>(v);                     // [1,1,1,1]
+    if (k == 2) return dpp_f64<0xAA>(v);                     // [2,2,2,2]
+    return dpp_f64<0xFF>(v);                                 // [3,3,3,3]
+}
+
 template <class NET, int G>
 __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTissue *const *tbl,
                                                 const ChiItem *items, uint32_t n_items,
@@ -947,12 +960,23 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
         uint32_t j = 0, ev = 0;
         bool capped = false;
         if (active && !retry) {
-            double e1, u2;
+            // Draws: with G lanes per cell, lane k of the group makes the
+            // draw of every ordinal = k (mod G), G at a time, and the group
+            // reads ordinal j's from its lane j mod G.  Every running group
+            // has made exactly one draw per iteration, so j is wave-uniform.
+            double e1, u2, eo = 0.0, uo = 0.0;
             {
-                const tdev::Words4 wds = tdev::philox4x32_10(0u, c.step, cell, c.tagword, c.key0, c.key1);
+                const tdev::Words4 wds = tdev::philox4x32_10((uint32_t)(G > 1 ? sub : 0), c.step, cell,
+                                                             c.tagword, c.key0, c.key1);
                 double u1;
-                tdev::two_uniforms(wds, u1, u2);
-                e1 = -tdev::plog(u1);
+                tdev::two_uniforms(wds, u1, uo);
+                eo = -tdev::plog(u1);
+                e1 = eo;
+                u2 = uo;
+                if (G > 1) {
+                    e1 = group_bcast_f64<G>(eo, 0u);
+                    u2 = group_bcast_f64<G>(uo, 0u);
+                }
             }
             for (;;) {
                 // the lane's 16 leaves and the levels of its subtree
@@ -993,11 +1017,22 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 if (tn >= dt) break;
                 t = tn;
                 double r = u2 * a0;
-                {
+                if (G == 1) {
                     const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
                     double u1;
                     tdev::two_uniforms(wds, u1, u2);
                     e1 = -tdev::plog(u1);
+                } else {
+                    const uint32_t k = uni(j) & (uint32_t)(G - 1);
+                    if (k == 0) {  // the next G ordinals, one per lane of the group
+                        const tdev::Words4 wds = tdev::philox4x32_10(j + (uint32_t)sub, c.step, cell,
+                                                                     c.tagword, c.key0, c.key1);
+                        double u1;
+                        tdev::two_uniforms(wds, u1, uo);
+                        eo = -tdev::plog(u1);
+                    }
+                    e1 = group_bcast_f64<G>(eo, k);
+                    u2 = group_bcast_f64<G>(uo, k);
                 }
                 // descent through the group's levels: only the lane whose
                 // subtree the path enters stays `on`

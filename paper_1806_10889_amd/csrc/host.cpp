@@ -532,12 +532,15 @@ struct ChiLaunch {
 };
 
 // chi mode request: lane, row, automatic, compact (lane16), or wide rows.
-// Automatic: for classes of at most 16 voxels, row mode when one lane per
-// cell would not give every SIMD a wavefront, else the compact layout;
-// larger cells: lane mode.  Compact: every class in the compact layout
-// (P / 16 lanes per cell above 16 leaves).  Wide rows: rows of max(32, P)
-// lanes, half as many cells per wavefront as rows of 16 for the small
-// cells, so twice the wavefronts.
+// Automatic: cells of at most 8 leaves take the lane layout (small in LDS,
+// few tree levels; a row would idle most of its lanes); classes of 16, 32
+// or 64 leaves take the compact layout when it has at least 16 lanes of
+// work per SIMD of the device (cells x P / 16), else rows of P lanes, whose
+// event chains are shorter (one voxel per lane) but which spend a row of
+// lanes per event.  Compact: every class in the compact layout (P / 16
+// lanes per cell above 16 leaves).  Wide rows: rows of max(32, P) lanes,
+// half as many cells per wavefront as rows of 16 for the small cells, so
+// twice the wavefronts.
 enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2, kModeLane16 = 3, kModeRowWide = 4 };
 
 // Work items and launches of the chi operator over a set of tissues: one
@@ -596,13 +599,9 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
             rw = std::max(32, k.P);
         }
         if (mode_req == kModeLane16 && k.P <= 64) mode = kChiLane16;
-        if (k.P <= 16) {
-            // automatic: cells of at most 8 leaves keep the full lane layout
-            // (small in LDS, few tree levels; a row would idle most of its
-            // lanes); 16-leaf cells take rows when one lane per cell would
-            // leave SIMDs without a wavefront, else the compact layout
-            if (mode_req == kModeAuto && k.P == 16)
-                mode = cells < (uint64_t)kWave * (uint64_t)std::max(n_simd, 1) ? kChiRow : kChiLane16;
+        if (mode_req == kModeAuto && k.P >= 16 && k.P <= 64) {
+            const uint64_t lanes = cells * (uint64_t)compact_lanes(k.P);
+            mode = lanes >= 16ull * (uint64_t)std::max(n_simd, 1) ? kChiLane16 : kChiRow;
         }
         ChiLaunch L;
         L.mode = mode;

@@ -307,7 +307,7 @@ def test_compact_wide_cells_redo_of_wide_counts(oracle_lib, mesh, jit):
 def test_step_timed_same_bits_and_reports_kernel(oracle_lib, mode, expect):
     """The eagerly launched, event-bracketed steps give the oracle's bits, one
     chi launch and the same S passes per step, and name the chi layout that ran (auto
-    takes rows for a tissue with fewer cells than 64 per SIMD)."""
+    takes rows for a tissue with fewer than 16 lanes of compact work per SIMD)."""
     from paper_1806_10889_amd import tissue as T
     p = W.config2(side=9, n_steps=7)
     o = _oracle(oracle_lib, p, 7, trace=False)
