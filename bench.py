@@ -15,7 +15,7 @@ FP64 oracle's rate on a bounded sample on the host cores, the batched form
 (512 tissues in one batch, with its own roofline) and the serving loop
 (Poisson arrivals, continuous batching, p50/p99 latency).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--leg all|plain|uneven|batched|serving|dt|notch|multifidelity]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--leg all|plain|uneven|batched|serving|dt|notch|multifidelity|large]
 """
 from __future__ import annotations
 
@@ -549,6 +549,50 @@ def run_multifidelity(args, torch, T, W):
     return res
 
 
+def run_large_cells(args, torch, T, W):
+    """Cells of 25 and 64 voxels (5x5 and 8x8 meshes) on hex tissues of
+    1024, 4096 and 16384 cells, 5-species network, dt 0.05: events/s of the
+    one-lane-per-cell layout (mode 0), rows of 32 or 64 lanes (mode 1), the
+    compact layout with 2 or 4 lanes per cell (mode 3) and the automatic
+    choice (mode 2), over 40 splitting steps replayed from graphs."""
+    import numpy as np
+    steps = 40
+    rows = []
+    for (w, h) in ((5, 5), (8, 8)):
+        for side in (32, 64, 128):
+            rng = np.random.Generator(np.random.PCG64(2))
+            m = W.model_nd5()
+            c = 10.0 ** rng.uniform(-2.0, 1.0, size=m["n_reactions"] + 1)
+            x0 = rng.integers(0, 51, size=(side * side * w * h, 5)).astype(np.int32)
+            p = W.make_problem(m, lattice=1, nx=side, ny=side, mesh_w=w, mesh_h=h, rates=c[:-1],
+                               trans_rate=c[-1], diffusion=1.0, init_counts=x0, seed=2, dt=0.05,
+                               n_steps=steps)
+            row = {"cells": side * side, "mesh": f"{w}x{h}"}
+            ref = None
+            for mode in (0, 1, 3, 2):
+                t = T.Tissue(p, device="cuda:0")
+                t.set_chi_mode(mode)
+                t.set_launch(False, 0)
+                t.set_graph_chunk(20)
+                t.step(0.05, 20)  # warm-up (graph capture)
+                t.restart(sim_id=1, start_step=0)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                t.step(0.05, steps)
+                st = t.stats()
+                el = time.perf_counter() - a
+                got = t.read_counts()
+                if ref is None:
+                    ref = got
+                assert np.array_equal(got, ref), "layouts disagree"
+                row[{0: "lane", 1: "rows", 3: "compact", 2: "auto"}[mode]] = \
+                    (st["chi_events"] + st["s_events"]) / el
+                t.close()
+            log(f"large cells: {row}")
+            rows.append(row)
+    return {"unit": "events/s", "steps": steps, "dt": 0.05, "rows": rows}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -594,7 +638,7 @@ def main():
     ap.add_argument("--dt-replicas", type=int, default=16384)
     ap.add_argument("--dt-T", type=float, default=20.0)
     ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt", "notch",
-                                      "multifidelity"],
+                                      "multifidelity", "large"],
                     default="all",
                     help="run one leg only (profiling runs); the JSON line then carries that leg")
     ap.add_argument("--plain-only", action="store_true", help="same as --leg plain")
@@ -681,6 +725,8 @@ def main():
         out["notch"] = run_notch(args, torch, T, W)
     if leg == "multifidelity":
         out["multifidelity"] = run_multifidelity(args, torch, T, W)
+    if leg == "large":
+        out["large_cells"] = run_large_cells(args, torch, T, W)
     if leg == "serving" or (leg == "all" and not args.no_serve):
         out["serving"] = run_serving(args, torch)
     if leg == "all" and not args.no_cpu_baseline:

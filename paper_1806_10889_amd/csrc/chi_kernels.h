@@ -588,12 +588,15 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
 // ---------------------------------------------------------------------------
 namespace {
 
+// The value of another lane by a DPP lane pattern (all row and bank masks
+// on: every lane of an active group reads an active lane of the same row,
+// so no fallback value is needed and none is initialised).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int plo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-    const int phi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    const int plo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+    const int phi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
     return __hiloint2double(phi, plo);
 }
 
@@ -750,17 +753,13 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                 }
             }
             if (!__any(run)) break;
-            bool event = false;
-            if (run) {
-                ++j;
-                const double tn = t + e1 / a0;
-                if (tn >= dt) {
-                    run = false;
-                } else {
-                    t = tn;
-                    event = true;
-                }
-            }
+            // the clock, without a branch: the division then overlaps the
+            // descent below (a lane that is not running discards it)
+            const double tn = t + e1 / a0;
+            j += run ? 1u : 0u;
+            const bool event = run && !(tn >= dt);
+            run = event;
+            t = event ? tn : t;
             // which lane's leaf the descent reaches
             const int lvo = opaque(lv);
             double rr = u2 * a0;
@@ -1013,9 +1012,9 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     break;
                 }
                 ++j;
+                // the clock; the stop test waits until after the descent,
+                // which the division then overlaps (the descent only reads)
                 const double tn = t + e1 / a0;
-                if (tn >= dt) break;
-                t = tn;
                 double r = u2 * a0;
                 if (G == 1) {
                     const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
@@ -1070,6 +1069,8 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     r = left ? r : r - L;
                     v = 2 * i1 + (left ? 0 : 1);
                 }
+                if (tn >= dt) break;
+                t = tn;
 
                 const Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
                 bool wide = false;
