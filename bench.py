@@ -50,7 +50,7 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # HBM traffic of the dominant chi kernel per launch, from rocprofv3 counter
 # runs of this script's legs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch),
 # each scaled by what the counter reads for a plain 256 MiB device copy
-# (FETCH_SIZE 131087 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  The
+# (FETCH_SIZE 131085 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  The
 # figures hold for the kernel sources whose digest is recorded with them; any
 # change to those sources makes `traffic` null until the counters are taken
 # again.
@@ -58,11 +58,11 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC = {   # leg -> counters of its dominant chi kernel
     # hex 64x64 tissue, 4096 cells x 4x4 voxels: 400 dispatches of 200-step runs
-    "plain": {"digest": "75522784b51f5a6e7159c4bdae366a6aeb9ae163", "kernel": "tissue_chi_row",
-              "fetch_kib": 927.508, "write_kib": 1344.0},
+    "plain": {"digest": "de77a5ffc4b87656348286962846b2be0f8c0016", "kernel": "tissue_chi_row",
+              "fetch_kib": 934.522, "write_kib": 1344.0},
     # 512 tissues, 3.12M cells, 200 steps: 450 dispatches
-    "batched": {"digest": "75522784b51f5a6e7159c4bdae366a6aeb9ae163", "kernel": "tissue_chi_lane16",
-                "fetch_kib": 508879.0, "write_kib": 979152.0},
+    "batched": {"digest": "de77a5ffc4b87656348286962846b2be0f8c0016", "kernel": "tissue_chi_lane16",
+                "fetch_kib": 508939.0, "write_kib": 979182.0},
 }
 
 
@@ -172,8 +172,37 @@ def run_single(args, torch, T, p, leg, sims, warmup):
     }
     res = dict(p=p, value=events / elapsed, elapsed=elapsed, lat=lat, chi=chi_ev, s=s_ev,
                roofline=roof, timing=tm, tuned=tuned, jit=bool(t.stats()["jit"]))
+    cfg = (tuned or {}).get("config")
     t.close()
+    if args.chain_steps > 0:
+        res["roofline"]["event_chains"] = event_chains(args, T, p, cfg)
     return res
+
+
+def event_chains(args, T, p, cfg):
+    """The latency side of the chi launch: each cell's events in a step form
+    one dependent chain, and a launch lasts as long as its busiest cell's
+    chain.  A traced simulation over the first chain_steps steps (eager,
+    HIP events around every launch) gives, per step, the busiest cell's and
+    the mean cell's events, and the time per event along the busiest chain."""
+    import numpy as np
+    n = min(args.chain_steps, p["n_steps"])
+    t = T.Tissue(p, device="cuda:0", trace_steps=n)
+    if cfg:
+        from paper_1806_10889_amd import autotune
+        autotune.apply(t, cfg)
+    t.restart(sim_id=4242, start_step=0)
+    tm = t.step_timed(p["dt"], n)
+    ce = t.trace(0, n)[0].astype(np.float64)
+    t.close()
+    busiest = float(ce.max(axis=1).mean())
+    if tm["chi_launches"] != n:
+        return None  # several chi launches per step: no single chain per launch
+    launch_ms = tm["chi_ms"] / n
+    return {"steps": n, "busiest_cell_events_per_step": busiest,
+            "mean_cell_events_per_step": float(ce.mean()),
+            "avg_launch_ms": launch_ms,
+            "ns_per_event_on_busiest_chain": launch_ms * 1e6 / max(busiest, 1.0)}
 
 
 def run_batched(args, torch, T, W):
@@ -635,6 +664,8 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--roofline-steps", type=int, default=0,
                     help="steps of the eagerly timed roofline pass (0: the whole horizon)")
+    ap.add_argument("--chain-steps", type=int, default=200,
+                    help="steps of the traced pass that measures the busiest cell's event chain (0: skip)")
     ap.add_argument("--dt-replicas", type=int, default=16384)
     ap.add_argument("--dt-T", type=float, default=20.0)
     ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt", "notch",

@@ -1,8 +1,8 @@
 """Autotuner of the launch shape.
 
-The launch shape -- chi kernel (one lane per cell with a full sum tree, one
-lane per cell with the compact 16-leaf layout, or one 16-lane row per
-cell), persistent work queue or one workgroup per item, resident workgroups
+The launch shape -- chi kernel (one lane per cell with a full sum tree, the
+compact layout with one lane per 16 voxels of a cell, or one row of lanes
+per cell), persistent work queue or one workgroup per item, resident workgroups
 per CU, steps per captured HIP graph -- never changes results (every choice
 is bit-identical), only speed.  `tune` times candidate shapes on a clone of
 the workload (the same problems, restarted before each candidate so all see
@@ -38,10 +38,10 @@ def signature(problems) -> str:
 
 def candidates(max_voxels: int):
     out = []
-    # the compact layout applies to cells of at most 16 voxels (larger cells
-    # keep the full lane layout); rows (16 or 32 lanes for the small cells)
-    # cover every class; auto mixes them per leaf-count class
-    modes = [0, 1, 4, 3, 2] if max_voxels <= 16 else [0, 2, 1, 4, 3]
+    # every mode covers every leaf-count class (the compact layout with 1, 2
+    # or 4 lanes per cell; rows of 16, 32 or 64 lanes); auto mixes them per
+    # class; listed so that the likelier winners come first
+    modes = [0, 1, 4, 3, 2] if max_voxels <= 16 else [2, 3, 1, 0, 4]
     for mode in modes:
         for persistent, wpc in [(1, 0), (0, 0), (1, 2), (1, 8)]:
             for chunk in (25, 100):
