@@ -156,6 +156,38 @@ def test_batch_equals_plain_and_oracle(oracle_lib):
         assert st["steps_done"] == p["start_step"] + n
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_compact_wide_cells_with_redo(oracle_lib, persistent):
+    """A batch of uneven-mesh tissues in the compact layout (1, 2 and 4
+    lanes per cell): every member's cells of a class share one launch, and
+    cells of several members and classes reach 2^16 and are redone from
+    their launch's part of the redo list; graphs of 2 steps (classes as
+    parallel branches with one workgroup per item, or persistent grids);
+    every member against the oracle."""
+    from paper_1806_10889_amd import tissue as T
+    probs = [W.random_problem(120 + k, lattice=k % 2, nx=6, ny=5, model="nd5", uneven=True,
+                              dt=0.05, sim_id=10 + k, n_steps=4) for k in range(4)]
+    for k, p in enumerate(probs):
+        sz = p["mesh_w"].astype(np.int64) * p["mesh_h"]
+        off = np.concatenate([[0], np.cumsum(sz)])
+        big = np.flatnonzero(sz > 16)[:2]
+        small = np.flatnonzero(sz <= 16)[:1]
+        for c in list(big) + list(small):
+            p["init_counts"][off[c + 1] - 1 - k % 3, 0] = 65535
+    ts = [T.Tissue(p) for p in probs]
+    b = T.Batch(ts)
+    b.set_chi_mode(3)
+    b.set_launch(persistent)
+    b.set_graph_chunk(2)
+    b.step(0.05, 4)
+    b.sync()
+    for p, t in zip(probs, ts):
+        o = oracle_lib.run(p, 0.05, 4)
+        assert np.array_equal(t.read_counts(), o.counts), p["name"]
+        st = t.stats()
+        assert (st["chi_events"], st["s_events"], st["draws"]) == (o.chi_events, o.s_events, o.draws)
+
+
 @pytest.mark.parametrize("mode", [2, 3, 0])
 def test_config4_sampled_tissues(oracle_lib, mode):
     from paper_1806_10889_amd import tissue as T
