@@ -78,9 +78,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
+        path = os.environ.get("ORACLE_LIBRARY")  # another build of oracle.c (sanitizer runs)
+        if not path:
+            if not os.path.exists(_LIB):
+                build()
+            path = _LIB
+        L = C.CDLL(path)
         u32p = C.POINTER(C.c_uint32)
         L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.oracle_uniforms.argtypes = [u32p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
