@@ -349,8 +349,31 @@ def test_step_timed_same_bits_and_reports_kernel(oracle_lib, mode, expect):
     g = dict(counts=t.read_counts(), stats=t.stats())
     t.close()
     assert_same(g, o, trace=False)
-    assert tm["chi_kernel"] == expect
+    assert tm["chi_kernel"] == expect and tm["chi_leaves"] == 16
     assert tm["chi_launches"] == 7 and tm["s_launches"] >= 7 and tm["s_launches"] % 7 == 0
+
+
+def test_step_timed_names_the_dominant_class(oracle_lib):
+    """On a tissue of 4x4 and 8x8 cells in the compact layout the 64-leaf
+    class dominates the eager steps' device time, and the timing names it
+    (compact mode, 64 leaves); same bits as the oracle."""
+    from paper_1806_10889_amd import tissue as T
+    p = W.random_problem(130, lattice=1, nx=12, ny=12, model="nd5", mesh=(4, 4), dt=0.05, n_steps=3)
+    w = np.where(np.arange(144) % 4 == 0, 8, 4).astype(np.int32)
+    nvox = int((w * w).sum())
+    x0 = np.random.default_rng(130).integers(0, 51, size=(nvox, 5)).astype(np.int32)
+    q = W.make_problem(W.model_nd5(), lattice=1, nx=12, ny=12, mesh_w=w, mesh_h=w, rates=p["rates"],
+                       trans_rate=p["trans_rate"], diffusion=1.0, init_counts=x0, seed=130,
+                       dt=0.05, n_steps=3)
+    o = _oracle(oracle_lib, q, 3, trace=False)
+    t = T.Tissue(q)
+    t.set_chi_mode(3)
+    tm = t.step_timed(q["dt"], 3)
+    g = dict(counts=t.read_counts(), stats=t.stats())
+    t.close()
+    assert_same(g, o, trace=False)
+    assert tm["chi_kernel"] == 3 and tm["chi_leaves"] == 64
+    assert tm["chi_launches"] == 6
     assert 0 < tm["chi_ms"] <= tm["total_ms"] and 0 < tm["s_ms"] <= tm["total_ms"]
 
 
