@@ -19,6 +19,156 @@ namespace tissue_impl {
 // ---------------------------------------------------------------------------
 // S: one lane per edge
 // ---------------------------------------------------------------------------
+namespace {
+
+// The SSA of one edge over dt for face groups of MA and MB voxels known at
+// compile time: the counts in registers, every channel loop unrolled, the
+// same operations in the same order as the general path below (so the same
+// bits).  Reads the face counts, runs the events, writes the counts back.
+template <int MA, int MB>
+__device__ __forceinline__ void s_edge_fixed(int32_t *counts, long long gi, long long gj,
+                                             const uint8_t *A, const uint8_t *B, int S, int sp0,
+                                             int sp1, int sp2, bool first_order, double c,
+                                             double ci, double cj, double dt, uint32_t step,
+                                             uint32_t e, uint32_t tagword, uint32_t key0,
+                                             uint32_t key1, uint32_t cap, double &t, uint32_t &j,
+                                             uint32_t &ev, bool &overflow, bool &capped)
+{
+    int32_t na[MA], da[MA], ia[MA], nb[MB], db[MB], ib[MB];
+#pragma unroll
+    for (int a = 0; a < MA; ++a) {
+        const long long g = (gi + A[a]) * S;
+        na[a] = first_order ? 0 : counts[g + sp0];
+        da[a] = counts[g + sp1];
+        ia[a] = counts[g + sp2];
+    }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const long long g = (gj + B[b]) * S;
+        nb[b] = first_order ? 0 : counts[g + sp0];
+        db[b] = counts[g + sp1];
+        ib[b] = counts[g + sp2];
+    }
+    for (;;) {
+        // channels: first order ci D_i(a), then cj D_j(b); trans
+        // c N_i(a) D_j(b) for a, b, then c N_j(b) D_i(a) for b, a
+        constexpr int NCH = MA * MB * 2 > MA + MB ? MA * MB * 2 : MA + MB;
+        double p[NCH];
+        int nch;
+        if (first_order) {
+#pragma unroll
+            for (int a = 0; a < MA; ++a) p[a] = ci * (double)da[a];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) p[MA + b] = cj * (double)db[b];
+            nch = MA + MB;
+        } else {
+#pragma unroll
+            for (int a = 0; a < MA; ++a)
+#pragma unroll
+                for (int b = 0; b < MB; ++b)
+                    p[a * MB + b] = c * (double)((long long)na[a] * db[b]);
+#pragma unroll
+            for (int b = 0; b < MB; ++b)
+#pragma unroll
+                for (int a = 0; a < MA; ++a)
+                    p[MA * MB + b * MA + a] = c * (double)((long long)nb[b] * da[a]);
+            nch = 2 * MA * MB;
+        }
+        double a0 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k)
+            if (k < nch) a0 = a0 + p[k];
+        if (a0 == 0.0) break;
+        if (ev >= cap) {
+            capped = true;
+            break;
+        }
+        const tdev::Words4 wds = tdev::philox4x32_10(j, step, e, tagword, key0, key1);
+        ++j;
+        double u1, u2;
+        tdev::two_uniforms(wds, u1, u2);
+        const double tau = (-tdev::plog(u1)) / a0;
+        const double tn = t + tau;
+        if (tn >= dt) break;
+        t = tn;
+        const double r = u2 * a0;
+        double prefix = 0.0;
+        int sel = -1, last = -1;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            if (k < nch) {
+                const double next = prefix + p[k];
+                if (p[k] > 0.0) {
+                    if (sel < 0 && r < next) sel = k;
+                    last = k;
+                }
+                prefix = next;
+            }
+        }
+        if (sel < 0) sel = last;
+        if (first_order) {
+            // a Delta of face voxel k of one group becomes an NICD in voxel
+            // m' - 1 - floor(k m' / m) of the other
+            int32_t nD = 0, nI = 0;
+#pragma unroll
+            for (int a = 0; a < MA; ++a)
+                if (sel == a) {
+                    nD = --da[a];
+#pragma unroll
+                    for (int b = 0; b < MB; ++b)
+                        if (b == MB - 1 - (a * MB) / MA) nI = ++ib[b];
+                }
+#pragma unroll
+            for (int b = 0; b < MB; ++b)
+                if (sel == MA + b) {
+                    nD = --db[b];
+#pragma unroll
+                    for (int a = 0; a < MA; ++a)
+                        if (a == MA - 1 - (b * MA) / MB) nI = ++ia[a];
+                }
+            overflow |= (nD < 0) | (nI >= kCountLimit);
+        } else {
+            int32_t nN = 0, nD = 0, nI = 0;
+#pragma unroll
+            for (int a = 0; a < MA; ++a)
+#pragma unroll
+                for (int b = 0; b < MB; ++b)
+                    if (sel == a * MB + b) {
+                        nN = --na[a];
+                        nD = --db[b];
+                        nI = ++ia[a];
+                    }
+#pragma unroll
+            for (int b = 0; b < MB; ++b)
+#pragma unroll
+                for (int a = 0; a < MA; ++a)
+                    if (sel == MA * MB + b * MA + a) {
+                        nN = --nb[b];
+                        nD = --da[a];
+                        nI = ++ib[b];
+                    }
+            overflow |= (nN < 0) | (nD < 0) | (nI >= kCountLimit);
+        }
+        ++ev;
+    }
+#pragma unroll
+    for (int a = 0; a < MA; ++a) {
+        const long long g = (gi + A[a]) * S;
+        if (!first_order) counts[g + sp0] = na[a];
+        counts[g + sp1] = da[a];
+        counts[g + sp2] = ia[a];
+    }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const long long g = (gj + B[b]) * S;
+        if (!first_order) counts[g + sp0] = nb[b];
+        counts[g + sp1] = db[b];
+        counts[g + sp2] = ib[b];
+    }
+}
+
+}  // namespace
+
 __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, const SItem *items,
                                                   uint32_t n_items, uint32_t *queue,
                                                   int persistent, double dt, uint32_t kstep)
@@ -64,9 +214,18 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 A[a] = er->A[a];
                 B[a] = er->B[a];
             }
+            // face groups of 2 and 2 voxels (4x4 cells on the hexagonal
+            // lattice) and of 1 and 1 (well-mixed cells): counts in registers
+            const int fixed = (mA == 2 && mB == 2) ? 2 : (mA == 1 && mB == 1) ? 1 : 0;
+            if (fixed == 2)
+                s_edge_fixed<2, 2>(counts, gi, gj, A, B, S, sp0, sp1, sp2, first_order, c, ci, cj, dt,
+                                   step, e, tagword, key0, key1, cap, t, j, ev, overflow, capped);
+            else if (fixed == 1)
+                s_edge_fixed<1, 1>(counts, gi, gj, A, B, S, sp0, sp1, sp2, first_order, c, ci, cj, dt,
+                                   step, e, tagword, key0, key1, cap, t, j, ev, overflow, capped);
 #pragma unroll
             for (int a = 0; a < kMaxFace; ++a)
-                if (a < mA) {
+                if (fixed == 0 && a < mA) {
                     const long long g = (gi + A[a]) * S;
                     if (!first_order) fa[0][a][lane] = counts[g + sp0];
                     fa[1][a][lane] = counts[g + sp1];
@@ -74,7 +233,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 }
 #pragma unroll
             for (int b = 0; b < kMaxFace; ++b)
-                if (b < mB) {
+                if (fixed == 0 && b < mB) {
                     const long long g = (gj + B[b]) * S;
                     if (!first_order) fb[0][b][lane] = counts[g + sp0];
                     fb[1][b][lane] = counts[g + sp1];
@@ -85,7 +244,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
             // b in B; a Delta of face voxel k of one group becomes an NICD in
             // voxel m' - 1 - floor(k m' / m) of the other (they run in
             // opposite directions along the shared face)
-            while (first_order) {
+            while (fixed == 0 && first_order) {
                 double a0 = 0.0;
                 for (int a = 0; a < mA; ++a) a0 = a0 + ci * (double)fa[1][a][lane];
                 for (int b = 0; b < mB; ++b) a0 = a0 + cj * (double)fb[1][b][lane];
@@ -129,7 +288,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 ++ev;
             }
             for (;;) {
-                if (first_order) break;
+                if (fixed != 0 || first_order) break;
                 // channels: N_i(a) D_j(b) for a, b; then N_j(b) D_i(a) for b, a
                 double a0 = 0.0;
                 for (int a = 0; a < mA; ++a)
@@ -194,7 +353,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
             }
 #pragma unroll
             for (int a = 0; a < kMaxFace; ++a)
-                if (a < mA) {
+                if (fixed == 0 && a < mA) {
                     const long long g = (gi + A[a]) * S;
                     if (!first_order) counts[g + sp0] = fa[0][a][lane];
                     counts[g + sp1] = fa[1][a][lane];
@@ -202,7 +361,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 }
 #pragma unroll
             for (int b = 0; b < kMaxFace; ++b)
-                if (b < mB) {
+                if (fixed == 0 && b < mB) {
                     const long long g = (gj + B[b]) * S;
                     if (!first_order) counts[g + sp0] = fb[0][b][lane];
                     counts[g + sp1] = fb[1][b][lane];
