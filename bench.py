@@ -212,6 +212,7 @@ def run_batched(args, torch, T, W):
     stream = torch.cuda.current_stream()
     ts = [T.Tissue(p, device="cuda:0", stream=stream) for p in probs]
     b = T.Batch(ts, device="cuda:0", stream=stream)
+    b.set_regroup(args.regroup)
     dt, n = probs[0]["dt"], probs[0]["n_steps"]
 
     def one(k):
@@ -676,6 +677,8 @@ def main():
     ap.add_argument("--batch-tissues", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--batch-reps", type=int, default=1)
+    ap.add_argument("--regroup", type=int, default=2,
+                    help="batched leg: regroup cells by load before compact launches (0 off, 1 on, 2 auto)")
     ap.add_argument("--cpu-steps", type=int, default=1200)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="fixed launch shape instead of the autotuner")

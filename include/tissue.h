@@ -258,6 +258,16 @@ int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 /* Steps captured per HIP graph launch (0 disables graphs). */
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
 
+/* Regroup pass before each compact-layout chi launch: the cells of each
+ * leaf-count class (of each tissue) are reordered by their total propensity
+ * after the previous compact pass, largest first, so that the cells sharing
+ * a wavefront carry similar numbers of events.  mode 0 = off, 1 = on, 2 =
+ * automatic (the default: on when a launch holds at least two rounds of
+ * resident wavefronts).  Results are bit-identical either way: a cell's
+ * result depends only on its counts and its counters.  Other values:
+ * TISSUE_EINVAL.  Synchronises the tissue's stream. */
+int tissue_set_regroup(tissue_t *t, int32_t mode);
+
 /* Per-kernel device time of the last tissue_step_timed call, in ms.
  * chi_ms brackets each chi launch (for mode 3 with its redo launch);
  * chi_kernel is the mode (0, 1, 3 or 4, as in tissue_set_chi_mode) of the chi
@@ -292,6 +302,7 @@ int tissue_batch_step_timed(tissue_batch_t *b, double dt, int32_t n_steps, tissu
 int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workgroups_per_cu);
 int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode);
 int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph);
+int tissue_batch_set_regroup(tissue_batch_t *b, int32_t mode);
 int tissue_batch_sync(tissue_batch_t *b);
 int tissue_batch_destroy(tissue_batch_t *b);
 

@@ -955,7 +955,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
             }
         }
 
-        double t = 0.0;
+        double t = 0.0, last_a0 = 0.0;
         uint32_t j = 0, ev = 0;
         bool capped = false;
         if (active && !retry) {
@@ -1006,6 +1006,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     p2 = dpp_f64<kDppQuadSwap>(hs);
                     a0 = hs + p2;
                 }
+                last_a0 = a0;
                 if (a0 == 0.0) break;
                 if (ev >= c.cap) {
                     capped = true;
@@ -1134,6 +1135,8 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 c.T->tr_chi_ev[at] = tag ? c.T->tr_chi_ev[at] + ev : ev;  // 2nd half adds
                 c.T->tr_chi_t[at] = (unsigned long long)__double_as_longlong(t);
             }
+            // the cell's total propensity now: the key of the next regroup
+            if (sub == 0) c.T->load[cell] = (float)last_a0;
         }
         const bool counted = active && !retry && sub == 0;
         item_stats(c, counted ? ev : 0u, counted ? j : 0u, false, capped && counted, 0);

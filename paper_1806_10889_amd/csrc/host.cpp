@@ -225,7 +225,7 @@ struct Plan {
     // byte offsets inside dev_buf
     size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
            off_cells = 0, off_edges = 0, off_models = 0, off_chi = 0, off_s = 0, off_ctl = 0,
-           off_trace = 0, off_lq = 0,
+           off_trace = 0, off_lq = 0, off_load = 0, off_ctmp = 0,
            off_retry = 0, bytes = 0;
     size_t n_chi_items = 0, n_s_items = 0;
 };
@@ -422,7 +422,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         const uint32_t wcpi = (uint32_t)(kWave / std::max(32, g.P));  // wide rows: fewest cells per item
         uint32_t most = std::max((g.count + lcpi - 1) / lcpi, (g.count + wcpi - 1) / wcpi);
         if (g.P <= 64) most = std::max(most, g.count);
-        p.n_chi_items += most;
+        p.n_chi_items += most + 1;  // + the class's regroup segment
     }
 
     // edges, face groups, S passes
@@ -508,6 +508,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     p.off_s = take(p.n_s_items * sizeof(SItem));
     p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue words u32[8]
     p.off_lq = take(kLaunchQueueBytes);  // per-launch queue words of the chi launches
+    p.off_load = take((size_t)p.ncell * 4);  // per-cell load: the regroup pass's key
+    p.off_ctmp = take((size_t)p.ncell * 4);  // the regroup pass's scratch
     p.off_retry = take((size_t)p.ncell * sizeof(ChiItem));  // lane16 cells to redo
     p.off_trace = take((size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12));
     p.bytes = o;
@@ -529,6 +531,8 @@ struct ChiLaunch {
     const ChiItem *items;
     uint32_t n_items;
     uint32_t retry_off;      // compact layout: this launch's part of the redo list
+    const ChiItem *segs;     // regroup segments (a class's cells of one member), or none
+    uint32_t n_segs;
 };
 
 // chi mode request: lane, row, automatic, compact (lane16), or wide rows.
@@ -546,7 +550,7 @@ enum { kModeLane = 0, kModeRow = 1, kModeAuto = 2, kModeLane16 = 3, kModeRowWide
 // Work items and launches of the chi operator over a set of tissues: one
 // launch per (leaf class, kernel instantiation).  Items are written to
 // items_out in launch order; ChiLaunch.items holds offsets until rebased.
-void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd,
+void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regroup, int n_simd,
               std::vector<ChiItem> &items_out, std::vector<ChiLaunch> &launches)
 {
     struct Key {
@@ -628,7 +632,26 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int n_simd
         L.n_items = (uint32_t)(items_out.size() - off);
         L.retry_off = (uint32_t)retry_cells;
         if (mode == kChiLane16) retry_cells += cells;
+        L.segs = nullptr;
+        L.n_segs = 0;
         launches.push_back(L);
+    }
+    // regroup segments of the compact launches (after every launch's items):
+    // on request, or automatically when a launch holds at least two rounds
+    // of full wavefronts (2 resident per SIMD), where grouping cells of
+    // similar load shortens each wavefront's wait for its busiest cell
+    size_t li = 0;
+    for (auto &kv : groups) {
+        ChiLaunch &L = launches[li++];
+        if (L.mode != kChiLane16 || regroup == 0) continue;
+        uint64_t cells = 0;
+        for (auto &m : kv.second.cells) cells += m.second->count;
+        const uint64_t lanes = cells * (uint64_t)compact_lanes(L.P);
+        if (regroup == 2 && lanes < 2ull * 2ull * kWave * (uint64_t)std::max(n_simd, 1)) continue;
+        L.segs = reinterpret_cast<const ChiItem *>(items_out.size());
+        for (auto &m : kv.second.cells)
+            items_out.push_back(ChiItem{m.first, m.second->first, m.second->count, (uint32_t)m.second->model});
+        L.n_segs = (uint32_t)kv.second.cells.size();
     }
 }
 
@@ -655,6 +678,7 @@ struct LaunchPlan {
     ChiItem *retry_items = nullptr;  // device region: compact-layout cells to redo (one per cell)
     uint32_t *lq = nullptr;     // device: 8 queue words per chi launch
     int chi_mode = kModeAuto;
+    int regroup = 2;            // regroup pass before compact launches: 0 off, 1 on, 2 automatic
     std::vector<ChiLaunch> chi;
     std::vector<SLaunch> s;
     uint32_t *queue = nullptr;  // device: [0] next item, [1] workgroups done
@@ -713,6 +737,10 @@ struct LaunchPlan {
                               uint32_t kstep, uint32_t tag)
     {
         uint32_t *const q = lq + 8 * (size_t)(&L - chi.data());
+        if (L.n_segs) {  // regroup the class's cells by load first (same stream)
+            const hipError_t er = launch_regroup(st, tbl, L.segs, L.n_segs);
+            if (er != hipSuccess) return er;
+        }
         int log2p = 0;
         while ((1 << log2p) < L.P) ++log2p;
         ChiArgs a{};
@@ -866,7 +894,7 @@ struct LaunchPlan {
     {
         std::vector<ChiItem> items;
         std::vector<ChiLaunch> launches;
-        plan_chi(members, mode, cus * 4, items, launches);
+        plan_chi(members, mode, regroup, cus * 4, items, launches);
         if (items.size() > chi_items_cap) return fail(TISSUE_EINVAL, "chi item region too small");
         if (launches.size() > (size_t)kMaxChiLaunches) return fail(TISSUE_EINVAL, "too many chi launch groups");
         HIP_TRY(hipStreamSynchronize(stream));
@@ -879,7 +907,10 @@ struct LaunchPlan {
             HIP_TRY(hipMemcpyAsync(chi_items, h, nb, hipMemcpyHostToDevice, stream));
             HIP_TRY(hipStreamSynchronize(stream));
         }
-        for (ChiLaunch &L : launches) L.items = chi_items + reinterpret_cast<uintptr_t>(L.items);
+        for (ChiLaunch &L : launches) {
+            L.items = chi_items + reinterpret_cast<uintptr_t>(L.items);
+            if (L.n_segs) L.segs = chi_items + reinterpret_cast<uintptr_t>(L.segs);
+        }
         chi = std::move(launches);
         chi_mode = mode;
         clear_graphs();
@@ -1089,7 +1120,9 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     R.counts = reinterpret_cast<int32_t *>(base + p.off_counts);
     R.vox_off = reinterpret_cast<const int32_t *>(base + p.off_voxoff);
     R.wh = reinterpret_cast<const uint8_t *>(base + p.off_wh);
-    R.cell_list = reinterpret_cast<const int32_t *>(base + p.off_cells);
+    R.cell_list = reinterpret_cast<int32_t *>(base + p.off_cells);
+    R.load = reinterpret_cast<float *>(base + p.off_load);
+    R.cell_tmp = reinterpret_cast<int32_t *>(base + p.off_ctmp);
     R.edges = reinterpret_cast<const EdgeRec *>(base + p.off_edges);
     R.stats = reinterpret_cast<unsigned long long *>(base + p.off_ctl);
     R.flags = reinterpret_cast<uint32_t *>(base + p.off_ctl + 24);
@@ -1122,7 +1155,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     {
         std::unique_lock<std::mutex> lk;
         unsigned char *h = nullptr;
-        const size_t up = p.off_lq + kLaunchQueueBytes;
+        const size_t up = p.off_ctmp + (size_t)p.ncell * 4;
         HIP_TRY(staging_acquire(lk, up, &h));
         std::memcpy(h + p.off_tissue, &R, sizeof(DevTissue));
         std::memcpy(h + p.off_tbl, &d_rec, sizeof(DevTissue *));
@@ -1343,6 +1376,14 @@ int tissue_set_chi_mode(tissue_t *t, int32_t mode)
     return t->lp.set_chi_mode(mode);
 }
 
+int tissue_set_regroup(tissue_t *t, int32_t mode)
+{
+    if (!t || mode < 0 || mode > 2) return fail(TISSUE_EINVAL, "regroup mode must be 0, 1 or 2");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    t->lp.regroup = mode;
+    return t->lp.set_chi_mode(t->lp.chi_mode);
+}
+
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph)
 {
     if (!t || steps_per_graph < 0 || steps_per_graph > 100000) return fail(TISSUE_EINVAL, "bad graph chunk");
@@ -1530,6 +1571,14 @@ int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workg
     b->lp.wpc = workgroups_per_cu;
     b->lp.clear_graphs();
     return TISSUE_OK;
+}
+
+int tissue_batch_set_regroup(tissue_batch_t *b, int32_t mode)
+{
+    if (!b || mode < 0 || mode > 2) return fail(TISSUE_EINVAL, "regroup mode must be 0, 1 or 2");
+    HIP_TRY(hipStreamSynchronize(b->lp.stream));
+    b->lp.regroup = mode;
+    return b->lp.set_chi_mode(b->lp.chi_mode);
 }
 
 int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph)

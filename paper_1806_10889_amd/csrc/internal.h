@@ -57,7 +57,8 @@ struct DevTissue {
     int32_t *counts;              // [n_voxels][n_species], cell order, v = y*w + x
     const int32_t *vox_off;       // [n_cells] first voxel of each cell
     const uint8_t *wh;            // [n_cells][2] mesh (w, h)
-    const int32_t *cell_list;     // [n_cells] cells grouped by leaf-count class
+    int32_t *cell_list;           // [n_cells] cells grouped by leaf-count class (each
+                                  // class's order may be regrouped between steps)
     const EdgeRec *edges;         // [n_edges], ranked by (colour, i)
     unsigned long long *stats;    // [3] chi events, S events, draws
     uint32_t *flags;              // [2] overflow, capped
@@ -66,6 +67,8 @@ struct DevTissue {
     uint32_t *tr_s_ev;            // [trace_steps][n_edges] or null
     unsigned long long *tr_s_t;
     const DevModel *models;       // [n_models] chi networks of the cells; [0] equals `model`
+    float *load;                  // [n_cells] total propensity after the last compact chi pass
+    int32_t *cell_tmp;            // [n_cells] scratch of the regroup pass
     uint64_t seed;
     uint32_t n_cells, n_edges;
     uint32_t sim_id;
@@ -84,10 +87,10 @@ struct ChiItem {
     uint32_t model;
 };
 
-// chi kernel variants: one lane per cell (any P); one 16-lane row per cell
-// (P <= 16, four cells per wavefront); one lane per cell with the compact
-// 16-leaf / uint16 LDS layout (P <= 16) and a full-width redo of cells whose
-// counts outgrow 16 bits
+// chi kernel variants: one lane per cell (any P); one row of 16, 32 or 64
+// lanes per cell; the compact 16-leaf / uint16 LDS layout with 1, 2 or 4
+// lanes per cell (P <= 64) and a full-width redo of cells whose counts
+// outgrow 16 bits
 enum ChiMode { kChiLane = 0, kChiRow = 1, kChiLane16 = 2 };
 
 // device control words of a launch plan (uint32 each): the persistent queue

@@ -396,6 +396,74 @@ __global__ void advance_kernel(DevTissue *const *tbl, uint32_t n_tissues, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Regroup: reorder the cells of one leaf-count class of one tissue by their
+// total propensity after the last compact chi pass, largest first, in
+// buckets of 1/16 of a binary order of magnitude below the class's largest,
+// so that the cells of a work item (one wavefront) carry similar numbers of
+// events and the heaviest items start first.  A cell's result depends only
+// on its own counts and counters, never on its item or position.  One
+// workgroup per segment (a class's cells of one tissue).
+// ---------------------------------------------------------------------------
+constexpr int kRegroupThreads = 256;
+constexpr int kRegroupBuckets = 256;
+
+__global__ __launch_bounds__(kRegroupThreads) void regroup_kernel(const DevTissue *const *tbl,
+                                                                  const ChiItem *segs,
+                                                                  uint32_t n_segs)
+{
+    __shared__ uint32_t count[kRegroupBuckets];
+    __shared__ uint32_t next[kRegroupBuckets];
+    __shared__ uint32_t top_bits;
+    if (blockIdx.x >= n_segs) return;
+    const ChiItem seg = segs[blockIdx.x];
+    const DevTissue *T = tbl[seg.tissue];
+    int32_t *cl = T->cell_list + seg.first;
+    int32_t *tmp = T->cell_tmp + seg.first;
+    const float *load = T->load;
+    const uint32_t n = seg.count;
+    const int tid = threadIdx.x;
+    for (int b = tid; b < kRegroupBuckets; b += kRegroupThreads) count[b] = 0u;
+    if (tid == 0) top_bits = 0u;
+    __syncthreads();
+    // the largest load (non-negative floats order as their bit patterns)
+    uint32_t mb = 0u;
+    for (uint32_t i = tid; i < n; i += kRegroupThreads) mb = max(mb, __float_as_uint(load[cl[i]]));
+    atomicMax(&top_bits, mb);
+    __syncthreads();
+    const float top = __uint_as_float(top_bits);
+    auto bucket = [&](float x) -> int {  // 0 = heaviest
+        if (!(x > 0.0f) || !(top > 0.0f)) return kRegroupBuckets - 1;
+        const float d = 16.0f * __log2f(top / x);
+        return d < (float)(kRegroupBuckets - 1) ? (int)d : kRegroupBuckets - 1;
+    };
+    for (uint32_t i = tid; i < n; i += kRegroupThreads) atomicAdd(&count[bucket(load[cl[i]])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0u;
+        for (int b = 0; b < kRegroupBuckets; ++b) {
+            next[b] = acc;
+            acc += count[b];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kRegroupThreads) {
+        const int32_t c = cl[i];
+        tmp[atomicAdd(&next[bucket(load[c])], 1u)] = c;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kRegroupThreads) cl[i] = tmp[i];
+}
+
+hipError_t launch_regroup(hipStream_t stream, const DevTissue *const *tbl, const ChiItem *segs,
+                          uint32_t n_segs)
+{
+    if (n_segs == 0) return hipSuccess;
+    hipLaunchKernelGGL(regroup_kernel, dim3(n_segs), dim3(kRegroupThreads), 0, stream, tbl, segs,
+                       n_segs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 size_t chi_lds_bytes(int mode, int P, int S, int cells_per_item)

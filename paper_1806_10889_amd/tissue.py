@@ -83,7 +83,7 @@ EXPORTS = [
     "tissue_set_launch", "tissue_set_chi_mode", "tissue_set_graph_chunk", "tissue_step_timed",
     "tissue_stats_enqueue", "tissue_stats_decode",
     "tissue_destroy", "tissue_batch_set_chi_mode", "tissue_network_check",
-    "tissue_batch_set_graph_chunk",
+    "tissue_batch_set_graph_chunk", "tissue_set_regroup", "tissue_batch_set_regroup",
     "tissue_batch_required_bytes", "tissue_batch_create", "tissue_batch_step",
     "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
     "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
@@ -110,6 +110,8 @@ def _load():
         "tissue_write_counts": (C.c_int, [vp, C.POINTER(C.c_int32), sz]),
         "tissue_set_launch": (C.c_int, [vp, i32, i32]),
         "tissue_set_graph_chunk": (C.c_int, [vp, i32]),
+        "tissue_set_regroup": (C.c_int, [vp, i32]),
+        "tissue_batch_set_regroup": (C.c_int, [vp, i32]),
         "tissue_set_chi_mode": (C.c_int, [vp, i32]),
         "tissue_batch_set_chi_mode": (C.c_int, [vp, i32]),
         "tissue_batch_set_graph_chunk": (C.c_int, [vp, i32]),
@@ -325,6 +327,11 @@ class Tissue:
     def set_graph_chunk(self, steps: int):
         _check(lib.tissue_set_graph_chunk(self.handle, int(steps)), "tissue_set_graph_chunk")
 
+    def set_regroup(self, mode: int):
+        """0 off, 1 on, 2 automatic: the load-ordered regroup pass before
+        compact-layout chi launches (results are unchanged)."""
+        _check(lib.tissue_set_regroup(self.handle, int(mode)), "tissue_set_regroup")
+
     def sync(self):
         self.stats()
 
@@ -381,6 +388,9 @@ class Batch:
 
     def set_graph_chunk(self, steps: int):
         _check(lib.tissue_batch_set_graph_chunk(self.handle, int(steps)), "tissue_batch_set_graph_chunk")
+
+    def set_regroup(self, mode: int):
+        _check(lib.tissue_batch_set_regroup(self.handle, int(mode)), "tissue_batch_set_regroup")
 
     def restart(self, sim_ids=None, start_step: int = 0):
         for i, t in enumerate(self.tissues):

@@ -159,7 +159,8 @@ def test_batch_equals_plain_and_oracle(oracle_lib):
 @pytest.mark.parametrize("persistent", [False, True])
 def test_batch_compact_wide_cells_with_redo(oracle_lib, persistent):
     """A batch of uneven-mesh tissues in the compact layout (1, 2 and 4
-    lanes per cell): every member's cells of a class share one launch, and
+    lanes per cell), regrouped by load before every launch: every member's
+    cells of a class share one launch, and
     cells of several members and classes reach 2^16 and are redone from
     their launch's part of the redo list; graphs of 2 steps (classes as
     parallel branches with one workgroup per item, or persistent grids);
@@ -177,6 +178,7 @@ def test_batch_compact_wide_cells_with_redo(oracle_lib, persistent):
     ts = [T.Tissue(p) for p in probs]
     b = T.Batch(ts)
     b.set_chi_mode(3)
+    b.set_regroup(1)  # the load-ordered regroup before every compact launch
     b.set_launch(persistent)
     b.set_graph_chunk(2)
     b.step(0.05, 4)
@@ -186,6 +188,33 @@ def test_batch_compact_wide_cells_with_redo(oracle_lib, persistent):
         assert np.array_equal(t.read_counts(), o.counts), p["name"]
         st = t.stats()
         assert (st["chi_events"], st["s_events"], st["draws"]) == (o.chi_events, o.s_events, o.draws)
+
+
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_regroup_by_load_keeps_bits(oracle_lib, scheme, persistent):
+    """The regroup pass before every compact launch (forced on) reorders
+    each class's cells by load between chi passes; bits, per-cell traces
+    and totals stay the oracle's, over graphs of 3 steps and an eager tail,
+    with cells redone at full width."""
+    p = W.random_problem(140, lattice=1, nx=11, ny=9, model="nd5", uneven=True, dt=0.05, n_steps=7)
+    p["scheme"] = scheme
+    off = np.concatenate([[0], np.cumsum(p["mesh_w"].astype(np.int64) * p["mesh_h"])])
+    for c in (3, 40, 77):
+        p["init_counts"][off[c], 0] = 65535
+    o = _oracle(oracle_lib, p, 7)
+    from paper_1806_10889_amd import tissue as T
+    t = T.Tissue(p, trace_steps=7)
+    t.set_chi_mode(3)
+    t.set_regroup(1)
+    t.set_launch(persistent)
+    t.set_graph_chunk(3)
+    t.step(p["dt"], 7)
+    g = dict(counts=t.read_counts(), stats=t.stats(), trace=t.trace(0, 7))
+    with pytest.raises(T.TissueError):
+        t.set_regroup(3)
+    t.close()
+    assert_same(g, o)
 
 
 @pytest.mark.parametrize("mode", [2, 3, 0])
