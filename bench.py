@@ -113,6 +113,7 @@ def run_single(args, torch, T, p, leg, sims, warmup):
     untimed ones; then the eager roofline pass."""
     stream = torch.cuda.current_stream()
     t = T.Tissue(p, device="cuda:0", stream=stream)
+    t.set_regroup(args.regroup)
     dt, n = p["dt"], p["n_steps"]
     if args.launch:
         mode, persistent, wpc, chunk = (int(v) for v in args.launch.split(","))
@@ -273,7 +274,11 @@ def run_serving(args, torch):
     reqs = serve.requests_from_workload(args.serve_requests + args.serve_warmup,
                                         rate_hz=args.serve_rate)
     log(f"serving: {len(reqs)} requests generated")
-    be = serve.GpuBackend(lanes=args.serve_lanes)
+    # compile the requests' network before the clock starts (the runtime
+    # compiles each network structure once per process, on first use)
+    from paper_1806_10889_amd import tissue as T
+    T.Tissue(reqs[0].problem, device="cuda:0").close()
+    be = serve.GpuBackend(lanes=args.serve_lanes, regroup=args.regroup)
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(args.serve_hbm_gib * (1 << 30), 0.5 * free))
     srv = serve.Server(be, max_bytes=budget, max_active=args.serve_slots, quantum=args.serve_quantum)
@@ -678,7 +683,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--batch-reps", type=int, default=1)
     ap.add_argument("--regroup", type=int, default=2,
-                    help="batched leg: regroup cells by load before compact launches (0 off, 1 on, 2 auto)")
+                    help="regroup cells by load before compact launches (0 off, 1 on, 2 auto)")
     ap.add_argument("--cpu-steps", type=int, default=1200)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="fixed launch shape instead of the autotuner")

@@ -262,8 +262,8 @@ int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
  * leaf-count class (of each tissue) are reordered by their total propensity
  * after the previous compact pass, largest first, so that the cells sharing
  * a wavefront carry similar numbers of events.  mode 0 = off, 1 = on, 2 =
- * automatic (the default: on when a launch holds at least two rounds of
- * resident wavefronts).  Results are bit-identical either way: a cell's
+ * automatic (the default: on for every compact launch that spans at least
+ * two wavefronts).  Results are bit-identical either way: a cell's
  * result depends only on its counts and its counters.  Other values:
  * TISSUE_EINVAL.  Synchronises the tissue's stream. */
 int tissue_set_regroup(tissue_t *t, int32_t mode);

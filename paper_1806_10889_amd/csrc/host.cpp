@@ -637,9 +637,10 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
         launches.push_back(L);
     }
     // regroup segments of the compact launches (after every launch's items):
-    // on request, or automatically when a launch holds at least two rounds
-    // of full wavefronts (2 resident per SIMD), where grouping cells of
-    // similar load shortens each wavefront's wait for its busiest cell
+    // on request, or automatically when a launch spans at least two
+    // wavefronts: grouping cells of similar load shortens each wavefront's
+    // wait for its busiest cell and, with the heaviest items first, frees
+    // SIMDs early for the other classes' branches
     size_t li = 0;
     for (auto &kv : groups) {
         ChiLaunch &L = launches[li++];
@@ -647,7 +648,7 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
         uint64_t cells = 0;
         for (auto &m : kv.second.cells) cells += m.second->count;
         const uint64_t lanes = cells * (uint64_t)compact_lanes(L.P);
-        if (regroup == 2 && lanes < 2ull * 2ull * kWave * (uint64_t)std::max(n_simd, 1)) continue;
+        if (regroup == 2 && lanes < 2ull * kWave) continue;
         L.segs = reinterpret_cast<const ChiItem *>(items_out.size());
         for (auto &m : kv.second.cells)
             items_out.push_back(ChiItem{m.first, m.second->first, m.second->count, (uint32_t)m.second->model});

@@ -267,7 +267,7 @@ class GpuBackend:
     hide.  Use a queue count of at least the lanes plus two."""
 
     def __init__(self, device="cuda:0", lanes: int = 4, graph_chunk: int = 0,
-                 persistent: bool = False, max_slots: int = 8192):
+                 persistent: bool = False, max_slots: int = 8192, regroup: int = 2):
         import os
         import warnings
 
@@ -289,6 +289,7 @@ class GpuBackend:
         # compute units as their workgroups retire (a persistent grid holds
         # every CU until its slowest item is done)
         self.persistent = bool(persistent)
+        self.regroup = int(regroup)  # the load-ordered regroup before compact launches
         self._batch = [None] * self.lanes
         self._key = [None] * self.lanes
         self._done = [None] * self.lanes
@@ -324,6 +325,8 @@ class GpuBackend:
             self._batch[lane] = self.T.Batch(handles, device=self.device, stream=self.streams[lane])
             self._batch[lane].set_graph_chunk(self.graph_chunk)
             self._batch[lane].set_launch(self.persistent, 0)
+            if self.regroup != 2:
+                self._batch[lane].set_regroup(self.regroup)
             self._key[lane] = key
         self._batch[lane].step(dt, n)
         for h in finishing:
