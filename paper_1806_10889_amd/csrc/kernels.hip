@@ -404,7 +404,7 @@ __global__ void advance_kernel(DevTissue *const *tbl, uint32_t n_tissues, uint32
 // on its own counts and counters, never on its item or position.  One
 // workgroup per segment (a class's cells of one tissue).
 // ---------------------------------------------------------------------------
-constexpr int kRegroupThreads = 256;
+constexpr int kRegroupThreads = 1024;  // 16 wavefronts: four passes over a class of up to 64Ki cells
 constexpr int kRegroupBuckets = 256;
 
 __global__ __launch_bounds__(kRegroupThreads) void regroup_kernel(const DevTissue *const *tbl,
