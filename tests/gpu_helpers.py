@@ -6,12 +6,14 @@ from paper_1806_10889_amd import workloads as W
 
 
 def gpu_run(problem, n_steps, trace=False, persistent=None, wpc=0, graph_chunk=None, chunks=None,
-            allow_flags=False, chi_mode=None, jit=True):
+            allow_flags=False, chi_mode=None, jit=True, regroup=None):
     from paper_1806_10889_amd import tissue as T
     t = T.Tissue(problem, trace_steps=n_steps if trace else 0, jit=jit)
     assert t.stats()["jit"] == int(jit), "network kernels not compiled"
     if chi_mode is not None:
         t.set_chi_mode(chi_mode)
+    if regroup is not None:
+        t.set_regroup(regroup)
     if persistent is not None:
         t.set_launch(persistent, wpc)
     if graph_chunk is not None:

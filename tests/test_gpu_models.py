@@ -49,6 +49,17 @@ def test_four_networks_uneven_meshes(oracle_lib, mode, jit):
     assert_same(gpu_run(p, 5, trace=True, chi_mode=mode, jit=jit), o)
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_four_networks_regrouped_by_load(oracle_lib, persistent):
+    """The compact layout with the regroup pass forced on: each (class,
+    network) launch reorders its own cells by load between steps; same
+    bits."""
+    p = _nd5_mixed(63, n_steps=6)
+    o = oracle_lib.run(p, p["dt"], 6, trace=True)
+    assert_same(gpu_run(p, 6, trace=True, chi_mode=3, regroup=1, persistent=persistent,
+                        graph_chunk=2), o)
+
+
 @pytest.mark.parametrize("scheme", ["lie", "strang"])
 def test_networks_in_forked_graphs_and_redo(oracle_lib, scheme):
     """One workgroup per item and captured graphs (the (class, network)
