@@ -225,7 +225,7 @@ struct Plan {
     // byte offsets inside dev_buf
     size_t off_tissue = 0, off_tbl = 0, off_counts = 0, off_init = 0, off_voxoff = 0, off_wh = 0,
            off_cells = 0, off_edges = 0, off_models = 0, off_chi = 0, off_s = 0, off_ctl = 0,
-           off_trace = 0, off_lq = 0, off_load = 0, off_ctmp = 0,
+           off_trace = 0, off_lq = 0, off_load = 0,
            off_retry = 0, bytes = 0;
     size_t n_chi_items = 0, n_s_items = 0;
 };
@@ -422,7 +422,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         const uint32_t wcpi = (uint32_t)(kWave / std::max(32, g.P));  // wide rows: fewest cells per item
         uint32_t most = std::max((g.count + lcpi - 1) / lcpi, (g.count + wcpi - 1) / wcpi);
         if (g.P <= 64) most = std::max(most, g.count);
-        p.n_chi_items += most + 1;  // + the class's regroup segment
+        p.n_chi_items += most + (g.count + kRegroupChunk - 1) / kRegroupChunk;  // + regroup segments
     }
 
     // edges, face groups, S passes
@@ -509,7 +509,6 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue words u32[8]
     p.off_lq = take(kLaunchQueueBytes);  // per-launch queue words of the chi launches
     p.off_load = take((size_t)p.ncell * 4);  // per-cell load: the regroup pass's key
-    p.off_ctmp = take((size_t)p.ncell * 4);  // the regroup pass's scratch
     p.off_retry = take((size_t)p.ncell * sizeof(ChiItem));  // lane16 cells to redo
     p.off_trace = take((size_t)p.trace_steps * ((size_t)p.ncell * 12 + (size_t)p.nedge * 12));
     p.bytes = o;
@@ -649,10 +648,14 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
         for (auto &m : kv.second.cells) cells += m.second->count;
         const uint64_t lanes = cells * (uint64_t)compact_lanes(L.P);
         if (regroup == 2 && lanes < 2ull * kWave) continue;
-        L.segs = reinterpret_cast<const ChiItem *>(items_out.size());
+        const size_t at = items_out.size();
+        L.segs = reinterpret_cast<const ChiItem *>(at);
         for (auto &m : kv.second.cells)
-            items_out.push_back(ChiItem{m.first, m.second->first, m.second->count, (uint32_t)m.second->model});
-        L.n_segs = (uint32_t)kv.second.cells.size();
+            for (uint32_t o = 0; o < m.second->count; o += kRegroupChunk)
+                items_out.push_back(ChiItem{m.first, m.second->first + o,
+                                            std::min(kRegroupChunk, m.second->count - o),
+                                            (uint32_t)m.second->model});
+        L.n_segs = (uint32_t)(items_out.size() - at);
     }
 }
 
@@ -1123,7 +1126,6 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     R.wh = reinterpret_cast<const uint8_t *>(base + p.off_wh);
     R.cell_list = reinterpret_cast<int32_t *>(base + p.off_cells);
     R.load = reinterpret_cast<float *>(base + p.off_load);
-    R.cell_tmp = reinterpret_cast<int32_t *>(base + p.off_ctmp);
     R.edges = reinterpret_cast<const EdgeRec *>(base + p.off_edges);
     R.stats = reinterpret_cast<unsigned long long *>(base + p.off_ctl);
     R.flags = reinterpret_cast<uint32_t *>(base + p.off_ctl + 24);
@@ -1156,7 +1158,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     {
         std::unique_lock<std::mutex> lk;
         unsigned char *h = nullptr;
-        const size_t up = p.off_ctmp + (size_t)p.ncell * 4;
+        const size_t up = p.off_load + (size_t)p.ncell * 4;
         HIP_TRY(staging_acquire(lk, up, &h));
         std::memcpy(h + p.off_tissue, &R, sizeof(DevTissue));
         std::memcpy(h + p.off_tbl, &d_rec, sizeof(DevTissue *));

@@ -68,7 +68,6 @@ struct DevTissue {
     unsigned long long *tr_s_t;
     const DevModel *models;       // [n_models] chi networks of the cells; [0] equals `model`
     float *load;                  // [n_cells] total propensity after the last compact chi pass
-    int32_t *cell_tmp;            // [n_cells] scratch of the regroup pass
     uint64_t seed;
     uint32_t n_cells, n_edges;
     uint32_t sim_id;

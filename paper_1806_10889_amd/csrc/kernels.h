@@ -53,8 +53,14 @@ hipError_t launch_s(uint32_t grid, hipStream_t stream, const DevTissue *const *t
                     double dt, uint32_t kstep);
 hipError_t launch_advance(hipStream_t stream, DevTissue *const *tbl, uint32_t n_tissues,
                           uint32_t n);
-// Reorder each segment's cells (a class's cells of one tissue: cell_list
-// [first, first + count) of tissue `tissue`) by their load, largest first.
+// Cells per regroup segment: a class's cells of one tissue are regrouped in
+// pieces of at most this many (a multiple of every work-item size, so pieces
+// hold whole items), one workgroup each.
+constexpr uint32_t kRegroupChunk = 16384;
+
+// Reorder each segment's cells (consecutive cells of a class of one tissue:
+// cell_list [first, first + count) of tissue `tissue`, count <=
+// kRegroupChunk) by their load, largest first.
 hipError_t launch_regroup(hipStream_t stream, const DevTissue *const *tbl, const ChiItem *segs,
                           uint32_t n_segs);
 

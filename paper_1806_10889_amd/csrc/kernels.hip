@@ -402,10 +402,14 @@ __global__ void advance_kernel(DevTissue *const *tbl, uint32_t n_tissues, uint32
 // so that the cells of a work item (one wavefront) carry similar numbers of
 // events and the heaviest items start first.  A cell's result depends only
 // on its own counts and counters, never on its item or position.  One
-// workgroup per segment (a class's cells of one tissue).
+// workgroup per segment (up to kRegroupChunk consecutive cells of a class
+// of one tissue, whole work items): every thread holds its cells and their
+// loads in registers, so the list is read once and rewritten in place.
 // ---------------------------------------------------------------------------
-constexpr int kRegroupThreads = 1024;  // 16 wavefronts: four passes over a class of up to 64Ki cells
+constexpr int kRegroupThreads = 1024;
+constexpr int kRegroupPerThread = (int)(kRegroupChunk / kRegroupThreads);
 constexpr int kRegroupBuckets = 256;
+static_assert(kRegroupChunk % kRegroupThreads == 0, "regroup chunk");
 
 __global__ __launch_bounds__(kRegroupThreads) void regroup_kernel(const DevTissue *const *tbl,
                                                                   const ChiItem *segs,
@@ -418,25 +422,38 @@ __global__ __launch_bounds__(kRegroupThreads) void regroup_kernel(const DevTissu
     const ChiItem seg = segs[blockIdx.x];
     const DevTissue *T = tbl[seg.tissue];
     int32_t *cl = T->cell_list + seg.first;
-    int32_t *tmp = T->cell_tmp + seg.first;
     const float *load = T->load;
-    const uint32_t n = seg.count;
+    const uint32_t n = min(seg.count, kRegroupChunk);
     const int tid = threadIdx.x;
     for (int b = tid; b < kRegroupBuckets; b += kRegroupThreads) count[b] = 0u;
     if (tid == 0) top_bits = 0u;
-    __syncthreads();
-    // the largest load (non-negative floats order as their bit patterns)
+    // this thread's cells and loads (non-negative floats order as their bits)
+    int32_t cell[kRegroupPerThread];
+    float key[kRegroupPerThread];
     uint32_t mb = 0u;
-    for (uint32_t i = tid; i < n; i += kRegroupThreads) mb = max(mb, __float_as_uint(load[cl[i]]));
+#pragma unroll
+    for (int r = 0; r < kRegroupPerThread; ++r) {
+        const uint32_t i = (uint32_t)(r * kRegroupThreads + tid);
+        cell[r] = i < n ? cl[i] : 0;
+        key[r] = i < n ? load[cell[r]] : 0.0f;
+        mb = max(mb, __float_as_uint(key[r]));
+    }
+    __syncthreads();  // counters cleared; every cell read before any is rewritten
     atomicMax(&top_bits, mb);
     __syncthreads();
     const float top = __uint_as_float(top_bits);
-    auto bucket = [&](float x) -> int {  // 0 = heaviest
-        if (!(x > 0.0f) || !(top > 0.0f)) return kRegroupBuckets - 1;
-        const float d = 16.0f * __log2f(top / x);
-        return d < (float)(kRegroupBuckets - 1) ? (int)d : kRegroupBuckets - 1;
-    };
-    for (uint32_t i = tid; i < n; i += kRegroupThreads) atomicAdd(&count[bucket(load[cl[i]])], 1u);
+    int bucket[kRegroupPerThread];  // 0 = heaviest
+#pragma unroll
+    for (int r = 0; r < kRegroupPerThread; ++r) {
+        const float x = key[r];
+        int b = kRegroupBuckets - 1;
+        if (x > 0.0f && top > 0.0f) {
+            const float d = 16.0f * __log2f(top / x);
+            b = d < (float)(kRegroupBuckets - 1) ? (int)d : kRegroupBuckets - 1;
+        }
+        bucket[r] = b;
+        if ((uint32_t)(r * kRegroupThreads + tid) < n) atomicAdd(&count[b], 1u);
+    }
     __syncthreads();
     if (tid == 0) {
         uint32_t acc = 0u;
@@ -446,12 +463,9 @@ __global__ __launch_bounds__(kRegroupThreads) void regroup_kernel(const DevTissu
         }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += kRegroupThreads) {
-        const int32_t c = cl[i];
-        tmp[atomicAdd(&next[bucket(load[c])], 1u)] = c;
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += kRegroupThreads) cl[i] = tmp[i];
+#pragma unroll
+    for (int r = 0; r < kRegroupPerThread; ++r)
+        if ((uint32_t)(r * kRegroupThreads + tid) < n) cl[atomicAdd(&next[bucket[r]], 1u)] = cell[r];
 }
 
 hipError_t launch_regroup(hipStream_t stream, const DevTissue *const *tbl, const ChiItem *segs,
