@@ -588,6 +588,7 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
     }
     items_out.clear();
     launches.clear();
+    std::vector<ChiItem> segs_out;  // regroup segments, appended after the items
     uint64_t retry_cells = 0;  // cells of the compact launches so far
     for (auto &kv : groups) {
         const Key &k = kv.first;
@@ -625,38 +626,69 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
         }
         L.lds = chi_lds_bytes(mode, k.P, G.max_s, L.cells_per_item);
         L.retry_lds = chi_lds_bytes(kChiLane, k.P, G.max_s, 1);
-        const size_t off = items_out.size();
-        for (auto &m : G.cells) cut_items(m.first, *m.second, L.cells_per_item, items_out);
-        L.items = reinterpret_cast<const ChiItem *>(off);
-        L.n_items = (uint32_t)(items_out.size() - off);
         L.retry_off = (uint32_t)retry_cells;
         if (mode == kChiLane16) retry_cells += cells;
         L.segs = nullptr;
         L.n_segs = 0;
+        // regroup of a compact class: on request, or automatically when the
+        // launch spans at least two wavefronts (grouping cells of similar
+        // load shortens each wavefront's wait for its busiest cell and, with
+        // the heaviest items first, frees SIMDs early for other classes)
+        const bool rg = mode == kChiLane16 && regroup != 0 &&
+                        (regroup == 1 || cells * (uint64_t)compact_lanes(k.P) >= 2ull * kWave);
+        if (rg) {
+            L.segs = reinterpret_cast<const ChiItem *>(segs_out.size());
+            for (auto &m : G.cells)
+                for (uint32_t o = 0; o < m.second->count; o += kRegroupChunk)
+                    segs_out.push_back(ChiItem{m.first, m.second->first + o,
+                                               std::min(kRegroupChunk, m.second->count - o),
+                                               (uint32_t)m.second->model});
+            L.n_segs = (uint32_t)(segs_out.size() - reinterpret_cast<uintptr_t>(L.segs));
+        }
+        // the row head: in a single tissue the 64-leaf cells' event chains
+        // are the longest of a step, and the compact layout advances a chain
+        // more slowly than a row of 64 lanes; once regrouped (heaviest
+        // first), the first min(SIMDs, cells / 4) cells of the class run in
+        // rows, one wavefront each, the rest compact
+        uint32_t head = 0;
+        if (rg && mode_req == kModeAuto && k.P == 64 && G.cells.size() == 1)
+            head = (uint32_t)std::min<uint64_t>((uint64_t)std::max(n_simd, 1), cells / 4);
+        const size_t off = items_out.size();
+        for (auto &m : G.cells) {
+            ChiGroupHost g = *m.second;
+            g.first += head;
+            g.count -= head;
+            cut_items(m.first, g, L.cells_per_item, items_out);
+        }
+        L.items = reinterpret_cast<const ChiItem *>(off);
+        L.n_items = (uint32_t)(items_out.size() - off);
+        if (head > 0) {
+            // the head first, carrying the class's regroup (in launch order
+            // the regroup precedes both parts; a step graph regroups every
+            // class before it forks)
+            ChiLaunch R = L;
+            R.mode = kChiRow;
+            R.rw = 64;
+            R.cells_per_item = 1;
+            R.lds = chi_lds_bytes(kChiRow, k.P, G.max_s, 1);
+            const size_t roff = items_out.size();
+            ChiGroupHost g = *G.cells[0].second;
+            g.count = head;
+            cut_items(G.cells[0].first, g, 1, items_out);
+            R.items = reinterpret_cast<const ChiItem *>(roff);
+            R.n_items = (uint32_t)(items_out.size() - roff);
+            launches.push_back(R);
+            L.segs = nullptr;
+            L.n_segs = 0;
+        }
         launches.push_back(L);
     }
-    // regroup segments of the compact launches (after every launch's items):
-    // on request, or automatically when a launch spans at least two
-    // wavefronts: grouping cells of similar load shortens each wavefront's
-    // wait for its busiest cell and, with the heaviest items first, frees
-    // SIMDs early for the other classes' branches
-    size_t li = 0;
-    for (auto &kv : groups) {
-        ChiLaunch &L = launches[li++];
-        if (L.mode != kChiLane16 || regroup == 0) continue;
-        uint64_t cells = 0;
-        for (auto &m : kv.second.cells) cells += m.second->count;
-        const uint64_t lanes = cells * (uint64_t)compact_lanes(L.P);
-        if (regroup == 2 && lanes < 2ull * kWave) continue;
-        const size_t at = items_out.size();
-        L.segs = reinterpret_cast<const ChiItem *>(at);
-        for (auto &m : kv.second.cells)
-            for (uint32_t o = 0; o < m.second->count; o += kRegroupChunk)
-                items_out.push_back(ChiItem{m.first, m.second->first + o,
-                                            std::min(kRegroupChunk, m.second->count - o),
-                                            (uint32_t)m.second->model});
-        L.n_segs = (uint32_t)(items_out.size() - at);
-    }
+    // every launch's regroup segments after all items, contiguous, so that
+    // a step graph can regroup every class in one launch before it forks
+    const size_t seg_base = items_out.size();
+    items_out.insert(items_out.end(), segs_out.begin(), segs_out.end());
+    for (ChiLaunch &L : launches)
+        if (L.n_segs) L.segs = reinterpret_cast<const ChiItem *>(seg_base + reinterpret_cast<uintptr_t>(L.segs));
 }
 
 struct SLaunch {
@@ -738,10 +770,10 @@ struct LaunchPlan {
     // count from device memory and exits at once when it is zero).  Each
     // launch uses its own queue words and its own part of the redo list.
     hipError_t launch_chi_any(const ChiLaunch &L, uint32_t grid, hipStream_t st, double dt,
-                              uint32_t kstep, uint32_t tag)
+                              uint32_t kstep, uint32_t tag, bool regrouped = false)
     {
         uint32_t *const q = lq + 8 * (size_t)(&L - chi.data());
-        if (L.n_segs) {  // regroup the class's cells by load first (same stream)
+        if (L.n_segs && !regrouped) {  // regroup the class's cells by load first (same stream)
             const hipError_t er = launch_regroup(st, tbl, L.segs, L.n_segs);
             if (er != hipSuccess) return er;
         }
@@ -842,16 +874,25 @@ struct LaunchPlan {
         }
         auto chi_pass = [&](double dchi, uint32_t k, uint32_t tag) -> int {
             if (fork) {
+                // every class's regroup in one launch, then the branches
+                const ChiItem *segs = nullptr;
+                uint32_t n_segs = 0;
+                for (const ChiLaunch &L : chi)
+                    if (L.n_segs) {
+                        if (!segs) segs = L.segs;
+                        n_segs += L.n_segs;
+                    }
+                if (n_segs) HIP_TRY(launch_regroup(st, tbl, segs, n_segs));
                 HIP_TRY(hipEventRecord(fork_ev, st));
                 size_t b = 0;
                 for (const ChiLaunch &L : chi) {
                     if (L.n_items == 0) continue;
                     if (b == 0) {
-                        HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag));
+                        HIP_TRY(launch_chi_any(L, chi_grid(L), st, dchi, k, tag, true));
                     } else {
                         hipStream_t ss = side[b - 1];
                         HIP_TRY(hipStreamWaitEvent(ss, fork_ev, 0));
-                        HIP_TRY(launch_chi_any(L, chi_grid(L), ss, dchi, k, tag));
+                        HIP_TRY(launch_chi_any(L, chi_grid(L), ss, dchi, k, tag, true));
                         HIP_TRY(hipEventRecord(joins[b - 1], ss));
                     }
                     ++b;

@@ -217,6 +217,23 @@ def test_regroup_by_load_keeps_bits(oracle_lib, scheme, persistent):
     assert_same(g, o)
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_row_head_of_the_largest_cells(oracle_lib, persistent):
+    """Automatic layout on a single tissue of 4096 cells of 8x8 voxels: the
+    64-leaf class is compact and regrouped by load, its heaviest 1024 cells
+    running in rows of 64 lanes (a launch of their own, a parallel graph
+    branch); same bits as the oracle."""
+    rng = np.random.default_rng(150)
+    m = W.model_nd5()
+    x0 = rng.integers(0, 51, size=(64 * 64 * 64, 5)).astype(np.int32)
+    p = W.make_problem(m, lattice=1, nx=64, ny=64, mesh_w=8, mesh_h=8,
+                       rates=10.0 ** rng.uniform(-2, 1, m["n_reactions"]), trans_rate=0.8,
+                       diffusion=1.0, init_counts=x0, seed=150, dt=0.02, n_steps=3)
+    o = _oracle(oracle_lib, p, 3, threads=0)
+    g = gpu_run(p, 3, trace=True, persistent=persistent, graph_chunk=2, chi_mode=2)
+    assert_same(g, o)
+
+
 @pytest.mark.parametrize("mode", [2, 3, 0])
 def test_config4_sampled_tissues(oracle_lib, mode):
     from paper_1806_10889_amd import tissue as T
