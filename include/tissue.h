@@ -251,8 +251,10 @@ int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu
  * their step; 2 = automatic (the default): cells of at most 8 voxels take
  * mode 0; a class of cells of 9 to 64 voxels takes the compact layout when
  * it holds at least 16 lanes of it per SIMD of the device (cells x P / 16),
- * else rows.  Results are bit-identical for every choice.  Other values:
- * TISSUE_EINVAL. */
+ * else rows; in a single tissue whose 33-64-voxel class is compact and
+ * regrouped by load, that class's heaviest min(SIMDs, cells / 4) cells run
+ * in rows of 64 lanes.  Results are bit-identical for every choice.  Other
+ * values: TISSUE_EINVAL. */
 int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 
 /* Steps captured per HIP graph launch (0 disables graphs). */
