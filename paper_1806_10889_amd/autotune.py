@@ -36,12 +36,18 @@ def signature(problems) -> str:
     return h.hexdigest()
 
 
-def candidates(max_voxels: int):
+def candidates(max_voxels: int, cells: int = 0):
     out = []
     # every mode covers every leaf-count class (the compact layout with 1, 2
     # or 4 lanes per cell; rows of 16, 32 or 64 lanes); auto mixes them per
-    # class; listed so that the likelier winners come first
-    modes = [0, 1, 4, 3, 2] if max_voxels <= 16 else [2, 3, 1, 0, 4]
+    # class; listed so that the likelier winners come first.  With 64 Ki
+    # cells or more every SIMD holds 64 compact lanes of work: one row of
+    # lanes per cell (modes 1, 4) or the full-LDS lane layout (mode 0) only
+    # cost more issue slots per event there, and are not timed
+    if cells >= 65536:
+        modes = [2, 3]
+    else:
+        modes = [0, 1, 4, 3, 2] if max_voxels <= 16 else [2, 3, 1, 0, 4]
     for mode in modes:
         for persistent, wpc in [(1, 0), (0, 0), (1, 2), (1, 8)]:
             for chunk in (25, 100):
@@ -77,7 +83,10 @@ def _save_cache(c):
 def tune(problems, dt: float, steps: int = 50, reps: int = 2, device="cuda:0", target=None,
          use_cache: bool = True, log=None) -> dict:
     """Pick the fastest launch shape for `problems` (one tissue, or a batch
-    when several) and apply it to `target` (a Tissue or Batch) if given."""
+    when several) and apply it to `target` (a Tissue or Batch) if given.
+    A single tissue is timed on `target` itself (restarted before every
+    candidate and at the end), which spares a second copy of its state and
+    its streams; a batch is timed on clones."""
     from . import tissue as T
     sig = signature(problems)
     cache = _load_cache() if use_cache else {}
@@ -86,11 +95,13 @@ def tune(problems, dt: float, steps: int = 50, reps: int = 2, device="cuda:0", t
         if target is not None:
             apply(target, best)
         return dict(cache[sig], cached=True)
-    clones = [T.Tissue(p, device=device) for p in problems]
+    own = not (len(problems) == 1 and isinstance(target, T.Tissue))
+    clones = [T.Tissue(p, device=device) for p in problems] if own else [target]
     runner = clones[0] if len(clones) == 1 else T.Batch(clones, device=device)
     vmax = max(int(np.max(np.asarray(p["mesh_w"]) * np.asarray(p["mesh_h"]))) for p in problems)
+    ncells = sum(int(p["nx"]) * int(p["ny"]) for p in problems)
     results = []
-    for cfg in candidates(vmax):
+    for cfg in candidates(vmax, ncells):
         apply(runner, cfg)
         times = []
         for _ in range(reps + 1):  # the first run captures the graph
@@ -113,6 +124,9 @@ def tune(problems, dt: float, steps: int = 50, reps: int = 2, device="cuda:0", t
         _save_cache(cache)
     if target is not None:
         apply(target, best)
+    if not own:
+        target.restart(target.problem["sim_id"], int(target.problem.get("start_step", 0)))
+        return dict(entry, cached=False)
     if runner is not clones[0]:
         runner.close()
     for t in clones:

@@ -701,7 +701,7 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
 #pragma unroll
         for (int l = 1; l <= 3; ++l) thr[l - 1] = l <= deg - 1 ? (double)l : __builtin_inf();
 
-        double t = 0.0, last_a0 = 0.0;
+        double t = 0.0, a0 = 0.0;  // a0: the row's total, rebuilt every iteration
         uint32_t j = 0, ev = 0;
         bool run = has_cell, overflow = false, capped = false;
         // Every running row has drawn exactly once per iteration so far, so
@@ -732,7 +732,7 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             const double p2 = dpp_f64<kDppHalfMirror>(s2);
             const double s3 = s2 + p2;
             const double p3 = dpp_f64<kDppRowMirror>(s3);
-            double a0 = s3 + p3;
+            a0 = s3 + p3;
             double s4 = 0.0, p4 = 0.0, s5 = 0.0, p5 = 0.0;
             if (RW >= 32) {
                 s4 = a0;
@@ -744,7 +744,6 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                 p5 = xlane_f64(s5, 32);
                 a0 = s5 + p5;
             }
-            last_a0 = run ? a0 : last_a0;  // the running cell's total so far
             if (run) {
                 if (a0 == 0.0) {
                     run = false;
@@ -814,8 +813,10 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             for (int q = 0; q < SM; ++q)
                 if (q < S) c.counts[vbase + q] = (int32_t)xd[q];
         }
-        // the cell's total propensity now: the key of the next regroup
-        if (has_cell && lv == 0) c.T->load[cell] = (float)last_a0;
+        // the cell's total propensity now (the last iteration rebuilt every
+        // row's tree, and a row's leaves stay put once it stops): the key
+        // of the next regroup
+        if (has_cell && lv == 0) c.T->load[cell] = (float)a0;
         if (has_cell && lv == 0 && c.T->tr_chi_ev) {
             const uint32_t ts = uni(c.T->trace_steps), nc = uni(c.T->n_cells);
             const size_t slot = (size_t)(c.step % ts) * nc + cell;
