@@ -58,11 +58,11 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC = {   # leg -> counters of its dominant chi kernel
     # hex 64x64 tissue, 4096 cells x 4x4 voxels: 400 dispatches of 200-step runs
-    "plain": {"digest": "1a9bb9370ce55cfa1a94fed45e4502966eb376c1", "kernel": "tissue_chi_row",
-              "fetch_kib": 935.521, "write_kib": 1344.0},
+    "plain": {"digest": "13244f677eda5d64f36d6eee2fb91a64f5e1cd58", "kernel": "tissue_chi_row",
+              "fetch_kib": 935.524, "write_kib": 1376.0},
     # 512 tissues, 3.12M cells, 200 steps: 450 dispatches
-    "batched": {"digest": "1a9bb9370ce55cfa1a94fed45e4502966eb376c1", "kernel": "tissue_chi_lane16",
-                "fetch_kib": 652416.0, "write_kib": 1060080.0},
+    "batched": {"digest": "13244f677eda5d64f36d6eee2fb91a64f5e1cd58", "kernel": "tissue_chi_lane16",
+                "fetch_kib": 652451.0, "write_kib": 1060010.0},
 }
 
 
