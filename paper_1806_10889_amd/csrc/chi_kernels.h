@@ -251,8 +251,8 @@ __device__ __forceinline__ int voxel_select_cached(const NET &n, const double *p
         if (k >= RM - 1) before = under ? pre[k] : before;
         under_prev = under;
     }
-    if (__builtin_expect(need && below >= NC, 0)) return voxel_select(n, xd, degd, r, resid, a1);
     resid = r - before;
+    if (__builtin_expect(need && below >= NC, 0)) below = voxel_select(n, xd, degd, r, resid, a1);
     return below;
 }
 
@@ -287,26 +287,14 @@ __device__ __forceinline__ void load_channel_table(ChanEntry *tab, const DevMode
     __builtin_amdgcn_wave_barrier();
 }
 
-// Whether any of the first S counts (held as doubles) left [0, limit).
-template <int SM>
-__device__ __forceinline__ bool out_of_range(const double *xd, int S, double limit)
+// Net change of species q in a packed change (signed bytes, species 0..3
+// in lo, 4..7 in hi).  Counts are kept as integers beside their exact
+// doubles: a count left [0, 2^k) exactly when the OR of the counts, taken
+// unsigned, is 2^k or more (a negative count has the sign bit set).
+__device__ __forceinline__ int entry_delta(uint32_t lo, uint32_t hi, int q)
 {
-    double mx = xd[0], mn = xd[0];
-#pragma unroll
-    for (int q = 1; q < SM; ++q) {
-        if (q < S) {
-            mx = __builtin_fmax(mx, xd[q]);
-            mn = __builtin_fmin(mn, xd[q]);
-        }
-    }
-    return (mn < 0.0) | (mx >= limit);
-}
-
-// Net change of species q in a table entry.
-__device__ __forceinline__ double entry_delta(const ChanEntry &e, int q)
-{
-    const uint32_t w = q < 4 ? e.lo : e.hi;
-    return (double)(int)(int8_t)((w >> (8 * (q & 3))) & 0xFFu);
+    const uint32_t w = q < 4 ? lo : hi;
+    return (int)(int8_t)((w >> (8 * (q & 3))) & 0xFFu);
 }
 
 // The value unchanged, but opaque to the optimiser (an empty asm with a
@@ -520,20 +508,27 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                 // the voxel's counts, the channel, the change
                 const Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
                 int32_t *x = cnt + v * S * stride;
+                int32_t xi[SM];
 #pragma unroll
-                for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
+                for (int q = 0; q < SM; ++q) {
+                    xi[q] = x[q * stride];
+                    xd[q] = (double)xi[q];
+                }
                 const int deg = voxel_degree(go, v);
                 double resid, a1;
                 const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
                 const ChanEntry e = tab[sel];
+                uint32_t any_bits = 0u;  // OR of the counts: the range check
 #pragma unroll
                 for (int q = 0; q < SM; ++q) {
                     if (q < S) {
-                        xd[q] += entry_delta(e, q);
-                        x[q * stride] = (int32_t)xd[q];
+                        xi[q] += entry_delta(e.lo, e.hi, q);
+                        x[q * stride] = xi[q];
+                        xd[q] = (double)xi[q];
+                        any_bits |= (uint32_t)xi[q];
                     }
                 }
-                overflow |= out_of_range<SM>(xd, S, (double)kCountLimit);
+                overflow |= any_bits >= (uint32_t)kCountLimit;
                 int dst = v;
                 if (e.spec >= 0) {
                     dst = neighbour_at(go, v, jump_direction(resid, a1, deg));
@@ -603,6 +598,10 @@ __device__ __forceinline__ double dpp_f64(double v)
 constexpr int kDppPairSwap = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int kDppQuadSwap = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppPairLeft = 0xA0;   // quad_perm [0,0,2,2]
+constexpr int kDppPairRight = 0xF5;  // quad_perm [1,1,3,3]
+constexpr int kDppQuadLeft = 0x00;   // quad_perm [0,0,0,0]
+constexpr int kDppQuadRight = 0xAA;  // quad_perm [2,2,2,2]
 constexpr int kDppRowMirror = 0x140;
 
 // OR of a 32-bit value over the lane's 16-lane row (full wave required).
@@ -621,6 +620,14 @@ __device__ __forceinline__ double xlane_f64(double v, int mask)
 {
     const int lo = __double2loint(v), hi = __double2hiint(v);
     return __hiloint2double(__shfl_xor(hi, mask, kWave), __shfl_xor(lo, mask, kWave));
+}
+
+// One descent level from the children L (left) and R of the lane's ancestor.
+__device__ __forceinline__ void descent_children(double L, double R, int bit, double &r, bool &on)
+{
+    const bool left = (r < L) || (R == 0.0);
+    on = on && (left == (bit == 0));
+    r = left ? r : r - L;
 }
 
 // One descent level: children L (left) and R of the lane's ancestor, given
@@ -682,9 +689,14 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             vbase = (long long)(c.T->vox_off[cell] + lv) * S;
         }
         const bool vox = has_cell && lv < g.w * g.h;
+        // the voxel's counts, as integers and as exact doubles
+        int32_t xi[SM];
         double xd[SM];
 #pragma unroll
-        for (int q = 0; q < SM; ++q) xd[q] = (vox && q < S) ? (double)c.counts[vbase + q] : 0.0;
+        for (int q = 0; q < SM; ++q) {
+            xi[q] = (vox && q < S) ? c.counts[vbase + q] : 0;
+            xd[q] = (double)xi[q];
+        }
         const int deg = vox ? voxel_degree(g, lv) : 0;
         const double degd = (double)deg;
         // cached with the leaf: the channel prefixes and D_s x_s
@@ -694,9 +706,10 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         // the lane's present neighbours in jump order (-x, +x, -y, +y), and
         // the jump thresholds' multipliers l for l = 1..3 (+inf past deg - 1,
         // so that the comparison fails as the rule's range ends)
-        int nb[4];
+        // (packed: neighbour k in bits 8k .. 8k+7)
+        uint32_t nbp = 0u;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) nb[k] = vox ? neighbour_at(g, lv, k < deg ? k : 0) : lv;
+        for (int k = 0; k < 4; ++k) nbp |= (uint32_t)(vox ? neighbour_at(g, lv, k < deg ? k : 0) : lv) << (8 * k);
         double thr[3];
 #pragma unroll
         for (int l = 1; l <= 3; ++l) thr[l - 1] = l <= deg - 1 ? (double)l : __builtin_inf();
@@ -720,15 +733,20 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-            // this iteration's draw of the row (read early: its latency hides
-            // behind the tree rebuild)
+            // this iteration's draw of the row
             const double e1 = rng_e[(row << LOG_RW) | (int)slot];
             const double u2 = rng_u[(row << LOG_RW) | (int)slot];
+            __builtin_amdgcn_sched_barrier(0);
             // the sum tree of the row, rebuilt from the leaves (full wave)
-            const double p0 = dpp_f64<kDppPairSwap>(leaf);
-            const double s1 = leaf + p0;
-            const double p1 = dpp_f64<kDppQuadSwap>(s1);
-            const double s2 = s1 + p1;
+            // (the two lowest levels as left and right children directly:
+            // quad permutations give every lane both, so the descent needs
+            // no swap by the lane's side there)
+            const double l0 = dpp_f64<kDppPairLeft>(leaf);
+            const double r0 = dpp_f64<kDppPairRight>(leaf);
+            const double s1 = l0 + r0;
+            const double l1 = dpp_f64<kDppQuadLeft>(s1);
+            const double r1 = dpp_f64<kDppQuadRight>(s1);
+            const double s2 = l1 + r1;
             const double p2 = dpp_f64<kDppHalfMirror>(s2);
             const double s3 = s2 + p2;
             const double p3 = dpp_f64<kDppRowMirror>(s3);
@@ -744,14 +762,18 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
                 p5 = xlane_f64(s5, 32);
                 a0 = s5 + p5;
             }
-            if (run) {
-                if (a0 == 0.0) {
-                    run = false;
-                } else if (ev >= c.cap) {
-                    run = false;
-                    capped = true;
-                }
+            {
+                // (without branches: a row with no propensity left stops, a
+                // running row at the event cap stops and is flagged)
+                const bool live = run & (a0 != 0.0);
+                const bool at_cap = live & (ev >= c.cap);
+                capped |= at_cap;
+                run = live & !at_cap;
             }
+            // the draw is waited for only here, after the rebuild (whose
+            // exchanges cover the read's latency), and not after the branch
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("" ::"v"(e1), "v"(u2));
             if (!__any(run)) break;
             // the clock, without a branch: the division then overlaps the
             // descent below (a lane that is not running discards it)
@@ -768,8 +790,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             if (RW >= 32) descent_level(s4, p4, (lvo >> 4) & 1, rr, on);
             descent_level(s3, p3, (lvo >> 3) & 1, rr, on);
             descent_level(s2, p2, (lvo >> 2) & 1, rr, on);
-            descent_level(s1, p1, (lvo >> 1) & 1, rr, on);
-            descent_level(leaf, p0, lvo & 1, rr, on);
+            descent_children(l1, r1, (lvo >> 1) & 1, rr, on);
+            descent_children(l0, r0, lvo & 1, rr, on);
             on = on && event;
 
             // every lane evaluates the selection on its own voxel (from the
@@ -782,27 +804,31 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             int kdir = 0;
 #pragma unroll
             for (int l = 0; l < 3; ++l) kdir += resid >= thr[l] * a1 ? 1 : 0;
-            int dst = nb[0];
-#pragma unroll
-            for (int k = 1; k < 4; ++k) dst = kdir == k ? nb[k] : dst;
-            uint32_t word = (on && e.spec >= 0) ? (1u | ((uint32_t)e.spec << 4) | ((uint32_t)dst << 8)) : 0u;
+            const uint32_t dst = (nbp >> (8 * kdir)) & 0xFFu;
+            // the word: bit 0 set, the species times 8 in bits 3..5, the
+            // destination lane from bit 8
+            uint32_t word = (on && e.spec >= 0) ? (1u | ((uint32_t)e.spec << 3) | (dst << 8)) : 0u;
             // the row's diffusion word reaches every lane of the row (it is
             // zero outside the selected lane): OR over the 16-lane DPP row,
             // then across DPP rows for wider rows
             word = row_or(word);
             if (RW >= 32) word |= (uint32_t)__shfl_xor((int)word, 16, kWave);
             if (RW == 64) word |= (uint32_t)__shfl_xor((int)word, 32, kWave);
-            const bool recv = event && (word & 1u) && (int)(word >> 8) == lvo;
-            const uint32_t rs = (word >> 4) & 15u;
-            const uint32_t inc = recv ? (1u << (8u * (rs & 3u))) : 0u;
+            // (a word is set only in a row that takes its event)
+            const bool recv = (word & 0xFFFFFF01u) == (((uint32_t)lvo << 8) | 1u);
+            const uint64_t inc = (uint64_t)(recv ? 1u : 0u) << (word & 0x38u);
             // the source lane's change and the destination's +1 (never the
             // same lane) as one packed change
-            const ChanEntry ch{(on ? e.lo : 0u) + (rs < 4u ? inc : 0u),
-                               (on ? e.hi : 0u) + (rs < 4u ? 0u : inc), -1, 0};
+            const ChanEntry ch{(on ? e.lo : 0u) + (uint32_t)inc, (on ? e.hi : 0u) + (uint32_t)(inc >> 32), -1, 0};
             const bool changed = on || recv;
+            uint32_t any_bits = 0u;  // OR of the counts: the range check
 #pragma unroll
-            for (int q = 0; q < SM; ++q) xd[q] += entry_delta(ch, q);
-            overflow |= changed & out_of_range<SM>(xd, S, (double)kCountLimit);
+            for (int q = 0; q < SM; ++q) {
+                xi[q] += entry_delta(ch.lo, ch.hi, q);
+                xd[q] = (double)xi[q];
+                any_bits |= (uint32_t)xi[q];
+            }
+            overflow |= changed & (any_bits >= (uint32_t)kCountLimit);
             leaf = voxel_fold_cached(net, xd, degd, pre, ad);
             leaf = vox ? leaf : 0.0;
             if (event) ++ev;
@@ -811,7 +837,7 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
         if (vox) {
 #pragma unroll
             for (int q = 0; q < SM; ++q)
-                if (q < S) c.counts[vbase + q] = (int32_t)xd[q];
+                if (q < S) c.counts[vbase + q] = xi[q];
         }
         // the cell's total propensity now (the last iteration rebuilt every
         // row's tree, and a row's leaves stay put once it stops): the key
@@ -1082,20 +1108,27 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                 uint32_t word = 0;  // a jump: 1 | species << 4 | destination voxel << 8
                 if (on) {
                     uint16_t *x = cnt + v * S * stride;
+                    int32_t xi[SM];
 #pragma unroll
-                    for (int q = 0; q < SM; ++q) xd[q] = (double)x[q * stride];
+                    for (int q = 0; q < SM; ++q) {
+                        xi[q] = x[q * stride];
+                        xd[q] = (double)xi[q];
+                    }
                     const int deg = voxel_degree(go, v0 + v);
                     double resid, a1;
                     const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
                     const ChanEntry e = tab[sel];
+                    uint32_t any_bits = 0u;  // OR of the counts: the range check
 #pragma unroll
                     for (int q = 0; q < SM; ++q) {
                         if (q < S) {
-                            xd[q] += entry_delta(e, q);
-                            x[q * stride] = (uint16_t)(int32_t)xd[q];
+                            xi[q] += entry_delta(e.lo, e.hi, q);
+                            x[q * stride] = (uint16_t)xi[q];
+                            xd[q] = (double)xi[q];
+                            any_bits |= (uint32_t)xi[q];
                         }
                     }
-                    wide = out_of_range<SM>(xd, S, (double)kLane16Limit);
+                    wide = any_bits >= (uint32_t)kLane16Limit;
                     if (e.spec >= 0) {
                         const int dst = neighbour_at(go, v0 + v, jump_direction(resid, a1, deg));
                         word = 1u | ((uint32_t)e.spec << 4) | ((uint32_t)dst << 8);
