@@ -291,6 +291,41 @@ def test_edge_cases(oracle_lib):
     assert np.array_equal(t.read_counts(allow_flags=True), o.counts)
 
 
+def _range_problem():
+    """4 cells of 4x4 voxels, one voxel per cell starting 5 below 2^26 and
+    receiving A at rate 50 over two unit steps.  (No count can go negative:
+    tissue creation rejects a reaction that removes a species it does not
+    read.)"""
+    net = W._net(["A", "B"], [("make", [], {"A": 1}), ("turn", ["A"], {"B": 1})], None)
+    x0 = np.zeros((4 * 16, 2), np.int32)
+    x0[:, 1] = 2
+    x0[::16, 0] = (1 << 26) - 5
+    return W.make_problem(net, lattice=1, nx=2, ny=2, mesh_w=4, mesh_h=4, rates=[50.0, 1e-9],
+                          trans_rate=0.0, diffusion=[0.0, 1.0], init_counts=x0, seed=17,
+                          dt=1.0, n_steps=2, name="range")
+
+
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("mode", MODES)
+def test_count_range_flag_in_every_layout(oracle_lib, mode, jit):
+    """The range check in every chi layout (an OR of the integer counts
+    against the power-of-two limit): a count crossing 2^26 (in the compact
+    layout after the redo of its 16-bit counts) flags the tissue, with the
+    oracle's counts and events."""
+    from paper_1806_10889_amd import tissue as T
+    p = _range_problem()
+    o = _oracle(oracle_lib, p, 2, trace=False)
+    assert o.overflow
+    assert_same(gpu_run(p, 2, chi_mode=mode, jit=jit, allow_flags=True), o, trace=False)
+    t = T.Tissue(p, jit=jit)
+    t.set_chi_mode(mode)
+    t.step(1.0, 2)
+    with pytest.raises(T.TissueError) as ei:
+        t.read_counts()
+    assert ei.value.code == T.EOVERFLOW
+    t.close()
+
+
 def test_invalid_calls_enqueue_nothing():
     from paper_1806_10889_amd import tissue as T
     p = W.random_problem(93, lattice=1, nx=3, ny=3, model="nd5", mesh=(2, 2), dt=0.05)
