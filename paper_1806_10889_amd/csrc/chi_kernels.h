@@ -1007,7 +1007,9 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     u2 = group_bcast_f64<G>(uo, 0u);
                 }
             }
-            for (;;) {
+            // (it: the iteration, wave-uniform; a running cell has drawn
+            // it + 1 times after this iteration's draw)
+            for (uint32_t it = 0;; ++it) {
                 // the lane's 16 leaves and the levels of its subtree
                 double l[kLane16Leaves];
 #pragma unroll
@@ -1037,12 +1039,15 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     a0 = hs + p2;
                 }
                 last_a0 = a0;
-                if (a0 == 0.0) break;
-                if (ev >= c.cap) {
-                    capped = true;
-                    break;
-                }
-                ++j;
+                // a cell with no propensity left, or at the event cap, stops
+                // at the single exit below with the cells whose next event
+                // falls past the interval (its draw and descent are
+                // discarded, and only read memory)
+                const bool live = a0 != 0.0;
+                const bool at_cap = live && ev >= c.cap;
+                capped = capped || at_cap;
+                const bool go = live && !at_cap;
+                j += go ? 1u : 0u;
                 // the clock; the stop test waits until after the descent,
                 // which the division then overlaps (the descent only reads)
                 const double tn = t + e1 / a0;
@@ -1053,7 +1058,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     tdev::two_uniforms(wds, u1, u2);
                     e1 = -tdev::plog(u1);
                 } else {
-                    const uint32_t k = uni(j) & (uint32_t)(G - 1);
+                    const uint32_t k = (it + 1u) & (uint32_t)(G - 1);
                     if (k == 0) {  // the next G ordinals, one per lane of the group
                         const tdev::Words4 wds = tdev::philox4x32_10(j + (uint32_t)sub, c.step, cell,
                                                                      c.tagword, c.key0, c.key1);
@@ -1100,10 +1105,10 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     r = left ? r : r - L;
                     v = 2 * i1 + (left ? 0 : 1);
                 }
-                if (tn >= dt) break;
+                if (!go || tn >= dt) break;
                 t = tn;
 
-                const Mesh go{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
+                const Mesh gm{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
                 bool wide = false;
                 uint32_t word = 0;  // a jump: 1 | species << 4 | destination voxel << 8
                 if (on) {
@@ -1114,7 +1119,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                         xi[q] = x[q * stride];
                         xd[q] = (double)xi[q];
                     }
-                    const int deg = voxel_degree(go, v0 + v);
+                    const int deg = voxel_degree(gm, v0 + v);
                     double resid, a1;
                     const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
                     const ChanEntry e = tab[sel];
@@ -1130,7 +1135,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     }
                     wide = any_bits >= (uint32_t)kLane16Limit;
                     if (e.spec >= 0) {
-                        const int dst = neighbour_at(go, v0 + v, jump_direction(resid, a1, deg));
+                        const int dst = neighbour_at(gm, v0 + v, jump_direction(resid, a1, deg));
                         word = 1u | ((uint32_t)e.spec << 4) | ((uint32_t)dst << 8);
                     }
                     leafp[(size_t)(v >> 1) * stride * 2 + (v & 1)] = voxel_fold(net, xd, (double)deg);
@@ -1148,7 +1153,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
 #pragma unroll
                     for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(dv * S + q) * stride];
                     leafp[(size_t)(dv >> 1) * stride * 2 + (dv & 1)] =
-                        voxel_fold(net, xd, (double)voxel_degree(go, v0 + dv));
+                        voxel_fold(net, xd, (double)voxel_degree(gm, v0 + dv));
                 }
                 if (G > 1) wide = group_or<G>(wide ? 1u : 0u) != 0u;
                 if (wide) {  // redo this cell-step at full width

@@ -64,6 +64,17 @@ __device__ __forceinline__ void two_uniforms(const Words4 &w, double &u1, double
     u2 = (double)hiB * 0x1p-53;
 }
 
+// p z + c as the three-operand FMA, so that a coefficient held in a register
+// is read in place (the two-operand form overwrites its addend, and a
+// coefficient kept for the next call is copied first); the same single
+// rounding as fma.
+__device__ __forceinline__ double fma3(double p, double z, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ double plog(double x)
 {
     // x = m 2^k with m in [1, 2): exponent and mantissa fields (x is normal)
@@ -80,17 +91,17 @@ __device__ __forceinline__ double plog(double x)
     const double z = s * s;
     // Horner over 2/(2l+3), l = 11 down to 0
     double p = 2.0 / 25.0;
-    p = __builtin_fma(p, z, 2.0 / 23.0);
-    p = __builtin_fma(p, z, 2.0 / 21.0);
-    p = __builtin_fma(p, z, 2.0 / 19.0);
-    p = __builtin_fma(p, z, 2.0 / 17.0);
-    p = __builtin_fma(p, z, 2.0 / 15.0);
-    p = __builtin_fma(p, z, 2.0 / 13.0);
-    p = __builtin_fma(p, z, 2.0 / 11.0);
-    p = __builtin_fma(p, z, 2.0 / 9.0);
-    p = __builtin_fma(p, z, 2.0 / 7.0);
-    p = __builtin_fma(p, z, 2.0 / 5.0);
-    p = __builtin_fma(p, z, 2.0 / 3.0);
+    p = fma3(p, z, 2.0 / 23.0);
+    p = fma3(p, z, 2.0 / 21.0);
+    p = fma3(p, z, 2.0 / 19.0);
+    p = fma3(p, z, 2.0 / 17.0);
+    p = fma3(p, z, 2.0 / 15.0);
+    p = fma3(p, z, 2.0 / 13.0);
+    p = fma3(p, z, 2.0 / 11.0);
+    p = fma3(p, z, 2.0 / 9.0);
+    p = fma3(p, z, 2.0 / 7.0);
+    p = fma3(p, z, 2.0 / 5.0);
+    p = fma3(p, z, 2.0 / 3.0);
     const double q = __builtin_fma(s * z, p, 2.0 * s);
     const double dk = (double)k;
     return __builtin_fma(dk, 0x1.62e42fefa39efp-1, __builtin_fma(dk, 0x1.abc9e3b39803fp-56, q));

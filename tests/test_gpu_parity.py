@@ -326,6 +326,31 @@ def test_count_range_flag_in_every_layout(oracle_lib, mode, jit):
     t.close()
 
 
+@pytest.mark.parametrize("mesh", [(4, 4), (8, 4), (8, 8)])
+@pytest.mark.parametrize("mode", MODES)
+def test_event_cap_in_every_layout(oracle_lib, mode, mesh):
+    """Cells of 16, 32 and 64 voxels (the compact layout with 1, 2 and 4
+    lanes per cell) reach the event cap in every unit step: every layout
+    stops each cell-step at the cap and flags the tissue, with the oracle's
+    counts and events."""
+    from paper_1806_10889_amd import tissue as T
+    w, h = mesh
+    net = W._net(["A", "B"], [("make", [], {"A": 1}), ("turn", ["A"], {"B": 1})], None)
+    p = W.make_problem(net, lattice=1, nx=2, ny=2, mesh_w=w, mesh_h=h, rates=[20.0, 0.5],
+                       trans_rate=0.0, diffusion=[1.0, 0.5], init_counts=np.zeros((4 * w * h, 2), np.int32),
+                       seed=23, dt=1.0, n_steps=2, event_cap=500, name="cap")
+    o = _oracle(oracle_lib, p, 2, trace=True)
+    assert o.capped and (o.chi_trace_events == 500).all()
+    assert_same(gpu_run(p, 2, trace=True, chi_mode=mode, allow_flags=True), o)
+    t = T.Tissue(p)
+    t.set_chi_mode(mode)
+    t.step(1.0, 2)
+    with pytest.raises(T.TissueError) as ei:
+        t.read_counts()
+    assert ei.value.code == T.ELIMIT
+    t.close()
+
+
 def test_invalid_calls_enqueue_nothing():
     from paper_1806_10889_amd import tissue as T
     p = W.random_problem(93, lattice=1, nx=3, ny=3, model="nd5", mesh=(2, 2), dt=0.05)
