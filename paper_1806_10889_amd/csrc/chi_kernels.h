@@ -470,7 +470,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                 const tdev::Words4 wds = tdev::philox4x32_10(0u, c.step, cell, c.tagword, c.key0, c.key1);
                 double u1;
                 tdev::two_uniforms(wds, u1, u2);
-                e1 = -tdev::plog(u1);
+                e1 = -tdev::plog<true>(u1);
             }
             for (;;) {
                 const double a0 = tree[1 * stride];
@@ -488,7 +488,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
                     const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
                     double u1;
                     tdev::two_uniforms(wds, u1, u2);
-                    e1 = -tdev::plog(u1);
+                    e1 = -tdev::plog<true>(u1);
                 }
 
                 // descend the sum tree
@@ -999,7 +999,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                                                              c.tagword, c.key0, c.key1);
                 double u1;
                 tdev::two_uniforms(wds, u1, uo);
-                eo = -tdev::plog(u1);
+                eo = -tdev::plog<true>(u1);
                 e1 = eo;
                 u2 = uo;
                 if (G > 1) {
@@ -1056,7 +1056,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                     const tdev::Words4 wds = tdev::philox4x32_10(j, c.step, cell, c.tagword, c.key0, c.key1);
                     double u1;
                     tdev::two_uniforms(wds, u1, u2);
-                    e1 = -tdev::plog(u1);
+                    e1 = -tdev::plog<true>(u1);
                 } else {
                     const uint32_t k = (it + 1u) & (uint32_t)(G - 1);
                     if (k == 0) {  // the next G ordinals, one per lane of the group
@@ -1064,7 +1064,7 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                                                                      c.tagword, c.key0, c.key1);
                         double u1;
                         tdev::two_uniforms(wds, u1, uo);
-                        eo = -tdev::plog(u1);
+                        eo = -tdev::plog<true>(u1);
                     }
                     e1 = group_bcast_f64<G>(eo, k);
                     u2 = group_bcast_f64<G>(uo, k);

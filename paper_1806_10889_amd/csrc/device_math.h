@@ -75,6 +75,16 @@ __device__ __forceinline__ double fma3(double p, double z, double c)
     return r;
 }
 
+// One Horner step of plog: the compiler's fma, or fma3 (same bits).  fma3
+// pays where a draw is made at every event (one lane per cell); in the row
+// kernel's batched draws the compiler's form schedules better.
+template <bool FMA3>
+__device__ __forceinline__ double horner_step(double p, double z, double c)
+{
+    return FMA3 ? fma3(p, z, c) : __builtin_fma(p, z, c);
+}
+
+template <bool FMA3 = false>
 __device__ __forceinline__ double plog(double x)
 {
     // x = m 2^k with m in [1, 2): exponent and mantissa fields (x is normal)
@@ -91,17 +101,17 @@ __device__ __forceinline__ double plog(double x)
     const double z = s * s;
     // Horner over 2/(2l+3), l = 11 down to 0
     double p = 2.0 / 25.0;
-    p = fma3(p, z, 2.0 / 23.0);
-    p = fma3(p, z, 2.0 / 21.0);
-    p = fma3(p, z, 2.0 / 19.0);
-    p = fma3(p, z, 2.0 / 17.0);
-    p = fma3(p, z, 2.0 / 15.0);
-    p = fma3(p, z, 2.0 / 13.0);
-    p = fma3(p, z, 2.0 / 11.0);
-    p = fma3(p, z, 2.0 / 9.0);
-    p = fma3(p, z, 2.0 / 7.0);
-    p = fma3(p, z, 2.0 / 5.0);
-    p = fma3(p, z, 2.0 / 3.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 23.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 21.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 19.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 17.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 15.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 13.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 11.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 9.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 7.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 5.0);
+    p = horner_step<FMA3>(p, z, 2.0 / 3.0);
     const double q = __builtin_fma(s * z, p, 2.0 * s);
     const double dk = (double)k;
     return __builtin_fma(dk, 0x1.62e42fefa39efp-1, __builtin_fma(dk, 0x1.abc9e3b39803fp-56, q));

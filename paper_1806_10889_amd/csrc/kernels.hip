@@ -87,7 +87,7 @@ __device__ __forceinline__ void s_edge_fixed(int32_t *counts, long long gi, long
         ++j;
         double u1, u2;
         tdev::two_uniforms(wds, u1, u2);
-        const double tau = (-tdev::plog(u1)) / a0;
+        const double tau = (-tdev::plog<true>(u1)) / a0;
         const double tn = t + tau;
         if (tn >= dt) break;
         t = tn;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 ++j;
                 double u1, u2;
                 tdev::two_uniforms(wds, u1, u2);
-                const double tau = (-tdev::plog(u1)) / a0;
+                const double tau = (-tdev::plog<true>(u1)) / a0;
                 const double tn = t + tau;
                 if (tn >= dt) break;
                 t = tn;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                 ++j;
                 double u1, u2;
                 tdev::two_uniforms(wds, u1, u2);
-                const double tau = (-tdev::plog(u1)) / a0;
+                const double tau = (-tdev::plog<true>(u1)) / a0;
                 const double tn = t + tau;
                 if (tn >= dt) break;
                 t = tn;
