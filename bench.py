@@ -58,11 +58,11 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 TRAFFIC = {   # leg -> counters of its dominant chi kernel
     # hex 64x64 tissue, 4096 cells x 4x4 voxels: 400 dispatches of 200-step runs
-    "plain": {"digest": "a9bf96a2d3d58f5a3a1002751722508b85a6bdd9", "kernel": "tissue_chi_row",
-              "fetch_kib": 932.026, "write_kib": 1376.0},
+    "plain": {"digest": "eba7aa892c4b9e74d051bae2fa0e1140423cb3d3", "kernel": "tissue_chi_row",
+              "fetch_kib": 932.024, "write_kib": 1376.0},
     # 512 tissues, 3.12M cells, 200 steps: 450 dispatches
-    "batched": {"digest": "a9bf96a2d3d58f5a3a1002751722508b85a6bdd9", "kernel": "tissue_chi_lane16",
-                "fetch_kib": 652393.0, "write_kib": 1058720.0},
+    "batched": {"digest": "eba7aa892c4b9e74d051bae2fa0e1140423cb3d3", "kernel": "tissue_chi_lane16",
+                "fetch_kib": 652358.0, "write_kib": 1058680.0},
 }
 
 

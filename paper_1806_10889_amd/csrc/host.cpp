@@ -844,12 +844,6 @@ struct LaunchPlan {
         return std::max<uint32_t>(1, std::min<uint32_t>(L.n_items, (uint32_t)(cus * per_cu)));
     }
 
-    uint32_t s_grid(const SLaunch &L) const
-    {
-        if (!persistent) return L.n_items;
-        const int per_cu = wpc > 0 ? wpc : 8;
-        return std::max<uint32_t>(1, std::min<uint32_t>(L.n_items, (uint32_t)(cus * per_cu)));
-    }
 
     // Enqueue n steps (k = 0..n-1) then step_base += n.  With events
     // (2 per launch, in launch order) each kernel is bracketed; kind gets the
@@ -918,8 +912,11 @@ struct LaunchPlan {
             for (const SLaunch &L : s) {
                 if (L.n_items == 0) continue;
                 if (ev) HIP_TRY(hipEventRecord((*ev)[e++], st));
-                HIP_TRY(launch_s(s_grid(L), st, tbl, L.items, L.n_items, queue, persistent, dt,
-                                 (uint32_t)k));
+                // the S operator: one workgroup per item of 64 edges, whatever
+                // the chi launch shape (its face-count gathers wait on memory,
+                // and many resident workgroups hide that better than a
+                // persistent grid: 2 % on the batched sweep)
+                HIP_TRY(launch_s(L.n_items, st, tbl, L.items, L.n_items, queue, 0, dt, (uint32_t)k));
                 if (ev) {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
                     kind->push_back(-1);
