@@ -183,9 +183,13 @@ int tissue_network_check(const tissue_desc_t *d);
  * Returns 0 for an invalid descriptor. */
 size_t tissue_required_bytes(const tissue_desc_t *d);
 
-/* Validate d, build the lattice, edges, colour classes, meshes and face
+/* Create a tissue: the cell network of the paper's network file (Fig. 2:
+ * each cell with its neighbours and its parameters, among them a seed).
+ * Validate d, build the lattice, edges, colour classes, meshes and face
  * groups on the host, lay the state out in dev_buf (>= required bytes,
  * 256-byte aligned) and upload it on hip_stream (NULL: the null stream).
+ * Errors: TISSUE_EINVAL (descriptor; nothing allocated or enqueued),
+ * TISSUE_ENOMEM (dev_bytes too small), TISSUE_EDEVICE (a HIP call failed).
  * Unless TISSUE_FLAG_NO_JIT is set, the chi kernels are compiled for the
  * network's structure (hipRTC, cached per process by structure, not rates);
  * if that compilation fails the generic kernels are used (same bits). */
@@ -193,12 +197,19 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes,
                   void *hip_stream, tissue_t **out);
 
 /* Enqueue n_steps splitting steps of length dt (finite, > 0); n_steps >= 0.
- * Step indices continue from steps_done.  Asynchronous. */
+ * One step is chi on every cell over dt, then S over every edge (Algorithm
+ * section, the splitting assumption; Fig. 1); n_steps is the configuration
+ * file's number of steps and dt each module's end time (Fig. 3).  Step
+ * indices continue from steps_done.  Asynchronous.  TISSUE_EINVAL (nothing
+ * enqueued) for a bad dt or n_steps, or when steps_done + n_steps would pass
+ * 2^32 (the step index is part of every random counter). */
 int tissue_step(tissue_t *t, double dt, int32_t n_steps);
 
-/* Synchronise and copy the counts out, layout as init_counts.  n_out must be
- * sum_c V_c * n_species.  Returns TISSUE_EOVERFLOW / TISSUE_ELIMIT if that
- * condition was flagged (the counts are still copied). */
+/* Synchronise and copy the counts out, layout as init_counts (the state the
+ * paper's modules write to their output files after each run, Fig. 3).
+ * host_out is caller-owned, n_out must be sum_c V_c * n_species.  Returns
+ * TISSUE_EOVERFLOW / TISSUE_ELIMIT if that condition was flagged (the counts
+ * are still copied). */
 int tissue_read_counts(tissue_t *t, int32_t *host_out, size_t n_out);
 
 /* Synchronise and report the running totals. */
@@ -286,6 +297,9 @@ typedef struct {
  * synchronises and returns the summed per-kernel device times. */
 int tissue_step_timed(tissue_t *t, double dt, int32_t n_steps, tissue_timing_t *out);
 
+/* Release the handle (not dev_buf, which stays the caller's).  TISSUE_ESTATE,
+ * with nothing released, while a live batch holds the tissue: destroy the
+ * batches first. */
 int tissue_destroy(tissue_t *t);
 
 /*
@@ -295,6 +309,9 @@ int tissue_destroy(tissue_t *t);
  * (the batch's stream is used); each still sees exactly its own sequence of
  * steps, so its bits equal those of a lone tissue_step.  The batch needs
  * tissue_batch_required_bytes() of device memory for its work lists.
+ * A tissue may appear at most once in a batch (TISSUE_EINVAL otherwise: its
+ * cells would run twice in one launch); a member cannot be destroyed while
+ * the batch lives (tissue_destroy returns TISSUE_ESTATE).
  */
 size_t tissue_batch_required_bytes(tissue_t *const *ts, int32_t n);
 int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t dev_bytes,

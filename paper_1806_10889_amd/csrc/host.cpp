@@ -1069,6 +1069,7 @@ struct tissue {
     hipStream_t stream = nullptr;
     DevTissue host_rec{};          // last uploaded DevTissue (host copy)
     uint32_t steps_done = 0;
+    int batches = 0;               // live batches holding this tissue
     LaunchPlan lp;
     DevTissue *d_rec() const { return reinterpret_cast<DevTissue *>(dev + plan.off_tissue); }
     int32_t *d_counts() const { return reinterpret_cast<int32_t *>(dev + plan.off_counts); }
@@ -1260,6 +1261,8 @@ int tissue_step_timed(tissue_t *t, double dt, int32_t n_steps, tissue_timing_t *
     if (!t) return fail(TISSUE_EINVAL, "null tissue");
     if (!std::isfinite(dt) || !(dt > 0.0)) return fail(TISSUE_EINVAL, "dt must be finite and > 0");
     if (n_steps < 0) return fail(TISSUE_EINVAL, "n_steps must be >= 0");
+    if ((uint64_t)t->steps_done + (uint64_t)n_steps > 0xFFFFFFFFull)
+        return fail(TISSUE_EINVAL, "step index would exceed 2^32");
     const int rc = t->lp.run_timed(dt, n_steps, out);
     if (rc == TISSUE_OK) t->steps_done += (uint32_t)n_steps;
     return rc;
@@ -1437,6 +1440,9 @@ int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph)
 int tissue_destroy(tissue_t *t)
 {
     if (!t) return TISSUE_OK;
+    if (t->batches > 0)
+        return fail(TISSUE_ESTATE, "tissue is a member of " + std::to_string(t->batches) +
+                                       " live batch(es); destroy them first");
     (void)hipStreamSynchronize(t->stream);
     delete t;
     return TISSUE_OK;
@@ -1459,6 +1465,13 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
     if (!ts || n < 1) return fail(TISSUE_EINVAL, "batch needs >= 1 tissue");
     for (int32_t i = 0; i < n; ++i)
         if (!ts[i]) return fail(TISSUE_EINVAL, "null tissue in batch");
+    {
+        // a tissue twice in one launch would run its cells twice, racing on its counts
+        std::vector<const tissue *> sorted(ts, ts + n);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(TISSUE_EINVAL, "a tissue appears twice in the batch");
+    }
     for (int32_t i = 1; i < n; ++i)
         if (ts[i]->plan.strang != ts[0]->plan.strang)
             return fail(TISSUE_EINVAL, "batch members must share the splitting scheme");
@@ -1569,6 +1582,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     }
     rc = L.set_chi_mode(kModeAuto);
     if (rc != TISSUE_OK) return rc;
+    for (tissue *t : b->members) t->batches++;
     *out = b.release();
     return TISSUE_OK;
 }
@@ -1648,6 +1662,7 @@ int tissue_batch_destroy(tissue_batch_t *b)
 {
     if (!b) return TISSUE_OK;
     (void)hipStreamSynchronize(b->lp.stream);
+    for (tissue *t : b->members) t->batches--;
     delete b;
     return TISSUE_OK;
 }

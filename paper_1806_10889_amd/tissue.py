@@ -336,8 +336,9 @@ class Tissue:
         self.stats()
 
     def close(self):
+        """Destroy the handle (TISSUE_ESTATE while a live batch holds it)."""
         if getattr(self, "handle", None):
-            lib.tissue_destroy(self.handle)
+            _check(lib.tissue_destroy(self.handle), "tissue_destroy")
             self.handle = None
 
     def __del__(self):

@@ -298,3 +298,27 @@ def test_event_cap_stops_a_unit(oracle_lib):
     p["event_cap"] = 1000
     r = oracle_lib.run(p, 1.0, 1)
     assert r.capped and r.chi_events == 1000 and r.counts[0] == 1000
+
+
+@pytest.mark.parametrize("margin,expect", [(0, True), (1, False), (-3, True), (1000, False)])
+def test_range_flag_at_2_26(oracle_lib, margin, expect):
+    """The range contract: a count reaching 2^26 flags the tissue while the
+    simulation goes on.  Pinned by the textbook direct method on the same
+    streams (int64 counts, no range check).  Under pure birth the
+    propensity does not depend on the count, so each cell's births N_c over
+    the unit interval are fixed by its draws alone: a first textbook run
+    from zero gives them, and cells started at 2^26 - N_c - margin end
+    exactly `margin` below 2^26 (margin 0: exactly at the limit, flagged;
+    margin 1: one below, not flagged).  The oracle's counts are the
+    textbook's and its flag is set exactly when a count reached 2^26."""
+    p = W.birth_death(50.0, 0.0, 0, nx=3, ny=2, dt=1.0, n_steps=1, seed=29)
+    births = refmath.textbook_v1(p, 1).astype(np.int64)
+    assert births.min() > 20
+    x0 = np.where(np.arange(6) == 4, (1 << 26) - births - margin, 1000 - births)
+    q = dict(p, init_counts=x0.astype(np.int32).reshape(6, 1))
+    want = refmath.textbook_v1(q, 1).astype(np.int64)
+    assert want[4] == (1 << 26) - margin
+    r = oracle_lib.run(q, 1.0, 1)
+    assert np.array_equal(r.counts.astype(np.int64), want)
+    assert r.chi_events == int(births.sum())
+    assert r.overflow == bool((want >= (1 << 26)).any()) == expect
