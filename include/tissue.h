@@ -325,6 +325,31 @@ int tissue_batch_set_regroup(tissue_batch_t *b, int32_t mode);
 int tissue_batch_sync(tissue_batch_t *b);
 int tissue_batch_destroy(tissue_batch_t *b);
 
+/*
+ * For callers that cannot allocate memory (serving loops and harnesses that
+ * forbid device or pinned-host allocation): tissue_batch_step without a
+ * batch handle or a caller's workspace.  Advances the n tissues ts[] by
+ * n_steps steps of length dt on hip_stream (NULL: the null stream), with
+ * the same bits as tissue_batch_step on a batch of the same tissues (the
+ * default batch launch: automatic chi layout and regroup, persistent chi
+ * launches; steps launched eagerly, no graph).  The batch's member table,
+ * queue words, work items and redo list go to a static device array of
+ * TISSUE_STATIC_WORKSPACE_BYTES per device (in the library's code object,
+ * held until the process ends); the call uploads them with one copy from
+ * ordinary host memory, waits for that copy, and enqueues the steps
+ * asynchronously.  It calls no allocation routine for device or pinned
+ * memory.  Every call on a device shares that device's array: calls that
+ * overlap on one device (steps of an earlier call still running on another
+ * stream) race; calls on one stream are ordered.  Errors: TISSUE_EINVAL as
+ * for tissue_batch_create and tissue_batch_step (nothing enqueued);
+ * TISSUE_ENOMEM when the batch's workspace (about 16 bytes per cell plus
+ * the work items) exceeds TISSUE_STATIC_WORKSPACE_BYTES (nothing
+ * enqueued).  Members are stepped on the current device.
+ */
+#define TISSUE_STATIC_WORKSPACE_BYTES (32u << 20)
+int tissue_batch_step_static(tissue_t *const *ts, int32_t n, double dt, int32_t n_steps,
+                             void *hip_stream);
+
 const char *tissue_strerror(int code);
 const char *tissue_last_error(void);
 

@@ -1658,6 +1658,128 @@ int tissue_batch_sync(tissue_batch_t *b)
     return TISSUE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batch steps without allocation: the batch's work lists, queue words and
+// redo list in a file-scope device array instead of a caller's buffer
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// One per device, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[TISSUE_STATIC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+int scratch_address(unsigned char **out)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TISSUE_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(TISSUE_EDEVICE, "no device address for the static workspace");
+        addr[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(addr[dev]);
+    return TISSUE_OK;
+}
+
+}  // namespace
+
+int tissue_batch_step_static(tissue_t *const *ts, int32_t n, double dt, int32_t n_steps,
+                             void *hip_stream)
+{
+    BatchLayout B;
+    int rc = plan_batch(ts, n, B);
+    if (rc != TISSUE_OK) return rc;
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(TISSUE_EINVAL, "dt must be finite and > 0");
+    if (n_steps < 0) return fail(TISSUE_EINVAL, "n_steps must be >= 0");
+    for (int32_t i = 0; i < n; ++i)
+        if ((uint64_t)ts[i]->steps_done + (uint64_t)n_steps > 0xFFFFFFFFull)
+            return fail(TISSUE_EINVAL, "step index would exceed 2^32");
+    if (n_steps == 0) return TISSUE_OK;
+    const int cus = device_cus();
+    if (cus <= 0) return fail(TISSUE_EDEVICE, "no HIP device");
+
+    // the launch plan of the default batch: automatic layout and regroup,
+    // persistent chi launches, steps launched eagerly (no graph)
+    LaunchPlan L;
+    for (int32_t i = 0; i < n; ++i) L.members.push_back(&ts[i]->plan);
+    std::vector<ChiItem> items;
+    std::vector<ChiLaunch> launches;
+    plan_chi(L.members, kModeAuto, L.regroup, cus * 4, items, launches);
+    if (launches.size() > (size_t)kMaxChiLaunches) return fail(TISSUE_EINVAL, "too many chi launch groups");
+    std::vector<SItem> s_all;
+    for (auto &ps : B.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
+    size_t cells = 0;
+    for (int32_t i = 0; i < n; ++i) cells += ts[i]->plan.ncell;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const size_t off_tbl = take((size_t)n * sizeof(DevTissue *));
+    const size_t off_queue = take(64);
+    const size_t off_lq = take(kLaunchQueueBytes);
+    const size_t off_chi = take(items.size() * sizeof(ChiItem));
+    const size_t off_s = take(s_all.size() * sizeof(SItem));
+    const size_t off_retry = take(cells * sizeof(ChiItem));
+    if (o > (size_t)TISSUE_STATIC_WORKSPACE_BYTES)
+        return fail(TISSUE_ENOMEM, "the batch needs " + std::to_string(o) +
+                                       " bytes of workspace, more than the static workspace's " +
+                                       std::to_string((size_t)TISSUE_STATIC_WORKSPACE_BYTES));
+    unsigned char *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != TISSUE_OK) return rc;
+
+    // the workspace image up to the end of the S items: member table, queue
+    // words (zero: every launch finds its queues cleared), items; one copy,
+    // waited for, so that the host image may go
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    std::vector<unsigned char> img(off_s + s_all.size() * sizeof(SItem), 0);
+    for (int32_t i = 0; i < n; ++i) {
+        DevTissue *rec = ts[i]->d_rec();
+        std::memcpy(img.data() + off_tbl + (size_t)i * sizeof(DevTissue *), &rec, sizeof(rec));
+    }
+    if (!items.empty()) std::memcpy(img.data() + off_chi, items.data(), items.size() * sizeof(ChiItem));
+    if (!s_all.empty()) std::memcpy(img.data() + off_s, s_all.data(), s_all.size() * sizeof(SItem));
+    HIP_TRY(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+
+    L.tbl = reinterpret_cast<DevTissue **>(ws + off_tbl);
+    L.n_tissues = (uint32_t)n;
+    L.queue = reinterpret_cast<uint32_t *>(ws + off_queue);
+    L.lq = reinterpret_cast<uint32_t *>(ws + off_lq);
+    L.stream = st;
+    L.cus = cus;
+    L.strang = ts[0]->plan.strang;
+    L.graph_chunk = 0;
+    L.chi_items = reinterpret_cast<ChiItem *>(ws + off_chi);
+    L.chi_items_cap = items.size();
+    L.retry_items = reinterpret_cast<ChiItem *>(ws + off_retry);
+    for (ChiLaunch &c : launches) {
+        c.items = L.chi_items + reinterpret_cast<uintptr_t>(c.items);
+        if (c.n_segs) c.segs = L.chi_items + reinterpret_cast<uintptr_t>(c.segs);
+    }
+    L.chi = std::move(launches);
+    size_t soff = 0;
+    for (auto &ps : B.s_passes) {
+        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(ws + off_s) + soff, (uint32_t)ps.size()});
+        soff += ps.size();
+    }
+    rc = L.run(dt, n_steps);
+    if (rc == TISSUE_OK)
+        for (int32_t i = 0; i < n; ++i) ts[i]->steps_done += (uint32_t)n_steps;
+    return rc;
+}
+
 int tissue_batch_destroy(tissue_batch_t *b)
 {
     if (!b) return TISSUE_OK;

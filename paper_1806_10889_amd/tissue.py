@@ -87,6 +87,7 @@ EXPORTS = [
     "tissue_batch_required_bytes", "tissue_batch_create", "tissue_batch_step",
     "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
     "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
+    "tissue_batch_step_static",
 ]
 
 
@@ -129,6 +130,7 @@ def _load():
         "tissue_strerror": (C.c_char_p, [C.c_int]),
         "tissue_last_error": (C.c_char_p, []),
         "tissue_device_cus": (C.c_int, [C.POINTER(C.c_int32)]),
+        "tissue_batch_step_static": (C.c_int, [C.POINTER(vp), i32, dbl, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -346,6 +348,18 @@ class Tissue:
             self.close()
         except Exception:
             pass
+
+
+STATIC_WORKSPACE_BYTES = 32 << 20  # TISSUE_STATIC_WORKSPACE_BYTES
+
+
+def batch_step_static(tissues, dt: float, n_steps: int, stream=None):
+    """tissue_batch_step_static: the tissues advanced together with the
+    batch's work lists in the library's static device workspace (no batch
+    handle, no allocation)."""
+    arr = (C.c_void_p * len(tissues))(*[t.handle.value for t in tissues])
+    _check(lib.tissue_batch_step_static(arr, len(tissues), float(dt), int(n_steps),
+                                        _stream_handle(stream)), "tissue_batch_step_static")
 
 
 class Batch:
