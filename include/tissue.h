@@ -271,6 +271,19 @@ int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 /* Steps captured per HIP graph launch (0 disables graphs). */
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
 
+/* Lane refill of compact-layout launches of cells of at most 16 voxels
+ * (compiled networks, persistent launches): a wavefront does not wait for
+ * the busiest cell of its work item; once min_idle_lanes of its 64 lanes
+ * have finished their cell-step it writes those cells back and gives the
+ * idle lanes the next cells of the launch, which may belong to other items
+ * and other tissues of a batch.  0 turns refill off (lanes then wait for
+ * their item; the default: with the load-ordered regroup the cells of an
+ * item finish close together, and the refill phases -- each a chain of
+ * dependent loads that stalls the whole wavefront -- cost more than the
+ * idle lanes they recover); 1..64 idle lanes.  Results are bit-identical
+ * for every value.  Other values: TISSUE_EINVAL.  Synchronises the stream. */
+int tissue_set_refill(tissue_t *t, int32_t min_idle_lanes);
+
 /* Regroup pass before each compact-layout chi launch: the cells of each
  * leaf-count class (of each tissue) are reordered by their total propensity
  * after the previous compact pass, largest first, so that the cells sharing
@@ -291,6 +304,7 @@ typedef struct {
     uint32_t chi_launches, s_launches;
     int32_t chi_kernel;
     int32_t chi_leaves;
+    int32_t chi_refill;       /* nonzero: that group ran the compact layout with lane refill */
 } tissue_timing_t;
 
 /* tissue_step, launched eagerly with a HIP event pair around every kernel;
@@ -322,6 +336,7 @@ int tissue_batch_set_launch(tissue_batch_t *b, int32_t persistent, int32_t workg
 int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode);
 int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph);
 int tissue_batch_set_regroup(tissue_batch_t *b, int32_t mode);
+int tissue_batch_set_refill(tissue_batch_t *b, int32_t min_idle_lanes);
 int tissue_batch_sync(tissue_batch_t *b);
 int tissue_batch_destroy(tissue_batch_t *b);
 

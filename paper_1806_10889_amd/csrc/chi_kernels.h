@@ -1186,4 +1186,354 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
     leave_queue(queue, persistent != 0);
 }
 
+
+// ---------------------------------------------------------------------------
+// chi, compact layout with one lane per cell of at most 16 voxels, with lane
+// refill (compiled networks, persistent launches).  A wavefront's lanes do not
+// wait for the busiest cell of their work item: a lane whose cell-step ends
+// keeps its results in LDS, and once at least `refill_min` lanes are idle
+// (or all of them) the wavefront writes those cells back and hands the idle
+// lanes the next cells of the launch's items, which it takes from the queue
+// one item at a time.  So lanes hold cells of different items, tissues and
+// rate sets at once: everything a cell needs -- its tissue, counter words,
+// key schedule and rates -- lives in the lane's registers.  A cell-step is the
+// same sequence of operations on the same values as in the compact layout
+// above (the same contract: its draws depend only on its counters), so the
+// bits are the same; only the order in which cells finish differs.
+// Cells that reach 2^16 molecules are handed to the full-width redo as above.
+// ---------------------------------------------------------------------------
+namespace {
+
+// The channel table of a compiled network from its compile-time structure.
+template <class NET>
+__device__ __forceinline__ void compiled_channel_table(ChanEntry *tab)
+{
+    constexpr int RM = NET::RM, NDM = NET::NDM;
+    const NET n{};
+    const int k = threadIdx.x;
+    if (k <= RM + NDM) {
+        ChanEntry e{0u, 0u, -1, 0};
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+            if (k == r) {
+#pragma unroll
+                for (int s = 0; s < NET::SM; ++s) {
+                    const uint32_t byte = (uint32_t)(uint8_t)(int8_t)n.delta(r, s);
+                    if (s < 4) e.lo |= byte << (8 * s);
+                    else e.hi |= byte << (8 * (s - 4));
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < NDM; ++q)
+            if (k == RM + q) {
+                const int sp = n.dsp(q);
+                e.spec = sp;
+                if (sp < 4) e.lo = 0xFFu << (8 * sp);
+                else e.hi = 0xFFu << (8 * (sp - 4));
+            }
+        tab[k] = e;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Philox4x32-10 with the key schedule precomputed (rk0[r], rk1[r]: the key
+// words of round r), for keys held per lane.
+__device__ __forceinline__ tdev::Words4 philox_rk(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                  const uint32_t *rk0, const uint32_t *rk1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ rk0[round];
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ rk1[round];
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+    }
+    return tdev::Words4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+}  // namespace
+
+template <class NET>
+__device__ __forceinline__ void chi_refill_body(unsigned char *lds, const DevTissue *const *tbl,
+                                                const ChiItem *items, uint32_t n_items,
+                                                uint32_t *queue, int persistent, double dt,
+                                                uint32_t kstep, uint32_t tag, ChiItem *retry_items,
+                                                uint32_t *retry_count, int refill_min)
+{
+    static_assert(NET::kFixedSpecies, "lane refill runs compiled networks only");
+    constexpr int SM = NET::SM, S = NET::SM;
+    constexpr int stride = kWave;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+    __shared__ ChanEntry tab[kChanSlots];
+    compiled_channel_table<NET>(tab);
+    const int lane = threadIdx.x;
+    double *leafp = reinterpret_cast<double *>(lds) + 2 * lane;
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(lds + (size_t)stride * kLane16Leaves * 8) + lane;
+
+    // the wavefront's item being handed out (wave-uniform)
+    uint32_t cursor = blockIdx.x;
+    uint32_t pend_next = 0, pend_count = 0, pend_tissue = 0, pend_first = 0, pend_model = 0;
+    bool drained = false;
+
+    // the lane's cell
+    bool has = false, fin = false, retry = false, capped = false;
+    const DevTissue *T = nullptr;
+    uint32_t tix = 0, model = 0, lidx = 0, cell = 0, step = 0, tagword = 0, cap = 0;
+    uint32_t rk0[10], rk1[10];
+    Mesh g{1, 1, 65537};
+    int nloc = 0;
+    long long gbase = 0;
+    NET net;
+    double t = 0.0, last_a0 = 0.0, e1 = 0.0, u2 = 0.0;
+    uint32_t j = 0, ev = 0;
+    double xd[SM];
+
+    for (;;) {
+        const uint64_t idle = __ballot(!has || fin);
+        const int n_idle = __popcll(idle);
+        if (n_idle == kWave || (!drained && n_idle >= refill_min)) {
+            // write the finished cells back
+            if (fin) {
+                if (retry) {
+                    const uint32_t at = atomicAdd(retry_count, 1u);
+                    retry_items[at] = ChiItem{tix, lidx, 1u, model};
+                } else {
+                    int32_t *counts = T->counts;
+                    const int n = nloc * S;
+                    for (int i = 0; i < n; ++i) counts[gbase + i] = (int32_t)cnt[i * stride];
+                    if (T->tr_chi_ev) {
+                        const uint32_t ts = T->trace_steps, nc = T->n_cells;
+                        const size_t at = (size_t)(step % ts) * nc + cell;
+                        T->tr_chi_ev[at] = tag ? T->tr_chi_ev[at] + ev : ev;  // 2nd half adds
+                        T->tr_chi_t[at] = (unsigned long long)__double_as_longlong(t);
+                    }
+                    T->load[cell] = (float)last_a0;  // the key of the next regroup
+                }
+            }
+            // their totals, summed per tissue across the wavefront
+            uint64_t todo = __ballot(fin && !retry);
+            while (todo) {
+                const int leader = __builtin_ctzll(todo);
+                const uint32_t lt = (uint32_t)__builtin_amdgcn_readlane((int)tix, leader);
+                const bool mine = fin && !retry && tix == lt;
+                const uint32_t ev_sum = wave_sum_u32(mine ? ev : 0u);
+                const uint32_t dr_sum = wave_sum_u32(mine ? j : 0u);
+                const bool any_cap = __any(mine && capped);
+                if (lane == leader) {
+                    if (ev_sum) atomicAdd(T->stats + 0, (unsigned long long)ev_sum);
+                    if (dr_sum) atomicAdd(T->stats + 2, (unsigned long long)dr_sum);
+                    if (any_cap) atomicOr(T->flags + 1, 1u);
+                }
+                todo &= ~__ballot(mine);
+            }
+            has = has && !fin;
+            fin = false;
+            // hand the idle lanes the next cells
+            bool got = false;
+            while (!drained) {
+                const uint64_t free = __ballot(!has);
+                if (free == 0) break;
+                if (pend_next >= pend_count) {
+                    const uint32_t it = next_item(queue, persistent != 0, cursor);
+                    if (it >= n_items) {
+                        drained = true;
+                        break;
+                    }
+                    const ChiItem item = items[it];
+                    pend_tissue = uni(item.tissue);
+                    pend_first = uni(item.first);
+                    pend_count = uni(item.count);
+                    pend_model = uni(item.model);
+                    pend_next = 0;
+                }
+                const uint32_t rank = lanes_below(free);
+                const uint32_t avail = pend_count - pend_next;
+                if (!has && rank < avail) {
+                    has = true;
+                    got = true;
+                    tix = pend_tissue;
+                    model = pend_model;
+                    lidx = pend_first + pend_next + rank;
+                }
+                pend_next += min(avail, (uint32_t)__popcll(free));
+            }
+            // the new cells: context, counts, leaves, first draw
+            if (got) {
+                T = tbl[tix];
+                const DevModel *M = T->models + model;
+                net.load(*M);
+                step = T->step_base + kstep;
+                const uint64_t seed = (uint64_t)T->seed;
+                uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+                for (int r = 0; r < 10; ++r) {
+                    rk0[r] = k0;
+                    rk1[r] = k1;
+                    k0 += kWeylA;
+                    k1 += kWeylB;
+                }
+                tagword = (T->sim_id << 2) | tag;
+                cap = T->event_cap;
+                cell = (uint32_t)T->cell_list[lidx];
+                g.w = T->wh[2 * cell];
+                g.h = T->wh[2 * cell + 1];
+                g.inv_w = 65536 / g.w + 1;
+                nloc = min(g.w * g.h, kLane16Leaves);
+                gbase = (long long)T->vox_off[cell] * S;
+                const int32_t *counts = T->counts;
+                retry = false;
+                const int n = nloc * S;
+                for (int i = 0; i < n; ++i) {
+                    const int32_t x = counts[gbase + i];
+                    retry |= x >= kLane16Limit;
+                    cnt[i * stride] = (uint16_t)x;
+                }
+                t = 0.0;
+                last_a0 = 0.0;
+                j = 0;
+                ev = 0;
+                capped = false;
+                fin = retry;  // a cell over 16 bits goes to the redo untouched
+                if (!retry) {
+#pragma unroll
+                    for (int k = 0; k < kLane16Leaves / 2; ++k) {
+                        double two[2];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int v = 2 * k + h;
+                            two[h] = 0.0;
+                            if (v < nloc) {
+#pragma unroll
+                                for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(v * S + q) * stride];
+                                two[h] = voxel_fold(net, xd, (double)voxel_degree(g, v));
+                            }
+                        }
+                        double *sl = leafp + (size_t)k * stride * 2;
+                        sl[0] = two[0];
+                        sl[1] = two[1];
+                    }
+                    const tdev::Words4 wds = philox_rk(0u, step, cell, tagword, rk0, rk1);
+                    double u1;
+                    tdev::two_uniforms(wds, u1, u2);
+                    e1 = -tdev::plog<true>(u1);
+                }
+            }
+            if (!__any(has)) break;
+        }
+        if (has && !fin) {
+            // one event of the lane's cell: the 16 leaves and the subtree levels
+            double l[kLane16Leaves];
+#pragma unroll
+            for (int k = 0; k < kLane16Leaves / 2; ++k) {
+                const double *sl = leafp + (size_t)k * stride * 2;
+                l[2 * k] = sl[0];
+                l[2 * k + 1] = sl[1];
+            }
+            double q1[8], q2[4], q3[2];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) q1[k] = l[2 * k] + l[2 * k + 1];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q2[k] = q1[2 * k] + q1[2 * k + 1];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) q3[k] = q2[2 * k] + q2[2 * k + 1];
+            const double a0 = q3[0] + q3[1];
+            last_a0 = a0;
+            const bool live = a0 != 0.0;
+            const bool at_cap = live && ev >= cap;
+            capped = capped || at_cap;
+            const bool go = live && !at_cap;
+            j += go ? 1u : 0u;
+            // the clock; the stop test waits until after the descent (which
+            // only reads) so that the division overlaps it
+            const double tn = t + e1 / a0;
+            double r = u2 * a0;
+            {
+                const tdev::Words4 wds = philox_rk(j, step, cell, tagword, rk0, rk1);
+                double u1;
+                tdev::two_uniforms(wds, u1, u2);
+                e1 = -tdev::plog<true>(u1);
+            }
+            int v = 0;
+            {
+                double L = q3[0], R = q3[1];
+                bool left = (r < L) || (R == 0.0);
+                r = left ? r : r - L;
+                const int b3 = left ? 0 : 1;
+                L = b3 ? q2[2] : q2[0];
+                R = b3 ? q2[3] : q2[1];
+                left = (r < L) || (R == 0.0);
+                r = left ? r : r - L;
+                const int i2 = 2 * b3 + (left ? 0 : 1);
+                const double *pa = leafp + (size_t)(2 * i2) * stride * 2;
+                const double *pb = pa + (size_t)stride * 2;
+                const double la0 = pa[0], la1 = pa[1], lb0 = pb[0], lb1 = pb[1];
+                L = la0 + la1;
+                R = lb0 + lb1;
+                left = (r < L) || (R == 0.0);
+                r = left ? r : r - L;
+                const int i1 = 2 * i2 + (left ? 0 : 1);
+                L = left ? la0 : lb0;
+                R = left ? la1 : lb1;
+                left = (r < L) || (R == 0.0);
+                r = left ? r : r - L;
+                v = 2 * i1 + (left ? 0 : 1);
+            }
+            if (!go || tn >= dt) {
+                fin = true;
+            } else {
+                t = tn;
+                const Mesh gm{opaque(g.w), opaque(g.h), opaque(g.inv_w)};
+                uint16_t *x = cnt + v * S * stride;
+                int32_t xi[SM];
+#pragma unroll
+                for (int q = 0; q < SM; ++q) {
+                    xi[q] = x[q * stride];
+                    xd[q] = (double)xi[q];
+                }
+                const int deg = voxel_degree(gm, v);
+                double resid, a1;
+                const int sel = voxel_select(net, xd, (double)deg, r, resid, a1);
+                const ChanEntry e = tab[sel];
+                uint32_t any_bits = 0u;  // OR of the counts: the range check
+#pragma unroll
+                for (int q = 0; q < SM; ++q) {
+                    xi[q] += entry_delta(e.lo, e.hi, q);
+                    x[q * stride] = (uint16_t)xi[q];
+                    xd[q] = (double)xi[q];
+                    any_bits |= (uint32_t)xi[q];
+                }
+                bool wide = any_bits >= (uint32_t)kLane16Limit;
+                leafp[(size_t)(v >> 1) * stride * 2 + (v & 1)] = voxel_fold(net, xd, (double)deg);
+                if (e.spec >= 0) {
+                    const int dv = neighbour_at(gm, v, jump_direction(resid, a1, deg));
+                    uint16_t *xdst = cnt + (dv * S + e.spec) * stride;
+                    const int32_t nd = (int32_t)*xdst + 1;
+                    wide |= nd >= kLane16Limit;
+                    *xdst = (uint16_t)nd;
+#pragma unroll
+                    for (int q = 0; q < SM; ++q) xd[q] = (double)cnt[(dv * S + q) * stride];
+                    leafp[(size_t)(dv >> 1) * stride * 2 + (dv & 1)] =
+                        voxel_fold(net, xd, (double)voxel_degree(gm, dv));
+                }
+                if (wide) {  // redo this cell-step at full width
+                    retry = true;
+                    fin = true;
+                } else {
+                    ++ev;
+                }
+            }
+        }
+    }
+    leave_queue(queue, persistent != 0);
+}
 }  // namespace tissue_impl

@@ -58,6 +58,7 @@ constexpr int kMaxChiLaunches = 64;
 constexpr size_t kLaunchQueueBytes = (size_t)kMaxChiLaunches * 8 * sizeof(uint32_t);
 constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kChiStaticLds = 512;  // the chi kernels' static LDS (channel table), rounded up
+constexpr int kDefaultRefillMin = 0;
 
 // Pinned host memory for the copies of the control path (tissue and batch
 // creation, work-item uploads, counts and stats readback).  The runtime
@@ -724,6 +725,10 @@ struct LaunchPlan {
     int wpc = 0;                // workgroups per CU in persistent mode (0 auto)
     int cus = 0;
     int graph_chunk = 50;
+    // compact launches of cells of at most 16 voxels with compiled networks
+    // and a persistent grid: a wavefront refills its idle lanes with new
+    // cells once this many are idle (0: never; lanes wait for their item)
+    int refill_min = kDefaultRefillMin;
     hipStream_t capture_stream = nullptr;
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     // side streams and fork/join events for running the leaf-count classes'
@@ -805,6 +810,12 @@ struct LaunchPlan {
                             &a.tag};
             hipFunction_t f = L.rw == 64 ? L.jit->row64 : L.rw == 32 ? L.jit->row32 : L.jit->row;
             e = hipModuleLaunchKernel(f, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
+        } else if (refills(L)) {
+            int rmin = refill_min;
+            void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.dt, &a.kstep,
+                            &a.tag, &a.retry_items, &a.retry_count, &rmin};
+            e = hipModuleLaunchKernel(L.jit->lane16r, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st,
+                                      args, nullptr);
         } else if (L.mode == kChiLane16) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
                             &a.dt, &a.kstep, &a.tag, &a.retry_items, &a.retry_count};
@@ -834,6 +845,13 @@ struct LaunchPlan {
                         &log2p, &r.dt, &r.kstep, &r.tag, &r.n_items_dev};
         return hipModuleLaunchKernel(L.jit->lane, r.grid, 1, 1, kWave, 1, 1, (unsigned)r.lds, st,
                                      args, nullptr);
+    }
+
+    // whether a chi launch runs the compact layout with lane refill
+    bool refills(const ChiLaunch &L) const
+    {
+        return L.mode == kChiLane16 && L.P <= 16 && persistent && refill_min > 0 &&
+               L.cells_per_item == kWave && L.jit && L.jit->lane16r;
     }
 
     uint32_t chi_grid(const ChiLaunch &L) const
@@ -1037,6 +1055,7 @@ struct LaunchPlan {
             T.chi_kernel = chi[g].mode == kChiRow ? (chi[g].rw > std::max(16, chi[g].P) ? kModeRowWide : kModeRow)
                          : chi[g].mode == kChiLane16 ? kModeLane16 : kModeLane;
             T.chi_leaves = chi[g].P;
+            T.chi_refill = refills(chi[g]) ? 1 : 0;
         }
         float tot = 0.f;
         HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
@@ -1428,6 +1447,15 @@ int tissue_set_regroup(tissue_t *t, int32_t mode)
     return t->lp.set_chi_mode(t->lp.chi_mode);
 }
 
+int tissue_set_refill(tissue_t *t, int32_t min_idle_lanes)
+{
+    if (!t || min_idle_lanes < 0 || min_idle_lanes > kWave) return fail(TISSUE_EINVAL, "refill must be 0..64");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    t->lp.refill_min = min_idle_lanes;
+    t->lp.clear_graphs();
+    return TISSUE_OK;
+}
+
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph)
 {
     if (!t || steps_per_graph < 0 || steps_per_graph > 100000) return fail(TISSUE_EINVAL, "bad graph chunk");
@@ -1634,6 +1662,15 @@ int tissue_batch_set_regroup(tissue_batch_t *b, int32_t mode)
     HIP_TRY(hipStreamSynchronize(b->lp.stream));
     b->lp.regroup = mode;
     return b->lp.set_chi_mode(b->lp.chi_mode);
+}
+
+int tissue_batch_set_refill(tissue_batch_t *b, int32_t min_idle_lanes)
+{
+    if (!b || min_idle_lanes < 0 || min_idle_lanes > kWave) return fail(TISSUE_EINVAL, "refill must be 0..64");
+    HIP_TRY(hipStreamSynchronize(b->lp.stream));
+    b->lp.refill_min = min_idle_lanes;
+    b->lp.clear_graphs();
+    return TISSUE_OK;
 }
 
 int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph)

@@ -117,6 +117,15 @@ std::string network_source(const DevModel &M)
           << "        queue, persistent, cells_per_item, dt, kstep, tag, retry_items, retry_count);\n"
           << "}\n";
     }
+    o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane16r(\n"
+      << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
+      << "    int persistent, double dt, uint32_t kstep, uint32_t tag, ChiItem *retry_items,\n"
+      << "    uint32_t *retry_count, int refill_min)\n"
+      << "{\n"
+      << "    extern __shared__ __align__(16) unsigned char lds[];\n"
+      << "    tissue_impl::chi_refill_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
+      << "        persistent, dt, kstep, tag, retry_items, retry_count, refill_min);\n"
+      << "}\n";
     for (int rw : {16, 32, 64}) {
         o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row"
           << (rw == 16 ? std::string() : std::to_string(rw)) << "(\n"
@@ -196,6 +205,7 @@ int jit_kernels(const DevModel &M, const JitKernels **out, std::string &err)
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16, k->module, "tissue_chi_lane16");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16x2, k->module, "tissue_chi_lane16x2");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16x4, k->module, "tissue_chi_lane16x4");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16r, k->module, "tissue_chi_lane16r");
     if (e != hipSuccess) {
         err = std::string("loading the compiled network: ") + hipGetErrorString(e);
         return -1;

@@ -18,6 +18,7 @@ struct JitKernels {
     hipFunction_t lane16 = nullptr; // one lane per cell, compact LDS
     hipFunction_t lane16x2 = nullptr; // compact, 2 lanes per cell (17..32 voxels)
     hipFunction_t lane16x4 = nullptr; // compact, 4 lanes per cell (33..64 voxels)
+    hipFunction_t lane16r = nullptr;  // compact, one lane per cell, lanes refilled (persistent)
 };
 
 // Cache key of a network's structure (not its rates).

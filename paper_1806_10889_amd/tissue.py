@@ -74,7 +74,7 @@ class Stats(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("chi_ms", C.c_double), ("s_ms", C.c_double), ("total_ms", C.c_double),
                 ("chi_launches", C.c_uint32), ("s_launches", C.c_uint32),
-                ("chi_kernel", C.c_int32), ("chi_leaves", C.c_int32)]
+                ("chi_kernel", C.c_int32), ("chi_leaves", C.c_int32), ("chi_refill", C.c_int32)]
 
 
 EXPORTS = [
@@ -87,7 +87,7 @@ EXPORTS = [
     "tissue_batch_required_bytes", "tissue_batch_create", "tissue_batch_step",
     "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
     "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
-    "tissue_batch_step_static",
+    "tissue_batch_step_static", "tissue_set_refill", "tissue_batch_set_refill",
 ]
 
 
@@ -131,6 +131,8 @@ def _load():
         "tissue_last_error": (C.c_char_p, []),
         "tissue_device_cus": (C.c_int, [C.POINTER(C.c_int32)]),
         "tissue_batch_step_static": (C.c_int, [C.POINTER(vp), i32, dbl, i32, vp]),
+        "tissue_set_refill": (C.c_int, [vp, i32]),
+        "tissue_batch_set_refill": (C.c_int, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -273,7 +275,7 @@ class Tissue:
         _check(lib.tissue_step_timed(self.handle, float(dt), int(n_steps), C.byref(t)), "tissue_step_timed")
         return dict(chi_ms=t.chi_ms, s_ms=t.s_ms, total_ms=t.total_ms,
                     chi_launches=t.chi_launches, s_launches=t.s_launches,
-                    chi_kernel=t.chi_kernel, chi_leaves=t.chi_leaves)
+                    chi_kernel=t.chi_kernel, chi_leaves=t.chi_leaves, chi_refill=t.chi_refill)
 
     def read_counts(self, allow_flags: bool = False) -> np.ndarray:
         out = np.empty(self.n_values, dtype=np.int32)
@@ -328,6 +330,10 @@ class Tissue:
 
     def set_graph_chunk(self, steps: int):
         _check(lib.tissue_set_graph_chunk(self.handle, int(steps)), "tissue_set_graph_chunk")
+
+    def set_refill(self, min_idle_lanes: int):
+        """Lane refill of compact launches (0 off, 1..64 idle lanes; results unchanged)."""
+        _check(lib.tissue_set_refill(self.handle, int(min_idle_lanes)), "tissue_set_refill")
 
     def set_regroup(self, mode: int):
         """0 off, 1 on, 2 automatic: the load-ordered regroup pass before
@@ -392,7 +398,7 @@ class Batch:
                "tissue_batch_step_timed")
         return dict(chi_ms=t.chi_ms, s_ms=t.s_ms, total_ms=t.total_ms,
                     chi_launches=t.chi_launches, s_launches=t.s_launches,
-                    chi_kernel=t.chi_kernel, chi_leaves=t.chi_leaves)
+                    chi_kernel=t.chi_kernel, chi_leaves=t.chi_leaves, chi_refill=t.chi_refill)
 
     def set_launch(self, persistent: bool, workgroups_per_cu: int = 0):
         _check(lib.tissue_batch_set_launch(self.handle, int(bool(persistent)), int(workgroups_per_cu)),
@@ -403,6 +409,9 @@ class Batch:
 
     def set_graph_chunk(self, steps: int):
         _check(lib.tissue_batch_set_graph_chunk(self.handle, int(steps)), "tissue_batch_set_graph_chunk")
+
+    def set_refill(self, min_idle_lanes: int):
+        _check(lib.tissue_batch_set_refill(self.handle, int(min_idle_lanes)), "tissue_batch_set_refill")
 
     def set_regroup(self, mode: int):
         _check(lib.tissue_batch_set_regroup(self.handle, int(mode)), "tissue_batch_set_regroup")

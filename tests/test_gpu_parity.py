@@ -190,6 +190,65 @@ def test_batch_compact_wide_cells_with_redo(oracle_lib, persistent):
         assert (st["chi_events"], st["s_events"], st["draws"]) == (o.chi_events, o.s_events, o.draws)
 
 
+@pytest.mark.parametrize("refill,regroup", [(0, 0), (1, 0), (8, 0), (8, 1), (33, 1), (64, 0)])
+def test_lane_refill_uneven_loads(oracle_lib, refill, regroup):
+    """The compact layout with lane refill in a persistent batch: a
+    wavefront's idle lanes take the next cells of the launch, of other items
+    and other tissues, while its busy lanes go on.  Tissues with loads that
+    differ by more than an order of magnitude (rates scaled per tissue, a
+    few hot cells with twenty times the molecules), cells of 4..16 voxels
+    (1 lane each) next to larger ones (2 and 4 lanes, no refill), counts at
+    2^16 redone at full width; graphs of 2 steps and an eager step; every
+    member's counts, totals and per-cell traces against the oracle."""
+    from paper_1806_10889_amd import tissue as T
+    probs = []
+    for k, (mesh, scale) in enumerate([((4, 4), 1.0), ((2, 3), 12.0), (None, 3.0), ((4, 4), 0.3),
+                                        ((3, 3), 30.0)]):
+        p = W.random_problem(160 + k, lattice=k % 2, nx=7 + k, ny=6, model="nd5", mesh=mesh,
+                             uneven=mesh is None, dt=0.05, sim_id=20 + k, n_steps=5)
+        p["rates"] = p["rates"] * scale
+        V = p["mesh_w"].astype(np.int64) * p["mesh_h"]
+        off = np.concatenate([[0], np.cumsum(V)])
+        for c in (1, 9, 17):  # hot cells
+            p["init_counts"][off[c]:off[c + 1]] *= 20
+        p["init_counts"][off[5], 0] = 65535  # the redo at full width
+        probs.append(p)
+    ts = [T.Tissue(p, trace_steps=5) for p in probs]
+    b = T.Batch(ts)
+    b.set_chi_mode(3)
+    b.set_regroup(regroup)
+    b.set_refill(refill)
+    b.set_graph_chunk(2)
+    b.step(0.05, 5)
+    b.sync()
+    for p, t in zip(probs, ts):
+        o = _oracle(oracle_lib, p, 5)
+        assert_same(dict(counts=t.read_counts(), stats=t.stats(), trace=t.trace(0, 5)), o)
+    b.close()
+    with pytest.raises(T.TissueError) as ei:
+        ts[0].set_refill(65)
+    assert ei.value.code == T.EINVAL
+    for t in ts:
+        t.close()
+
+
+@pytest.mark.parametrize("refill", [0, 8])
+def test_step_timed_names_the_refill_kernel(oracle_lib, refill):
+    """A persistent compact launch of 4x4 cells reports whether it ran with
+    lane refill; same bits either way."""
+    from paper_1806_10889_amd import tissue as T
+    p = W.config2(side=40, n_steps=3)
+    t = T.Tissue(p)
+    t.set_chi_mode(3)
+    t.set_launch(True, 0)
+    t.set_refill(refill)
+    tm = t.step_timed(p["dt"], 3)
+    g = dict(counts=t.read_counts(), stats=t.stats())
+    t.close()
+    assert_same(g, _oracle(oracle_lib, p, 3, trace=False), trace=False)
+    assert tm["chi_kernel"] == 3 and tm["chi_refill"] == int(refill > 0)
+
+
 @pytest.mark.parametrize("scheme", ["lie", "strang"])
 @pytest.mark.parametrize("persistent", [False, True])
 def test_regroup_by_load_keeps_bits(oracle_lib, scheme, persistent):
