@@ -8,14 +8,20 @@ initial counts as a new simulation (sim_id = step index) and advance it over
 the whole horizon T (tissue_step(dt, 2000), replayed from captured HIP
 graphs).  value = (chi + S events) / wall time of the K timed steps.
 
-Also reported: the chi kernel's roofline fraction (HIP events around every
-launch of one extra simulation over the same horizon, launched eagerly; the
-kernel is bound by vector ALU issue, 432 lane-operations per event), the CPU
-FP64 oracle's rate on a bounded sample on the host cores, the batched form
-(512 tissues in one batch, with its own roofline) and the serving loop
+Also reported: the chi kernel's roofline fraction -- algorithmic lane
+operations per event (counted per leaf class) times events per launch over
+the live launch time (HIP events around every launch of one extra
+simulation over the same horizon, launched eagerly on the tissue's stream),
+or over the timed steps' wall time where a step forks several classes'
+launches -- with VALU busy, issued lane-slots per event and HBM bytes from
+the committed rocprofv3 counter figures of the same sources; the CPU FP64
+oracle's rate on a bounded sample on the host cores; the tiny plain
+workload (latency per simulation and per step); the batched form (512
+tissues in one batch, with its own roofline) and the serving loop
 (Poisson arrivals, continuous batching, p50/p99 latency).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--leg all|plain|uneven|batched|serving|dt|notch|multifidelity|large]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--leg all|plain|tiny|uneven|batched|serving|dt|notch|multifidelity|large]
 """
 from __future__ import annotations
 
@@ -39,31 +45,49 @@ if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
 
 METRIC = "SSA events/sec on 1 MI355X (batched vs plain); p50/p99 sim latency"
 
-# Algorithmic VALU work per accepted event, in full-rate lane-operation
-# equivalents (a quarter-rate instruction counts 4), for the 5-species
-# network on 4x4-voxel cells; derivation in the design notes.
-OPS_PER_CHI_EVENT = 432
+# Algorithmic VALU work per accepted chi event, in full-rate lane-operation
+# equivalents (a quarter-rate instruction counts 4): a fixed part (Philox4x32-10
+# 120, two uniforms 12, plog 40, the clock 15, r = U2 a0 1, the apply 6), per
+# channel slot of a voxel the scan (7) and the refolds of the two changed
+# voxels (8), per tree level the descent (5) and the two ancestor paths (2).
+# The 5-species network has 14 channel slots (9 reactions, 5 diffusing
+# species): 432 on cells of 16 leaves.  Derivation in the design notes.
+OPS_FIXED, OPS_PER_CHANNEL, OPS_PER_LEVEL = 194, 15, 7
 OPS_PER_S_EVENT = 289
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
-# HBM traffic of the dominant chi kernel per launch, from rocprofv3 counter
-# runs of this script's legs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch),
-# each scaled by what the counter reads for a plain 256 MiB device copy
-# (FETCH_SIZE 131085 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  The
-# figures hold for the kernel sources whose digest is recorded with them; any
-# change to those sources makes `traffic` null until the counters are taken
+
+def ops_per_chi_event(leaves: int, channels: int = 14) -> float:
+    return OPS_FIXED + OPS_PER_CHANNEL * channels + OPS_PER_LEVEL * math.log2(max(leaves, 1))
+
+
+def ops_per_chi_event_of(p) -> float:
+    """Weighted over the tissue's leaf-count classes by their share of the
+    voxels (events per voxel are alike across the classes)."""
+    import numpy as np
+    V = np.asarray(p["mesh_w"], np.int64) * np.asarray(p["mesh_h"], np.int64)
+    P = 2.0 ** np.ceil(np.log2(np.maximum(V, 1)))
+    ch = int(p["n_reactions"]) + int((np.asarray(p["diffusion"]) > 0).sum())
+    return float(np.sum(V * (OPS_FIXED + OPS_PER_CHANNEL * ch + OPS_PER_LEVEL * np.log2(P))) / V.sum())
+
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s
+N_SIMD, CLOCK_HZ = 256 * 4, 2.4e9
+PEAK_LANE_OPS = N_SIMD * 16 * CLOCK_HZ
+PEAK_HBM = 8.0e12
+
+# Counter figures of each leg's chi kernels from rocprofv3 runs of this
+# script (profiles/), per dispatch: the kernel-trace duration and the SQ
+# counters of the same run, FETCH_SIZE and WRITE_SIZE (KiB; each pass also
+# carries the SQ counters and the duration).  FETCH_SIZE and WRITE_SIZE are
+# scaled by what they read for a plain 256 MiB device copy (FETCH 131085 KiB,
+# WRITE 262144 KiB for 262144 KiB moved each way).  chi_events_per_step is
+# that run's own count (chi events over the steps it ran, from its bench
+# line).  The figures hold for the kernel sources whose digest is recorded;
+# any change to those sources makes them null until the counters are taken
 # again.
 FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
-TRAFFIC = {   # leg -> counters of its dominant chi kernel
-    # hex 64x64 tissue, 4096 cells x 4x4 voxels: 400 dispatches of 200-step runs
-    "plain": {"digest": "eba7aa892c4b9e74d051bae2fa0e1140423cb3d3", "kernel": "tissue_chi_row",
-              "fetch_kib": 932.024, "write_kib": 1376.0},
-    # 512 tissues, 3.12M cells, 200 steps: 450 dispatches
-    "batched": {"digest": "eba7aa892c4b9e74d051bae2fa0e1140423cb3d3", "kernel": "tissue_chi_lane16",
-                "fetch_kib": 652358.0, "write_kib": 1058680.0},
-}
+COUNTERS = {}
 
 
 def kernel_source_digest() -> str:
@@ -78,17 +102,37 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def traffic_bytes(leg: str, kernel: str):
-    rec = TRAFFIC.get(leg)
-    if not rec or rec["kernel"] != kernel or rec["digest"] != kernel_source_digest():
+def counter_figures(leg: str, kernels=None, live_s_per_step=None):
+    """VALU busy, issued lane-slots per event and HBM bytes of the leg's chi
+    kernels (one dispatch of each per step) from the committed counter
+    figures, or None when they were taken on other sources.  VALU busy =
+    SQ_INSTS_VALU x 4 cycles / (SIMDs x the dispatch's own duration in that
+    run x clock); lane-slots per event = SQ_INSTS_VALU x 64 / chi events
+    per step; HBM fraction = the scaled FETCH + WRITE bytes over the live
+    time per step (or the counter run's duration) / 8 TB/s."""
+    rec = COUNTERS.get(leg)
+    if not rec or rec["digest"] != kernel_source_digest():
         return None
-    return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
+    kernels = sorted(rec["kernels"]) if kernels is None else kernels
+    ks = [rec["kernels"][k] for k in kernels if k in rec["kernels"]]
+    if not kernels or len(ks) != len(kernels):
+        return None
+    valu = sum(k["sq_insts_valu"] for k in ks)
+    dur = sum(k["avg_us"] for k in ks) * 1e-6
+    traffic = 1024.0 * sum(k["fetch_kib"] * FETCH_SCALE + k["write_kib"] * WRITE_SCALE for k in ks)
+    t = live_s_per_step or dur
+    return {"kernels": list(kernels), "valu_busy": valu * 4.0 / (N_SIMD * dur * CLOCK_HZ),
+            "issued_lane_slots_per_event": valu * 64.0 / rec["chi_events_per_step"],
+            "counter_run_us_per_step": dur * 1e6, "traffic": traffic,
+            "hbm_frac": traffic / t / PEAK_HBM, "profile": rec["profile"]}
 
 
-def chi_kernel_name(mode: int, jit: bool, leaves: int = 16) -> str:
+def chi_kernel_name(mode: int, jit: bool, leaves: int = 16, refill: int = 0) -> str:
     base = {0: "lane", 1: "row", 3: "lane16", 4: "row"}.get(mode, "unknown")
     if base == "lane16" and leaves > 16:
         base += f"x{leaves // 16}"  # the compact layout with 2 or 4 lanes per cell
+    elif base == "lane16" and refill and jit:
+        base += "r"  # one lane per cell, lanes refilled
     if base == "row" and jit and (leaves > 16 or mode == 4):
         base += str(max(leaves, 32) if mode == 4 else leaves)
     return f"tissue_chi_{base}" if jit else f"chi_{base}_kernel"
@@ -114,6 +158,8 @@ def run_single(args, torch, T, p, leg, sims, warmup):
     stream = torch.cuda.current_stream()
     t = T.Tissue(p, device="cuda:0", stream=stream)
     t.set_regroup(args.regroup)
+    if args.refill >= 0:
+        t.set_refill(args.refill)
     dt, n = p["dt"], p["n_steps"]
     if args.launch:
         mode, persistent, wpc, chunk = (int(v) for v in args.launch.split(","))
@@ -129,11 +175,14 @@ def run_single(args, torch, T, p, leg, sims, warmup):
         from paper_1806_10889_amd import autotune
         tuned = autotune.tune([p], dt, steps=min(50, n), reps=2, target=t, log=log)
         log(f"autotuned launch: {tuned['config']}")
+    basis = {"chi_events": 0, "steps": 0}  # every chi step this leg runs after tuning
 
     def one(k):
         t.restart(sim_id=k, start_step=0)
         t.step(dt, n)
         st = t.stats()  # synchronises the stream
+        basis["chi_events"] += st["chi_events"]
+        basis["steps"] += n
         return st["chi_events"] + st["s_events"], st
 
     for w in range(warmup):
@@ -155,28 +204,53 @@ def run_single(args, torch, T, p, leg, sims, warmup):
 
     # roofline pass: one more simulation over the same horizon, launched
     # eagerly with every kernel bracketed by HIP events on the tissue's stream
+    ops = ops_per_chi_event_of(p)
     t.restart(sim_id=sims + 7, start_step=0)
-    tm = t.step_timed(dt, min(n, args.roofline_steps) if args.roofline_steps > 0 else n)
+    rsteps = min(n, args.roofline_steps) if args.roofline_steps > 0 else n
+    tm = t.step_timed(dt, rsteps)
     st = t.stats()
+    basis["chi_events"] += st["chi_events"]
+    basis["steps"] += rsteps
     chi_per_launch = st["chi_events"] / max(tm["chi_launches"], 1)
     chi_avg_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
     s_avg_ms = tm["s_ms"] / max(tm["s_launches"], 1)
-    achieved = chi_per_launch * OPS_PER_CHI_EVENT / (chi_avg_ms * 1e-3)
-    kernel = chi_kernel_name(tm["chi_kernel"], bool(st["jit"]), tm["chi_leaves"])
-    roof = {
-        "bound": "alu", "kernel": kernel,
-        "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-        "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_bytes(leg, kernel),
-        "avg_launch_ms": chi_avg_ms, "events_per_launch": chi_per_launch,
-        "ops_per_event": OPS_PER_CHI_EVENT, "s_kernel_avg_ms": s_avg_ms,
-        "chi_share_of_kernel_time": tm["chi_ms"] / max(tm["chi_ms"] + tm["s_ms"], 1e-12),
-    }
+    kernel = chi_kernel_name(tm["chi_kernel"], bool(st["jit"]), tm["chi_leaves"], tm["chi_refill"])
+    launches_per_step = tm["chi_launches"] / max(rsteps, 1)
+    # the timed run: chi events x algorithmic operations over its wall time
+    timed = {"basis": "the timed simulations' chi events over their whole wall time (every "
+                      "kernel of a step, launch gaps included)",
+             "achieved": chi_ev * ops / elapsed / 1e12, "frac": chi_ev * ops / elapsed / PEAK_LANE_OPS}
+    if launches_per_step <= 1.0 + 1e-9:
+        # one chi launch per step: the kernel's own rate from its live launch times
+        achieved = chi_per_launch * ops / (chi_avg_ms * 1e-3)
+        cnt = counter_figures(leg, [kernel], live_s_per_step=chi_avg_ms * 1e-3)
+        roof = {"bound": "alu", "kernel": kernel,
+                "basis": "HIP events around every chi launch of one eager simulation over the horizon",
+                "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                "frac": achieved / PEAK_LANE_OPS, "avg_launch_ms": chi_avg_ms,
+                "events_per_launch": chi_per_launch}
+    else:
+        # several classes' launches per step, run as parallel graph branches in
+        # the timed run: the rate of the timed steps themselves
+        cnt = counter_figures(leg, None, live_s_per_step=elapsed / max(sims * n, 1))
+        roof = {"bound": "alu", "kernel": "every chi launch of a step (forked graph branches)",
+                "basis": timed["basis"], "achieved": timed["achieved"],
+                "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s", "frac": timed["frac"],
+                "eager_dominant_kernel": kernel,
+                "eager_avg_launch_ms": chi_avg_ms, "events_per_step": st["chi_events"] / max(rsteps, 1)}
+    roof.update({"ops_per_event": ops, "traffic": cnt["traffic"] if cnt else None,
+                 "hbm_frac": cnt["hbm_frac"] if cnt else None, "counters": cnt,
+                 "timed_run": timed, "s_kernel_avg_ms": s_avg_ms,
+                 "chi_share_of_kernel_time": tm["chi_ms"] / max(tm["chi_ms"] + tm["s_ms"], 1e-12),
+                 "counter_basis": dict(basis)})
     res = dict(p=p, value=events / elapsed, elapsed=elapsed, lat=lat, chi=chi_ev, s=s_ev,
                roofline=roof, timing=tm, tuned=tuned, jit=bool(t.stats()["jit"]))
     cfg = (tuned or {}).get("config")
     t.close()
     if args.chain_steps > 0:
-        res["roofline"]["event_chains"] = event_chains(args, T, p, cfg)
+        res["roofline"]["event_chains"], more = event_chains(args, T, p, cfg)
+        for k in ("chi_events", "steps"):
+            res["roofline"]["counter_basis"][k] += more[k]
     return res
 
 
@@ -195,26 +269,40 @@ def event_chains(args, T, p, cfg):
     t.restart(sim_id=4242, start_step=0)
     tm = t.step_timed(p["dt"], n)
     ce = t.trace(0, n)[0].astype(np.float64)
+    basis = {"chi_events": t.stats()["chi_events"], "steps": n}
     t.close()
     busiest = float(ce.max(axis=1).mean())
     if tm["chi_launches"] != n:
-        return None  # several chi launches per step: no single chain per launch
+        return None, basis  # several chi launches per step: no single chain per launch
     launch_ms = tm["chi_ms"] / n
     return {"steps": n, "busiest_cell_events_per_step": busiest,
             "mean_cell_events_per_step": float(ce.mean()),
             "avg_launch_ms": launch_ms,
-            "ns_per_event_on_busiest_chain": launch_ms * 1e6 / max(busiest, 1.0)}
+            "ns_per_event_on_busiest_chain": launch_ms * 1e6 / max(busiest, 1.0)}, basis
 
 
 def run_batched(args, torch, T, W):
     """Config-4-shaped sweep: independent tissues in one batch (one graph per
-    chunk of steps); latency = completion of the whole sweep per tissue."""
+    chunk of steps).  Every member shares every launch, so each tissue's
+    result is complete when the sweep is: a tissue's completion time is the
+    sweep's, and its p50/p99 are taken over the repetitions."""
     probs = W.config4(n_tissues=args.batch_tissues, n_steps=args.batch_steps)
     stream = torch.cuda.current_stream()
     ts = [T.Tissue(p, device="cuda:0", stream=stream) for p in probs]
     b = T.Batch(ts, device="cuda:0", stream=stream)
     b.set_regroup(args.regroup)
+    if args.refill >= 0:
+        b.set_refill(args.refill)
     dt, n = probs[0]["dt"], probs[0]["n_steps"]
+    basis = {"chi_events": 0, "steps": 0}
+
+    def totals():
+        chi = s_ = 0
+        for t in ts:
+            st = t.stats()
+            chi += st["chi_events"]
+            s_ += st["s_events"]
+        return chi, s_
 
     def one(k):
         for i, t in enumerate(ts):
@@ -223,47 +311,96 @@ def run_batched(args, torch, T, W):
         b.step(dt, n)
         b.sync()
         wall = time.perf_counter() - a
-        ev = 0
-        for t in ts:
-            st = t.stats()
-            ev += st["chi_events"] + st["s_events"]
-        return ev, wall
+        chi, s_ = totals()
+        basis["chi_events"] += chi
+        basis["steps"] += n
+        return chi, s_, wall
 
     # warm-up: network compilation and the graph capture of one chunk
     for i, t in enumerate(ts):
         t.restart(sim_id=i + 99000, start_step=0)
     b.step(dt, min(n, 50))
     b.sync()
-    tot_ev, tot_t, walls = 0, 0.0, []
+    basis["chi_events"] += totals()[0]
+    basis["steps"] += min(n, 50)
+    tot_ev, tot_chi, tot_t, walls = 0, 0, 0.0, []
     for k in range(max(1, args.batch_reps)):
-        ev, wall = one(k)
-        tot_ev += ev
+        chi, s_, wall = one(k)
+        tot_ev += chi + s_
+        tot_chi += chi
         tot_t += wall
         walls.append(wall)
-        log(f"batched rep {k + 1}: {ev} events in {wall * 1e3:.1f} ms")
+        log(f"batched rep {k + 1}: {chi + s_} events in {wall * 1e3:.1f} ms")
     cells = sum(p["nx"] * p["ny"] for p in probs)
     out = dict(events_per_s=tot_ev / tot_t, tissues=len(probs), cells=cells, steps=n, dt=dt,
-               sweep_ms_p50=pct(walls, 50) * 1e3, sweep_ms_p99=pct(walls, 99) * 1e3)
+               reps=len(walls), sweep_ms_p50=pct(walls, 50) * 1e3, sweep_ms_p99=pct(walls, 99) * 1e3,
+               tissue_completion_ms_p50=pct(walls, 50) * 1e3,
+               tissue_completion_ms_p99=pct(walls, 99) * 1e3,
+               tissue_completion="every member completes with the sweep (shared launches); "
+                                 "p50/p99 over the repetitions")
     # roofline of the batched chi kernel: the same sweep once more, launched
     # eagerly with HIP events around each launch
     for i, t in enumerate(ts):
         t.restart(sim_id=i + 777, start_step=0)
     tm = b.step_timed(dt, n)
-    chi_ev = sum(t.stats()["chi_events"] for t in ts)
+    chi_ev = totals()[0]
+    basis["chi_events"] += chi_ev
+    basis["steps"] += n
+    ops = ops_per_chi_event_of(probs[0])
     per_launch_ms = tm["chi_ms"] / max(tm["chi_launches"], 1)
-    achieved = chi_ev / max(tm["chi_launches"], 1) * OPS_PER_CHI_EVENT / (per_launch_ms * 1e-3)
-    kernel = chi_kernel_name(tm["chi_kernel"], bool(ts[0].stats()["jit"]), tm["chi_leaves"])
-    out["roofline"] = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12,
+    achieved = chi_ev / max(tm["chi_launches"], 1) * ops / (per_launch_ms * 1e-3)
+    kernel = chi_kernel_name(tm["chi_kernel"], bool(ts[0].stats()["jit"]), tm["chi_leaves"],
+                             tm["chi_refill"])
+    cnt = counter_figures("batched", [kernel], live_s_per_step=per_launch_ms * 1e-3)
+    out["roofline"] = {"bound": "alu", "kernel": kernel,
+                       "basis": "HIP events around every chi launch of one eager sweep",
+                       "achieved": achieved / 1e12,
                        "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                        "frac": achieved / PEAK_LANE_OPS,
-                       "traffic": traffic_bytes("batched", kernel),
+                       "traffic": cnt["traffic"] if cnt else None,
+                       "hbm_frac": cnt["hbm_frac"] if cnt else None, "counters": cnt,
                        "avg_launch_ms": per_launch_ms,
                        "events_per_launch": chi_ev / max(tm["chi_launches"], 1),
-                       "ops_per_event": OPS_PER_CHI_EVENT}
+                       "ops_per_event": ops,
+                       "s_kernel_avg_ms": tm["s_ms"] / max(tm["s_launches"], 1),
+                       "timed_run": {"achieved": tot_chi * ops / tot_t / 1e12,
+                                     "frac": tot_chi * ops / tot_t / PEAK_LANE_OPS,
+                                     "basis": "the timed sweeps' chi events over their wall time"},
+                       "counter_basis": dict(basis)}
     b.close()
     for t in ts:
         t.close()
     return out
+
+
+def run_tiny(args, torch, T, W):
+    """The plain tiny workload: 16 well-mixed cells on a 4x4 square lattice,
+    the 4-species network, dt 0.1, T 10 (100 steps) -- a latency case: each
+    simulation is 100 steps of a handful of events per cell, replayed from
+    captured graphs; events/s and the latency per simulation and per step."""
+    p = W.config1()
+    t = T.Tissue(p, device="cuda:0", stream=torch.cuda.current_stream())
+    t.set_launch(False, 0)
+    t.set_graph_chunk(p["n_steps"])
+    n = p["n_steps"]
+    t.step(p["dt"], n)  # warm-up: the graph capture
+    t.stats()
+    lat, ev = [], 0
+    for k in range(args.tiny_sims):
+        a = time.perf_counter()
+        t.restart(sim_id=k, start_step=0)
+        t.step(p["dt"], n)
+        st = t.stats()
+        lat.append(time.perf_counter() - a)
+        ev += st["chi_events"] + st["s_events"]
+    t.close()
+    return {"workload": "square 4x4 tissue, 16 well-mixed cells, 4 species, 7+1 reactions, "
+                        "dt=0.1, T=10 (100 splitting steps)",
+            "sims": len(lat), "events_per_s": ev / sum(lat),
+            "sim_latency_ms_p50": pct(lat, 50) * 1e3, "sim_latency_ms_p99": pct(lat, 99) * 1e3,
+            "step_latency_us_p50": pct(lat, 50) * 1e6 / n,
+            "launch": "one workgroup per item, one graph of 100 steps; latency includes the "
+                      "restart and the synchronising read of the totals"}
 
 
 def run_serving(args, torch):
@@ -674,14 +811,18 @@ def main():
                     help="steps of the traced pass that measures the busiest cell's event chain (0: skip)")
     ap.add_argument("--dt-replicas", type=int, default=16384)
     ap.add_argument("--dt-T", type=float, default=20.0)
-    ap.add_argument("--leg", choices=["all", "plain", "uneven", "batched", "serving", "dt", "notch",
-                                      "multifidelity", "large"],
+    ap.add_argument("--leg", choices=["all", "plain", "tiny", "uneven", "batched", "serving", "dt",
+                                      "notch", "multifidelity", "large"],
                     default="all",
                     help="run one leg only (profiling runs); the JSON line then carries that leg")
     ap.add_argument("--plain-only", action="store_true", help="same as --leg plain")
     ap.add_argument("--batch-tissues", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=200)
-    ap.add_argument("--batch-reps", type=int, default=1)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--tiny-sims", type=int, default=50)
+    ap.add_argument("--refill", type=int, default=-1,
+                    help="lane refill of compact launches: idle lanes that trigger it (0 off; "
+                         "-1: the library's default)")
     ap.add_argument("--regroup", type=int, default=2,
                     help="regroup cells by load before compact launches (0 off, 1 on, 2 auto)")
     ap.add_argument("--cpu-steps", type=int, default=1200)
@@ -756,6 +897,8 @@ def main():
             "events_per_s": u["value"], "chi_events": u["chi"], "s_events": u["s"],
             "sim_latency_ms_p50": pct(u["lat"], 50) * 1e3,
             "launch": (u["tuned"] or {}).get("config"), "roofline": u["roofline"]}
+    if leg in ("all", "tiny"):
+        out["tiny"] = run_tiny(args, torch, T, W)
     if leg in ("all", "batched"):
         out["batched"] = run_batched(args, torch, T, W)
     if leg == "dt":

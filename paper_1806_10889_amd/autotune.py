@@ -4,10 +4,11 @@ The launch shape -- chi kernel (one lane per cell with a full sum tree, the
 compact layout with one lane per 16 voxels of a cell, or one row of lanes
 per cell), persistent work queue or one workgroup per item, resident workgroups
 per CU, steps per captured HIP graph -- never changes results (every choice
-is bit-identical), only speed.  `tune` times candidate shapes on a clone of
-the workload (the same problems, restarted before each candidate so all see
-the same work), keeps the fastest, caches it on disk under a signature of
-the workload's shape and applies it.
+is bit-identical), only speed.  `tune` times candidate shapes on the
+workload -- a single tissue on the tissue itself, a batch on clones of its
+problems -- restarted before each candidate so that all see the same work,
+keeps the fastest, caches it on disk under a signature of the workload's
+shape and applies it.
 """
 from __future__ import annotations
 

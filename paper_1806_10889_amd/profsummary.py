@@ -4,8 +4,9 @@
 
 For a kernel-trace database: per kernel, calls, total and average duration
 (microseconds) and share of GPU time.  For a counter-collection database: per
-kernel, the number of dispatches and the per-dispatch average of every
-collected counter.
+kernel, the number of dispatches, their average duration in that same run
+(when it was collected with --kernel-trace) and the per-dispatch average of
+every collected counter.
 """
 from __future__ import annotations
 
@@ -29,11 +30,17 @@ def summarise(path: str) -> str:
             disp[k].add(did)
         if agg:
             has_counters = True
-            out.append("kernel | dispatches | per-dispatch average of each counter")
+            dur = {}
+            if "kernels" in tables:
+                for did, d in con.execute("select dispatch_id, duration from kernels"):
+                    dur[did] = d
+            out.append("kernel | dispatches | average_us (same run) | per-dispatch average of each counter")
             for k in sorted(agg, key=lambda k: -len(disp[k])):
                 n = len(disp[k])
+                ds = [dur[d] for d in disp[k] if d in dur]
+                avg_us = f"{sum(ds) / len(ds) / 1e3:.3f}" if ds else "-"
                 vals = ", ".join(f"{c}={agg[k][c] / n:.6g}" for c in sorted(agg[k]))
-                out.append(f"{k} | {n} | {vals}")
+                out.append(f"{k} | {n} | {avg_us} | {vals}")
     if "top_kernels" in tables and not has_counters:
         out.append("kernel | calls | total_us | average_us | percent")
         for name, calls, tot, avg, pctg in con.execute(
