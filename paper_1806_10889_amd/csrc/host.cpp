@@ -212,6 +212,7 @@ struct Plan {
     std::vector<uint32_t> class_start;  // [n_colours + 1] edge ranges per colour
     bool disjoint = true;               // every cell's face groups pairwise disjoint
     bool has_s = false;
+    int face_kind = 0;                  // 2 or 1: every edge has face groups of 2 and 2 (1 and 1) voxels
     std::vector<ChiGroupHost> chi;
     std::vector<std::vector<SItem>> s_passes;
     // the cells' networks: [0] is the descriptor's own (with the S reaction),
@@ -450,9 +451,25 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         p.nedge = (uint32_t)E.size();
         p.edges.resize(E.size());
         p.class_start.assign(ncol + 1, 0);
+        // processing order of the records: with disjoint face groups S is one
+        // pass, and the edges go in the order of their first cell (then
+        // direction), so that the edges around a cell are processed close
+        // together and its counts are fetched into a cache once; otherwise
+        // the colour classes in rank order
+        std::vector<uint32_t> pos(E.size());
+        for (size_t e = 0; e < E.size(); ++e) pos[e] = (uint32_t)e;
+        if (p.disjoint) {
+            std::vector<uint32_t> ord(E.size());
+            for (size_t e = 0; e < E.size(); ++e) ord[e] = (uint32_t)e;
+            std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+                return E[a].i != E[b].i ? E[a].i < E[b].i : E[a].d < E[b].d;
+            });
+            for (size_t k = 0; k < ord.size(); ++k) pos[ord[k]] = (uint32_t)k;
+        }
         for (size_t e = 0; e < E.size(); ++e) {
             const Edge &ed = E[e];
             EdgeRec r{};
+            r.id = (uint32_t)e;
             r.vox_i = p.vox_off[ed.i];
             r.vox_j = p.vox_off[ed.j];
             const auto &gi = faces[p.wh[2 * ed.i] * 16 + p.wh[2 * ed.i + 1]][ed.d];
@@ -465,10 +482,16 @@ int build_plan(const tissue_desc_t *d, Plan &p)
             r.model_j = p.cell_model[ed.j];
             for (size_t q = 0; q < gi.size(); ++q) r.A[q] = (uint8_t)gi[q];
             for (size_t q = 0; q < gj.size(); ++q) r.B[q] = (uint8_t)gj[q];
-            p.edges[e] = r;
+            p.edges[pos[e]] = r;
             p.class_start[ed.colour + 1]++;
         }
         for (int c = 0; c < ncol; ++c) p.class_start[c + 1] += p.class_start[c];
+        p.face_kind = -1;
+        for (const EdgeRec &r : p.edges) {
+            const int k = (r.m_a == 2 && r.m_b == 2) ? 2 : (r.m_a == 1 && r.m_b == 1) ? 1 : 0;
+            p.face_kind = p.face_kind < 0 || p.face_kind == k ? k : 0;
+        }
+        if (p.face_kind < 0) p.face_kind = 0;
         auto cut = [](uint32_t lo, uint32_t hi, std::vector<SItem> &out) {
             for (uint32_t o = lo; o < hi; o += kWave)
                 out.push_back(SItem{0, o, std::min<uint32_t>(kWave, hi - o), 0});
@@ -695,6 +718,7 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
 struct SLaunch {
     const SItem *items;
     uint32_t n_items;
+    int fix;  // 2 or 1: every edge's face groups have 2 and 2 (1 and 1) voxels; else 0
 };
 
 struct GraphKey {
@@ -934,7 +958,7 @@ struct LaunchPlan {
                 // the chi launch shape (its face-count gathers wait on memory,
                 // and many resident workgroups hide that better than a
                 // persistent grid: 2 % on the batched sweep)
-                HIP_TRY(launch_s(L.n_items, st, tbl, L.items, L.n_items, queue, 0, dt, (uint32_t)k));
+                HIP_TRY(launch_s(L.n_items, st, tbl, L.items, L.n_items, queue, 0, dt, (uint32_t)k, L.fix));
                 if (ev) {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
                     kind->push_back(-1);
@@ -1253,7 +1277,8 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     L.chi_items_cap = p.n_chi_items;
     size_t off = 0;
     for (auto &ps : p.s_passes) {
-        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(base + p.off_s) + off, (uint32_t)ps.size()});
+        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(base + p.off_s) + off, (uint32_t)ps.size(),
+                              p.face_kind});
         off += ps.size();
     }
     rc = L.set_chi_mode(kModeAuto);
@@ -1486,6 +1511,7 @@ struct BatchLayout {
     size_t off_tbl = 0, off_queue = 0, off_lq = 0, off_chi = 0, off_s = 0, off_retry = 0, bytes = 0;
     size_t chi_cap = 0;
     std::vector<std::vector<SItem>> s_passes;
+    std::vector<int> s_fix;  // per pass: the face-group kind shared by every member in it, or 0
 };
 
 int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
@@ -1514,9 +1540,12 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
         max_pass = std::max(max_pass, p.disjoint ? 1 : (int)p.class_start.size() - 1);
     }
     B.s_passes.assign(max_pass, {});
+    B.s_fix.assign(max_pass, -1);
     for (int32_t i = 0; i < n; ++i) {
         const Plan &p = ts[i]->plan;
         if (!p.has_s || p.nedge == 0) continue;
+        for (int c = 0; c < (p.disjoint ? 1 : (int)p.class_start.size() - 1); ++c)
+            B.s_fix[c] = B.s_fix[c] < 0 || B.s_fix[c] == p.face_kind ? p.face_kind : 0;
         auto cut = [&](uint32_t lo, uint32_t hi, std::vector<SItem> &out) {
             for (uint32_t o = lo; o < hi; o += kWave)
                 out.push_back(SItem{(uint32_t)i, o, std::min<uint32_t>(kWave, hi - o), 0});
@@ -1528,6 +1557,7 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
                 cut(p.class_start[c], p.class_start[c + 1], B.s_passes[c]);
         }
     }
+    for (int &f : B.s_fix) f = std::max(f, 0);
     size_t n_s = 0;
     for (auto &ps : B.s_passes) n_s += ps.size();
     size_t o = 0;
@@ -1605,7 +1635,8 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     L.chi_items_cap = B.chi_cap;
     size_t off = 0;
     for (auto &ps : B.s_passes) {
-        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(b->dev + B.off_s) + off, (uint32_t)ps.size()});
+        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(b->dev + B.off_s) + off, (uint32_t)ps.size(),
+                              B.s_fix[(size_t)(&ps - B.s_passes.data())]});
         off += ps.size();
     }
     rc = L.set_chi_mode(kModeAuto);
@@ -1808,7 +1839,8 @@ int tissue_batch_step_static(tissue_t *const *ts, int32_t n, double dt, int32_t 
     L.chi = std::move(launches);
     size_t soff = 0;
     for (auto &ps : B.s_passes) {
-        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(ws + off_s) + soff, (uint32_t)ps.size()});
+        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(ws + off_s) + soff, (uint32_t)ps.size(),
+                              B.s_fix[(size_t)(&ps - B.s_passes.data())]});
         soff += ps.size();
     }
     rc = L.run(dt, n_steps);

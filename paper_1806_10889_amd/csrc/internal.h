@@ -43,6 +43,9 @@ struct DevModel {
 
 // One lattice edge (i < j) and the facing membrane groups A of cell i and
 // B of cell j; the voxel offsets locate the two cells in the counts array.
+// Records are stored in the order the S operator processes them, which need
+// not be the edges' rank: `id` is the edge's rank in (colour, i) order, the
+// edge's index in every random counter and trace.
 struct EdgeRec {
     int32_t vox_i;         // first voxel of cell i (global voxel index)
     int32_t vox_j;
@@ -50,8 +53,9 @@ struct EdgeRec {
     uint8_t model_i, model_j;  // the two cells' networks (first-order signalling rates)
     uint8_t A[kMaxFace];
     uint8_t B[kMaxFace];
+    uint32_t id;
 };
-static_assert(sizeof(EdgeRec) == 28, "EdgeRec layout");
+static_assert(sizeof(EdgeRec) == 32, "EdgeRec layout");
 
 struct DevTissue {
     int32_t *counts;              // [n_voxels][n_species], cell order, v = y*w + x

@@ -21,6 +21,16 @@ namespace tissue_impl {
 // ---------------------------------------------------------------------------
 namespace {
 
+// Workgroup b of n, dealt to XCD b mod 8, takes item x q + min(x, r) + b / 8
+// (x = b mod 8, q = n / 8, r = n mod 8): each XCD gets one contiguous range
+// of the items (a bijection on 0..n-1).
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n)
+{
+    constexpr uint32_t kXcds = 8;
+    const uint32_t x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + min(x, r) + k;
+}
+
 // The SSA of one edge over dt for face groups of MA and MB voxels known at
 // compile time: the counts in registers, every channel loop unrolled, the
 // same operations in the same order as the general path below (so the same
@@ -169,6 +179,10 @@ __device__ __forceinline__ void s_edge_fixed(int32_t *counts, long long gi, long
 
 }  // namespace
 
+// FIX = 2 or 1: every edge of the launch has face groups of FIX and FIX
+// voxels (counts in registers only: no LDS, fewer registers, more resident
+// wavefronts); FIX = 0: any sizes, the general path in LDS for the others.
+template <int FIX>
 __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, const SItem *items,
                                                   uint32_t n_items, uint32_t *queue,
                                                   int persistent, double dt, uint32_t kstep)
@@ -177,7 +191,10 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
     __shared__ int32_t fa[3][kMaxFace][kWave];
     __shared__ int32_t fb[3][kMaxFace][kWave];
     const int lane = threadIdx.x;
-    uint32_t cursor = blockIdx.x;
+    // one workgroup per item: consecutive items on one XCD (workgroups are
+    // dealt to the XCDs in turn), so that the edges around a cell share that
+    // XCD's L2
+    uint32_t cursor = persistent ? blockIdx.x : xcd_contiguous(blockIdx.x, gridDim.x);
     for (;;) {
         const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
@@ -196,12 +213,12 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
         const uint32_t cap = uni(T->event_cap);
         int32_t *counts = T->counts;
         const bool active = lane < (int)count;
-        const uint32_t e = first + lane;
         double t = 0.0;
-        uint32_t j = 0, ev = 0;
+        uint32_t j = 0, ev = 0, e = 0;
         bool overflow = false, capped = false;
         if (active) {
-            const EdgeRec *er = T->edges + e;
+            const EdgeRec *er = T->edges + (first + lane);
+            e = er->id;  // the edge's rank: its counters and trace slot
             const int mA = er->m_a, mB = er->m_b;
             // first order: each side's molecules signal at their own
             // cell's network's rate (the tissue's rate without per-cell models)
@@ -216,7 +233,7 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
             }
             // face groups of 2 and 2 voxels (4x4 cells on the hexagonal
             // lattice) and of 1 and 1 (well-mixed cells): counts in registers
-            const int fixed = (mA == 2 && mB == 2) ? 2 : (mA == 1 && mB == 1) ? 1 : 0;
+            const int fixed = FIX ? FIX : (mA == 2 && mB == 2) ? 2 : (mA == 1 && mB == 1) ? 1 : 0;
             if (fixed == 2)
                 s_edge_fixed<2, 2>(counts, gi, gj, A, B, S, sp0, sp1, sp2, first_order, c, ci, cj, dt,
                                    step, e, tagword, key0, key1, cap, t, j, ev, overflow, capped);
@@ -515,10 +532,17 @@ hipError_t launch_chi(int SM, int RM, int NDM, const ChiArgs &a)
 
 hipError_t launch_s(uint32_t grid, hipStream_t stream, const DevTissue *const *tbl,
                     const SItem *items, uint32_t n_items, uint32_t *queue, int persistent,
-                    double dt, uint32_t kstep)
+                    double dt, uint32_t kstep, int fix)
 {
-    hipLaunchKernelGGL(s_kernel, dim3(grid), dim3(kWave), 0, stream, tbl, items, n_items, queue,
-                       persistent, dt, kstep);
+    if (fix == 2)
+        hipLaunchKernelGGL(s_kernel<2>, dim3(grid), dim3(kWave), 0, stream, tbl, items, n_items,
+                           queue, persistent, dt, kstep);
+    else if (fix == 1)
+        hipLaunchKernelGGL(s_kernel<1>, dim3(grid), dim3(kWave), 0, stream, tbl, items, n_items,
+                           queue, persistent, dt, kstep);
+    else
+        hipLaunchKernelGGL(s_kernel<0>, dim3(grid), dim3(kWave), 0, stream, tbl, items, n_items,
+                           queue, persistent, dt, kstep);
     return hipGetLastError();
 }
 
