@@ -403,32 +403,33 @@ def run_tiny(args, torch, T, W):
                       "restart and the synchronising read of the totals"}
 
 
-def run_serving(args, torch):
+def run_serving(args, torch, budget_bytes=None, n_requests=None):
     """Config-5-shaped serving: Poisson arrivals replayed in real time,
-    continuous batching with HBM-budgeted admission; latency = arrival to
+    continuous batching with HBM-budgeted admission (the device's free
+    memory less a margin, unless a budget is given); latency = arrival to
     result in host memory."""
     from paper_1806_10889_amd import serve
-    reqs = serve.requests_from_workload(args.serve_requests + args.serve_warmup,
-                                        rate_hz=args.serve_rate)
+    n_req = args.serve_requests if n_requests is None else n_requests
+    reqs = serve.requests_from_workload(n_req + args.serve_warmup, rate_hz=args.serve_rate)
     log(f"serving: {len(reqs)} requests generated")
     # compile the requests' network before the clock starts (the runtime
     # compiles each network structure once per process, on first use)
     from paper_1806_10889_amd import tissue as T
     T.Tissue(reqs[0].problem, device="cuda:0").close()
     be = serve.GpuBackend(lanes=args.serve_lanes, regroup=args.regroup)
-    free, _ = torch.cuda.mem_get_info()
-    budget = int(min(args.serve_hbm_gib * (1 << 30), 0.5 * free))
-    srv = serve.Server(be, max_bytes=budget, max_active=args.serve_slots, quantum=args.serve_quantum)
+    srv = serve.Server(be, max_bytes=budget_bytes, max_active=args.serve_slots,
+                       quantum=args.serve_quantum, margin_bytes=args.serve_margin_gib << 30)
     st, done = srv.run(reqs, real_time=True)
-    measured = [r for r in done if r.rid >= args.serve_warmup]
+    measured = [r for r in done if r.rid >= args.serve_warmup and r.status == "done"]
     lat = sorted(r.finished - r.arrival for r in measured)
     ev = sum(r.events for r in measured)
     span = max(r.finished for r in measured) - min(r.arrival for r in measured)
     out = st.summary()
     out.update({"measured_requests": len(measured), "warmup_requests": args.serve_warmup,
                 "offered_rate_hz": args.serve_rate, "quantum_steps": args.serve_quantum,
-                "lanes": args.serve_lanes,
-                "hbm_budget_bytes": budget,
+                "lanes": args.serve_lanes, "batch_rebuilds": be.rebuilds,
+                "budget": "device free memory less a margin" if budget_bytes is None
+                          else f"{budget_bytes} bytes",
                 "measured_req_per_s": len(measured) / span, "measured_events_per_s": ev / span,
                 "measured_latency_ms_p50": pct(lat, 50) * 1e3,
                 "measured_latency_ms_p99": pct(lat, 99) * 1e3})
@@ -838,7 +839,11 @@ def main():
     ap.add_argument("--serve-quantum", type=int, default=10)
     ap.add_argument("--serve-slots", type=int, default=4096)
     ap.add_argument("--serve-lanes", type=int, default=4)
-    ap.add_argument("--serve-hbm-gib", type=float, default=64.0)
+    ap.add_argument("--serve-margin-gib", type=int, default=8,
+                    help="serving budget: the device's free memory less this margin")
+    ap.add_argument("--serve-bound-mib", type=int, default=48,
+                    help="the budget of the second serving run, one that binds (0: skip it)")
+    ap.add_argument("--serve-bound-requests", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
@@ -911,6 +916,9 @@ def main():
         out["large_cells"] = run_large_cells(args, torch, T, W)
     if leg == "serving" or (leg == "all" and not args.no_serve):
         out["serving"] = run_serving(args, torch)
+        if args.serve_bound_mib > 0:
+            out["serving_bound_budget"] = run_serving(args, torch, budget_bytes=args.serve_bound_mib << 20,
+                                                      n_requests=args.serve_bound_requests)
     if leg == "all" and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, W, plain["p"])
     print(json.dumps(out), flush=True)

@@ -338,6 +338,19 @@ int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph);
 int tissue_batch_set_regroup(tissue_batch_t *b, int32_t mode);
 int tissue_batch_set_refill(tissue_batch_t *b, int32_t min_idle_lanes);
 int tissue_batch_sync(tissue_batch_t *b);
+/* Replace the batch's members in place (continuous batching: admit and
+ * retire tissues between steps) without creating a new batch: the work
+ * lists are planned again on the host and copied into the batch's buffer
+ * on its stream, with no host synchronisation (the host waits only for the
+ * previous set_members copy to have left its pinned staging memory).
+ * n = 0 empties the batch (its steps then do nothing).  New members on other
+ * streams are waited for by the batch's stream; members that leave wait, on
+ * their own stream, for the batch's work so far, so that they can be
+ * destroyed next.  The same rules as tissue_batch_create (TISSUE_EINVAL,
+ * nothing changed); TISSUE_EBUSY, nothing changed, when the members' work
+ * lists need more than the dev_bytes the batch was created with (retry
+ * after members have left, or create a larger batch). */
+int tissue_batch_set_members(tissue_batch_t *b, tissue_t *const *ts, int32_t n);
 int tissue_batch_destroy(tissue_batch_t *b);
 
 /*

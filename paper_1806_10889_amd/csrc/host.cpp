@@ -1113,6 +1113,7 @@ struct tissue {
     DevTissue host_rec{};          // last uploaded DevTissue (host copy)
     uint32_t steps_done = 0;
     int batches = 0;               // live batches holding this tissue
+    hipEvent_t ready = nullptr;    // marks the tissue's stream for batches on other streams
     LaunchPlan lp;
     DevTissue *d_rec() const { return reinterpret_cast<DevTissue *>(dev + plan.off_tissue); }
     int32_t *d_counts() const { return reinterpret_cast<int32_t *>(dev + plan.off_counts); }
@@ -1122,7 +1123,18 @@ struct tissue {
 struct tissue_batch {
     std::vector<tissue *> members;
     unsigned char *dev = nullptr;
+    size_t bytes = 0;                 // dev_buf's size: the capacity of set_members
     LaunchPlan lp;
+    // set_members: the image of the work lists in pinned host memory (grown
+    // on demand) and the event after its last copy
+    unsigned char *stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t staged = nullptr;
+    ~tissue_batch()
+    {
+        if (staged) (void)hipEventDestroy(staged);
+        if (stage) (void)hipHostFree(stage);
+    }
 };
 
 extern "C" {
@@ -1497,6 +1509,7 @@ int tissue_destroy(tissue_t *t)
         return fail(TISSUE_ESTATE, "tissue is a member of " + std::to_string(t->batches) +
                                        " live batch(es); destroy them first");
     (void)hipStreamSynchronize(t->stream);
+    if (t->ready) (void)hipEventDestroy(t->ready);
     delete t;
     return TISSUE_OK;
 }
@@ -1603,6 +1616,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     std::unique_ptr<tissue_batch> b(new tissue_batch());
     b->members.assign(ts, ts + n);
     b->dev = static_cast<unsigned char *>(dev_buf);
+    b->bytes = dev_bytes;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     for (int32_t i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(ts[i]->stream));
     std::vector<DevTissue *> tbl(n);
@@ -1646,6 +1660,101 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     return TISSUE_OK;
 }
 
+int tissue_batch_set_members(tissue_batch_t *b, tissue_t *const *ts, int32_t n)
+{
+    if (!b) return fail(TISSUE_EINVAL, "null batch");
+    if (n < 0 || (n > 0 && !ts)) return fail(TISSUE_EINVAL, "bad member list");
+    BatchLayout B;
+    if (n > 0) {
+        const int rc = plan_batch(ts, n, B);
+        if (rc != TISSUE_OK) return rc;
+        if (B.bytes > b->bytes)
+            return fail(TISSUE_EBUSY, "the batch's buffer holds " + std::to_string(b->bytes) +
+                                          " bytes; these members need " + std::to_string(B.bytes));
+    }
+    LaunchPlan &L = b->lp;
+    std::vector<const Plan *> plans;
+    for (int32_t i = 0; i < n; ++i) plans.push_back(&ts[i]->plan);
+    std::vector<ChiItem> items;
+    std::vector<ChiLaunch> launches;
+    if (n > 0) plan_chi(plans, L.chi_mode, L.regroup, L.cus * 4, items, launches);
+    if (launches.size() > (size_t)kMaxChiLaunches) return fail(TISSUE_EINVAL, "too many chi launch groups");
+    std::vector<SItem> s_all;
+    for (auto &ps : B.s_passes) s_all.insert(s_all.end(), ps.begin(), ps.end());
+
+    // the image up to the end of the S items (member table, cleared queue
+    // words, chi and S items), copied on the batch's stream after the
+    // previous image's copy has left the staging memory
+    const size_t up = n > 0 ? B.off_s + s_all.size() * sizeof(SItem) : 0;
+    if (!b->staged) HIP_TRY(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
+    HIP_TRY(hipEventSynchronize(b->staged));
+    if (up > b->stage_cap) {
+        // once, for the whole buffer: the image never outgrows it (pinned
+        // allocation and release can wait for the whole device)
+        if (b->stage) HIP_TRY(hipHostFree(b->stage));
+        b->stage = nullptr;
+        b->stage_cap = 0;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&b->stage), b->bytes, hipHostMallocDefault));
+        b->stage_cap = b->bytes;
+    }
+    hipStream_t st = L.stream;
+    if (n > 0) {
+        unsigned char *h = b->stage;
+        for (int32_t i = 0; i < n; ++i) {
+            DevTissue *rec = ts[i]->d_rec();
+            std::memcpy(h + B.off_tbl + (size_t)i * sizeof(DevTissue *), &rec, sizeof(rec));
+        }
+        std::memset(h + B.off_queue, 0, B.off_chi - B.off_queue);
+        if (!items.empty()) std::memcpy(h + B.off_chi, items.data(), items.size() * sizeof(ChiItem));
+        if (!s_all.empty()) std::memcpy(h + B.off_s, s_all.data(), s_all.size() * sizeof(SItem));
+        // members on other streams: the batch's stream waits for their work so far
+        for (int32_t i = 0; i < n; ++i)
+            if (ts[i]->stream != st) {
+                if (!ts[i]->ready) HIP_TRY(hipEventCreateWithFlags(&ts[i]->ready, hipEventDisableTiming));
+                HIP_TRY(hipEventRecord(ts[i]->ready, ts[i]->stream));
+                HIP_TRY(hipStreamWaitEvent(st, ts[i]->ready, 0));
+            }
+        HIP_TRY(hipMemcpyAsync(b->dev, h, up, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipEventRecord(b->staged, st));
+    }
+
+    L.clear_graphs();
+    L.tbl = reinterpret_cast<DevTissue **>(b->dev + B.off_tbl);
+    L.n_tissues = (uint32_t)n;
+    L.queue = reinterpret_cast<uint32_t *>(b->dev + B.off_queue);
+    L.lq = reinterpret_cast<uint32_t *>(b->dev + B.off_lq);
+    L.members = plans;
+    L.strang = n > 0 ? ts[0]->plan.strang : L.strang;
+    L.retry_items = reinterpret_cast<ChiItem *>(b->dev + B.off_retry);
+    L.chi_items = reinterpret_cast<ChiItem *>(b->dev + B.off_chi);
+    L.chi_items_cap = B.chi_cap;
+    for (ChiLaunch &c : launches) {
+        c.items = L.chi_items + reinterpret_cast<uintptr_t>(c.items);
+        if (c.n_segs) c.segs = L.chi_items + reinterpret_cast<uintptr_t>(c.segs);
+    }
+    L.chi = std::move(launches);
+    L.s.clear();
+    size_t off = 0;
+    for (auto &ps : B.s_passes) {
+        L.s.push_back(SLaunch{reinterpret_cast<const SItem *>(b->dev + B.off_s) + off, (uint32_t)ps.size(),
+                              B.s_fix[(size_t)(&ps - B.s_passes.data())]});
+        off += ps.size();
+    }
+    // members that leave: their own stream waits for the batch's work so far,
+    // so that destroying them (which synchronises their stream) also waits
+    // for the batch's steps that still read their state
+    for (tissue *t : b->members) {
+        if (std::find(ts, ts + n, t) != ts + n || t->stream == st) continue;
+        if (!t->ready) HIP_TRY(hipEventCreateWithFlags(&t->ready, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(t->ready, st));
+        HIP_TRY(hipStreamWaitEvent(t->stream, t->ready, 0));
+    }
+    for (tissue *t : b->members) t->batches--;
+    b->members.assign(ts, ts + n);
+    for (tissue *t : b->members) t->batches++;
+    return TISSUE_OK;
+}
+
 static int batch_check(tissue_batch_t *b, double dt, int32_t n_steps)
 {
     if (!b) return fail(TISSUE_EINVAL, "null batch");
@@ -1660,7 +1769,7 @@ static int batch_check(tissue_batch_t *b, double dt, int32_t n_steps)
 int tissue_batch_step(tissue_batch_t *b, double dt, int32_t n_steps)
 {
     int rc = batch_check(b, dt, n_steps);
-    if (rc != TISSUE_OK || n_steps == 0) return rc;
+    if (rc != TISSUE_OK || n_steps == 0 || b->members.empty()) return rc;
     rc = b->lp.run(dt, n_steps);
     if (rc == TISSUE_OK)
         for (tissue *t : b->members) t->steps_done += (uint32_t)n_steps;
@@ -1671,6 +1780,10 @@ int tissue_batch_step_timed(tissue_batch_t *b, double dt, int32_t n_steps, tissu
 {
     int rc = batch_check(b, dt, n_steps);
     if (rc != TISSUE_OK) return rc;
+    if (b->members.empty()) {
+        if (out) *out = tissue_timing_t{};
+        return TISSUE_OK;
+    }
     rc = b->lp.run_timed(dt, n_steps, out);
     if (rc == TISSUE_OK)
         for (tissue *t : b->members) t->steps_done += (uint32_t)n_steps;

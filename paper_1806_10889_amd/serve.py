@@ -36,6 +36,10 @@ from dataclasses import dataclass, field
 import numpy as np
 
 
+# submission results, the library's codes (include/tissue.h)
+OK, EINVAL, EBUSY = 0, -1, -5
+
+
 @dataclass
 class Request:
     rid: int
@@ -50,6 +54,10 @@ class Request:
     result: object = None
     events: int = 0
     lane: int = 0
+    status: str = "pending"        # then "waiting", "active", and at the end
+                                   # "done", "cancelled", "failed" or "rejected"
+    error: str = ""
+    cancel_requested: bool = False
 
 
 @dataclass
@@ -62,6 +70,11 @@ class ServeStats:
     max_bytes: int = 0
     ticks: int = 0
     lanes: int = 1
+    cancelled: int = 0
+    failed: int = 0
+    rejected: int = 0
+    busy_retries: int = 0
+    budget_bytes: int = 0
     latencies: list = field(default_factory=list)
     queue_waits: list = field(default_factory=list)
 
@@ -82,7 +95,10 @@ class ServeStats:
             "latency_ms_p99": None if not lat else pct(99) * 1e3,
             "latency_ms_mean": None if not lat else 1e3 * sum(lat) / len(lat),
             "max_active": self.max_active, "mean_active": self.mean_active,
-            "max_hbm_bytes": self.max_bytes, "ticks": self.ticks, "lanes": self.lanes,
+            "max_hbm_bytes": self.max_bytes, "budget_bytes": self.budget_bytes,
+            "ticks": self.ticks, "lanes": self.lanes,
+            "cancelled": self.cancelled, "failed": self.failed, "rejected": self.rejected,
+            "busy_retries": self.busy_retries,
         }
 
 
@@ -116,22 +132,48 @@ class Server:
       all handles by n steps, asynchronously allowed; `finishing` are the
       handles whose last step this is, whose totals events() will report),
       busy(lane) (the lane's last step still running), sync(lane),
-      events(handle), read(handle), free(lane, handle).
-    max_bytes: HBM budget for resident tissues; max_active: slot count over
-    all lanes; quantum: steps per tick.  Requests go to lanes by the rank of
-    chain_estimate among the requests seen so far (one lane: all).
+      events(handle), read(handle), and retire(lane, handles) (release
+      finished or abandoned requests; free(lane, handle) for one at a time
+      where there is no retire), and optionally free_bytes() (device memory
+      free now).
+    max_bytes: HBM budget for resident tissues; None: the backend's free
+      memory at start minus margin_bytes.  max_active: slot count over all
+      lanes; quantum: steps per tick.  max_waiting: bound on admitted-but-
+      waiting requests, beyond which submit() answers EBUSY (None: no
+      bound).  tick_deadline_s: a lane's tick still running after this long
+      fails the requests in it (they are released when the tick ends; the
+      loop goes on; None: no deadline).  Requests go to lanes by the rank
+      of chain_estimate among the requests seen so far (one lane: all).
     """
 
-    def __init__(self, backend, max_bytes: int, max_active: int = 4096, quantum: int = 10,
-                 clock=time.perf_counter, keep_results: bool = False):
+    def __init__(self, backend, max_bytes=None, max_active: int = 4096, quantum: int = 10,
+                 clock=time.perf_counter, keep_results: bool = False, max_waiting=None,
+                 tick_deadline_s=None, margin_bytes: int = 1 << 30, sleep=time.sleep):
         self.backend = backend
+        if max_bytes is None:
+            max_bytes = max(0, int(backend.free_bytes()) - int(margin_bytes))
         self.max_bytes = int(max_bytes)
         self.max_active = int(max_active)
         self.quantum = int(quantum)
         self.clock = clock
+        self.sleep = sleep
         self.keep_results = keep_results
+        self.max_waiting = max_waiting
+        self.tick_deadline_s = tick_deadline_s
         self.lanes = max(1, int(getattr(backend, "lanes", 1)))
         self._seen: list = []
+        self._reset()
+
+    def _reset(self):
+        K = self.lanes
+        self.waiting = [[] for _ in range(K)]   # per lane: (arrival, rid, req)
+        self.active = [[] for _ in range(K)]
+        self.by_id = {}
+        self.n_waiting = 0
+        self.done: list[Request] = []
+        self.st = ServeStats(lanes=K, budget_bytes=self.max_bytes)
+        self.used = 0
+        self.n_active = 0
 
     def _route(self, r: Request) -> int:
         if self.lanes == 1:
@@ -141,20 +183,80 @@ class Server:
         bisect.insort(self._seen, e)
         return min(self.lanes - 1, int(rank * self.lanes))
 
-    def run(self, requests, real_time: bool = True) -> tuple[ServeStats, list]:
-        """Serve `requests` (sorted by arrival).  With real_time, arrivals are
-        replayed against the wall clock (a request cannot be admitted before
-        its arrival time); otherwise the clock is virtual: it advances by the
-        measured time of each pass of the loop and jumps over idle gaps."""
-        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    def _end(self, r: Request, status: str, when: float, error: str = ""):
+        r.status, r.error, r.finished = status, error, when
+        if status == "cancelled":
+            self.st.cancelled += 1
+        elif status == "failed":
+            self.st.failed += 1
+        elif status == "rejected":
+            self.st.rejected += 1
+        self.done.append(r)
+
+    def submit(self, r: Request, now: float = 0.0) -> int:
+        """Queue a request for admission.  EINVAL: it can never fit the budget
+        (ended as "rejected"); EBUSY: the waiting queue is full -- retry
+        later; OK: queued."""
+        need = self.backend.required_bytes(r.problem)
+        if need > self.max_bytes:
+            self._end(r, "rejected", now, f"needs {need} B, over the whole budget of {self.max_bytes} B")
+            return EINVAL
+        if self.max_waiting is not None and self.n_waiting >= self.max_waiting:
+            return EBUSY
+        r.bytes = need
+        r.lane = self._route(r)
+        r.status = "waiting"
+        heapq.heappush(self.waiting[r.lane], (r.arrival, r.rid, r))
+        self.n_waiting += 1
+        self.by_id[r.rid] = r
+        return OK
+
+    def cancel(self, rid: int, now: float = 0.0) -> bool:
+        """Cancel a submitted request: a waiting one leaves the queue at
+        once, an active one is released when its lane's tick ends."""
+        r = self.by_id.get(rid)
+        if r is None or r.status not in ("waiting", "active"):
+            return False
+        if r.status == "waiting":
+            self.waiting[r.lane] = [e for e in self.waiting[r.lane] if e[2] is not r]
+            heapq.heapify(self.waiting[r.lane])
+            self.n_waiting -= 1
+            self._end(r, "cancelled", now)
+        else:
+            r.cancel_requested = True
+        return True
+
+    def _retire(self, L: int, rs):
+        if not rs:
+            return
+        hs = [r.handle for r in rs]
+        if hasattr(self.backend, "retire"):
+            self.backend.retire(L, hs)
+        else:
+            for h in hs:
+                self.backend.free(L, h)
+        for r in rs:
+            r.handle = None
+            self.used -= r.bytes
+            self.n_active -= 1
+
+    def run(self, requests, real_time: bool = True, cancels=(), busy_retry_s: float = 0.005):
+        """Serve `requests` (by arrival time).  With real_time, arrivals are
+        replayed against the clock (a request cannot be admitted before its
+        arrival time); otherwise the clock is virtual: it advances by the
+        measured time of each pass of the loop and jumps over idle gaps.
+        cancels: (time, rid) pairs, each cancelling that request at that
+        time.  A submission answered EBUSY is tried again busy_retry_s
+        later (its latency still counts from its arrival)."""
+        self._reset()
+        every = {r.rid: r for r in requests}
+        pending = sorted(((r.arrival, r.rid, r) for r in requests), key=lambda e: e[:2])
+        heapq.heapify(pending)
+        cancel_q = sorted(cancels)
         K = self.lanes
-        waiting = [[] for _ in range(K)]   # per lane: (arrival, rid, req)
-        active = [[] for _ in range(K)]
         inflight = [0] * K                 # steps of the running tick (0: idle)
-        done: list[Request] = []
-        st = ServeStats(lanes=K)
-        used = 0
-        n_active = 0
+        started = [0.0] * K                # when it was launched
+        st = self.st
         t0 = self.clock()
         vt = 0.0
         last = t0
@@ -163,111 +265,136 @@ class Server:
         def now():
             return (self.clock() - t0) if real_time else vt
 
-        while pending or any(waiting) or n_active:
+        while pending or self.n_waiting or self.n_active or any(inflight):
             if not real_time:
                 c = self.clock()
                 vt += c - last
                 last = c
-            while pending and pending[0].arrival <= now():
-                r = pending.popleft()
-                r.lane = self._route(r)
-                heapq.heappush(waiting[r.lane], (r.arrival, r.rid, r))
+            while pending and pending[0][0] <= now():
+                when, rid, r = heapq.heappop(pending)
+                if r.cancel_requested:  # cancelled before it was submitted
+                    self._end(r, "cancelled", now())
+                    continue
+                rc = self.submit(r, now())
+                if rc == EBUSY:
+                    st.busy_retries += 1
+                    heapq.heappush(pending, (now() + busy_retry_s, rid, r))
+            while cancel_q and cancel_q[0][0] <= now():
+                _, rid = cancel_q.pop(0)
+                if not self.cancel(rid, now()) and rid in every and every[rid].status == "pending":
+                    every[rid].cancel_requested = True
             progressed = False
             for L in range(K):
                 if inflight[L]:
                     if self.backend.busy(L):
+                        if (self.tick_deadline_s is not None and
+                                now() - started[L] > self.tick_deadline_s):
+                            for r in self.active[L]:
+                                if r.status == "active":
+                                    r.status = "failing"
+                                    r.error = f"tick over its deadline of {self.tick_deadline_s} s"
                         continue
                     # the lane's tick has finished: account for it
                     q = inflight[L]
                     inflight[L] = 0
                     progressed = True
                     end = now()
-                    still = []
-                    for r in active[L]:
+                    still, leave = [], []
+                    for r in self.active[L]:
                         r.steps_done += q
-                        if r.steps_done >= r.n_steps:
+                        if r.status == "failing":
+                            leave.append(r)
+                            self._end(r, "failed", end, r.error)
+                        elif r.cancel_requested:
+                            leave.append(r)
+                            self._end(r, "cancelled", end)
+                        elif r.steps_done >= r.n_steps:
                             r.events = self.backend.events(r.handle)
                             if self.keep_results:
                                 r.result = self.backend.read(r.handle)
-                            self.backend.free(L, r.handle)
-                            r.handle = None
-                            used -= r.bytes
-                            n_active -= 1
-                            r.finished = end
+                            leave.append(r)
+                            self._end(r, "done", end)
                             st.completed += 1
                             st.events += r.events
                             st.latencies.append(r.finished - r.arrival)
                             st.queue_waits.append(r.admitted - r.arrival)
-                            done.append(r)
                         else:
                             still.append(r)
-                    active[L] = still
+                    self._retire(L, leave)
+                    self.active[L] = still
                 # admission into this lane: oldest first, by slots and HBM
-                while waiting[L] and n_active < self.max_active:
-                    r = waiting[L][0][2]
-                    need = self.backend.required_bytes(r.problem)
-                    if need > self.max_bytes:
-                        raise ValueError(f"request {r.rid} needs {need} B, over the whole budget")
-                    if used + need > self.max_bytes:
+                while self.waiting[L] and self.n_active < self.max_active:
+                    r = self.waiting[L][0][2]
+                    if self.used + r.bytes > self.max_bytes:
                         break
-                    heapq.heappop(waiting[L])
-                    r.bytes = need
+                    heapq.heappop(self.waiting[L])
+                    self.n_waiting -= 1
                     r.handle = self.backend.create(r.problem, L)
                     r.admitted = now()
-                    used += need
-                    n_active += 1
-                    active[L].append(r)
+                    r.status = "active"
+                    self.used += r.bytes
+                    self.n_active += 1
+                    self.active[L].append(r)
                     progressed = True
-                if active[L]:
-                    q = min([self.quantum] + [r.n_steps - r.steps_done for r in active[L]])
+                if self.active[L]:
+                    q = min([self.quantum] + [r.n_steps - r.steps_done for r in self.active[L]])
                     by_dt = collections.defaultdict(list)
                     ending = collections.defaultdict(list)
-                    for r in active[L]:
+                    for r in self.active[L]:
                         by_dt[r.problem["dt"]].append(r.handle)
                         if r.steps_done + q >= r.n_steps:
                             ending[r.problem["dt"]].append(r.handle)
                     for d, hs in by_dt.items():
                         self.backend.step(L, hs, d, q, ending[d])
                     inflight[L] = q
+                    started[L] = now()
                     st.ticks += 1
-                    active_sum += n_active
+                    active_sum += self.n_active
                     progressed = True
-            st.max_active = max(st.max_active, n_active)
-            st.max_bytes = max(st.max_bytes, used)
+            st.max_active = max(st.max_active, self.n_active)
+            st.max_bytes = max(st.max_bytes, self.used)
             if progressed:
                 continue
             if not any(inflight):
                 # idle: wait for the next arrival
                 if not pending:
-                    break
+                    if not self.n_waiting:
+                        break
+                    continue
                 if real_time:
-                    delay = pending[0].arrival - now()
+                    delay = pending[0][0] - now()
                     if delay > 0:
-                        time.sleep(min(delay, 0.05))
+                        self.sleep(min(delay, 0.05))
                 else:
-                    vt = max(vt, pending[0].arrival)
+                    vt = max(vt, pending[0][0])
                     last = self.clock()
             else:
                 # the device is busy: wait a little for a lane to finish
-                time.sleep(2e-4)
+                self.sleep(2e-4)
         st.wall_s = now()
         st.mean_active = active_sum / st.ticks if st.ticks else 0.0
-        return st, done
+        return st, self.done
 
 
 class GpuBackend:
     """The C-ABI library as a serving backend: one Tissue per request (its
-    own device buffer), per lane one stream and one Batch per distinct
-    active set, rebuilt only when the set changes.
+    own device buffer), per lane one stream and one Batch whose members are
+    replaced in place (tissue_batch_set_members: the work lists are planned
+    again and copied on the lane's stream, with no host synchronisation and
+    no new batch) as requests are admitted and retired.  A lane's batch is
+    created at its first admission with a work-list buffer of
+    `lane_capacity_bytes`, and made again, larger, only when a member set
+    outgrows it (set_members answers EBUSY).
 
     Each lane needs a hardware queue of its own: HIP maps streams onto
     GPU_MAX_HW_QUEUES queues (4 by default, set before the runtime starts),
     and a lane sharing a queue waits behind the other lane's kernels in
-    every synchronisation (creation, batch rebuild), which the loop cannot
-    hide.  Use a queue count of at least the lanes plus two."""
+    every synchronisation (creation), which the loop cannot hide.  Use a
+    queue count of at least the lanes plus two."""
 
     def __init__(self, device="cuda:0", lanes: int = 4, graph_chunk: int = 0,
-                 persistent: bool = False, max_slots: int = 8192, regroup: int = 2):
+                 persistent: bool = False, max_slots: int = 8192, regroup: int = 2,
+                 lane_capacity_bytes: int = 32 << 20):
         import os
         import warnings
 
@@ -290,16 +417,21 @@ class GpuBackend:
         # every CU until its slowest item is done)
         self.persistent = bool(persistent)
         self.regroup = int(regroup)  # the load-ordered regroup before compact launches
+        self.capacity = int(lane_capacity_bytes)
         self._batch = [None] * self.lanes
-        self._key = [None] * self.lanes
+        self._members = [[] for _ in range(self.lanes)]
         self._done = [None] * self.lanes
         self._bytes = {}
+        self.rebuilds = 0
         # pinned host slots for the statistics blocks copied at the end of a
         # request's last tick (no blocking read in the serving loop)
         B = T.STATS_BLOCK_BYTES
         self._stats_host = torch.empty(max_slots * B, dtype=torch.uint8, pin_memory=True)
         self._free_slots = list(range(max_slots - 1, -1, -1))
         self._slot = {}
+
+    def free_bytes(self):
+        return self.torch.cuda.mem_get_info(self.device)[0]
 
     def required_bytes(self, problem):
         k = id(problem)
@@ -317,17 +449,40 @@ class GpuBackend:
     def _slot_ptr(self, h):
         return self._stats_host.data_ptr() + self._slot[id(h)] * self.T.STATS_BLOCK_BYTES
 
+    def _set_members(self, lane, handles):
+        """The lane's batch with exactly these members (made at first use,
+        made again larger when they outgrow its buffer)."""
+        handles = list(handles)
+        if [id(h) for h in handles] == [id(h) for h in self._members[lane]]:
+            return
+        b = self._batch[lane]
+        if b is not None:
+            try:
+                b.set_members(handles)
+                self._members[lane] = handles
+                return
+            except self.T.TissueError as e:
+                if e.code != self.T.EBUSY:
+                    raise
+                b.set_members([])
+                b.close()
+                self._batch[lane] = None
+                self.capacity *= 2
+        if not handles:
+            self._members[lane] = []
+            return
+        b = self.T.Batch(handles, device=self.device, stream=self.streams[lane],
+                         capacity_bytes=self.capacity)
+        b.set_graph_chunk(self.graph_chunk)
+        b.set_launch(self.persistent, 0)
+        if self.regroup != 2:
+            b.set_regroup(self.regroup)
+        self._batch[lane] = b
+        self._members[lane] = handles
+        self.rebuilds += 1
+
     def step(self, lane, handles, dt, n, finishing=()):
-        key = tuple(id(h) for h in handles)
-        if key != self._key[lane]:
-            if self._batch[lane] is not None:
-                self._batch[lane].close()
-            self._batch[lane] = self.T.Batch(handles, device=self.device, stream=self.streams[lane])
-            self._batch[lane].set_graph_chunk(self.graph_chunk)
-            self._batch[lane].set_launch(self.persistent, 0)
-            if self.regroup != 2:
-                self._batch[lane].set_regroup(self.regroup)
-            self._key[lane] = key
+        self._set_members(lane, handles)
         self._batch[lane].step(dt, n)
         for h in finishing:
             h.stats_enqueue(self._slot_ptr(h))
@@ -352,13 +507,18 @@ class GpuBackend:
     def read(self, h):
         return h.read_counts()
 
+    def retire(self, lane, handles):
+        """Release finished or abandoned requests: out of the lane's batch
+        first (a member cannot be destroyed), then destroyed."""
+        gone = {id(h) for h in handles}
+        self._set_members(lane, [h for h in self._members[lane] if id(h) not in gone])
+        for h in handles:
+            h.close()
+            h.buffer = None
+            self._free_slots.append(self._slot.pop(id(h)))
+
     def free(self, lane, h):
-        if self._batch[lane] is not None:
-            self._batch[lane].close()
-            self._batch[lane], self._key[lane] = None, None
-        h.close()
-        h.buffer = None
-        self._free_slots.append(self._slot.pop(id(h)))
+        self.retire(lane, [h])
 
 
 def requests_from_workload(n: int, seed: int = 5, rate_hz: float = 200.0, n_steps: int = 100,

@@ -88,6 +88,7 @@ EXPORTS = [
     "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
     "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
     "tissue_batch_step_static", "tissue_set_refill", "tissue_batch_set_refill",
+    "tissue_batch_set_members",
 ]
 
 
@@ -133,6 +134,7 @@ def _load():
         "tissue_batch_step_static": (C.c_int, [C.POINTER(vp), i32, dbl, i32, vp]),
         "tissue_set_refill": (C.c_int, [vp, i32]),
         "tissue_batch_set_refill": (C.c_int, [vp, i32]),
+        "tissue_batch_set_members": (C.c_int, [vp, C.POINTER(vp), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -369,9 +371,11 @@ def batch_step_static(tissues, dt: float, n_steps: int, stream=None):
 
 
 class Batch:
-    """Many tissues advanced by shared launches (one HIP graph per chunk of steps)."""
+    """Many tissues advanced by shared launches (one HIP graph per chunk of steps).
+    capacity_bytes: a larger work-list buffer than these members need, room
+    for set_members to admit more later."""
 
-    def __init__(self, tissues, device="cuda:0", stream=None):
+    def __init__(self, tissues, device="cuda:0", stream=None, capacity_bytes: int = 0):
         import torch
         self.tissues = list(tissues)
         arr = (C.c_void_p * len(self.tissues))(*[t.handle.value for t in self.tissues])
@@ -380,6 +384,7 @@ class Batch:
         if need == 0:
             _check(lib.tissue_batch_create(arr, len(self.tissues), None, 0, None, C.byref(C.c_void_p())),
                    "tissue_batch_create")
+        need = max(need, int(capacity_bytes))
         self.buffer = torch.empty(need + 256, dtype=torch.uint8, device=device)
         addr = self.buffer.data_ptr()
         aligned = (addr + 255) // 256 * 256
@@ -422,6 +427,15 @@ class Batch:
 
     def sync(self):
         _check(lib.tissue_batch_sync(self.handle), "tissue_batch_sync")
+
+    def set_members(self, tissues):
+        """Replace the members in place (no host synchronisation); raises
+        TissueError with code EBUSY when they do not fit the buffer."""
+        tissues = list(tissues)
+        arr = (C.c_void_p * max(len(tissues), 1))(*[t.handle.value for t in tissues])
+        _check(lib.tissue_batch_set_members(self.handle, arr, len(tissues)), "tissue_batch_set_members")
+        self.tissues = tissues
+        self._arr = arr
 
     def close(self):
         if getattr(self, "handle", None):

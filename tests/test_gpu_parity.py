@@ -455,6 +455,48 @@ def test_batch_membership_rules():
     b.close()
 
 
+def test_batch_set_members_in_place(oracle_lib):
+    """Continuous batching: members admitted and retired between steps of one
+    batch (tissue_batch_set_members, no new batch), each tissue's bits equal
+    to its steps alone; a member set over the batch's buffer answers EBUSY
+    and changes nothing; a retired member can be destroyed; an empty batch
+    steps nothing."""
+    from paper_1806_10889_amd import tissue as T
+    probs = [W.random_problem(170 + k, lattice=k % 2, nx=5 + 2 * k, ny=6, model="nd5",
+                              mesh=(4, 4) if k % 3 else (2, 3), dt=0.05, sim_id=30 + k, n_steps=6)
+             for k in range(5)]
+    ts = [T.Tissue(p) for p in probs]
+    b = T.Batch(ts[:2], capacity_bytes=4 << 20)
+    b.step(0.05, 2)                      # 0, 1: steps 0..1
+    b.set_members([ts[0], ts[1], ts[2]])
+    b.step(0.05, 2)                      # 0, 1: 2..3; 2: 0..1
+    b.set_members([ts[2], ts[3]])        # 0 and 1 retire
+    ts[1].close()
+    b.step(0.05, 2)                      # 2: 2..3; 3: 0..1
+    b.set_members([])
+    b.step(0.05, 3)                      # nothing
+    b.set_members([ts[4], ts[0], ts[2]])
+    b.step(0.05, 2)                      # 4: 0..1; 0: 4..5; 2: 4..5
+    b.sync()
+    big = T.Tissue(W.birth_death(1.0, 0.1, 3, nx=400, ny=400, dt=0.05))  # > 4 MiB of work lists
+    with pytest.raises(T.TissueError) as ei:
+        b.set_members([ts[4], big])
+    assert ei.value.code == T.EBUSY
+    b.step(0.05, 1)                      # unchanged members: 4: 2; 0: 6; 2: 6
+    b.sync()
+    want = {0: 7, 2: 7, 3: 2, 4: 3}
+    for k, n in want.items():
+        o = _oracle(oracle_lib, probs[k], n, trace=False)
+        st = ts[k].stats()
+        assert np.array_equal(ts[k].read_counts(), o.counts), k
+        assert (st["chi_events"], st["s_events"], st["draws"], st["steps_done"]) == \
+            (o.chi_events, o.s_events, o.draws, n)
+    b.close()
+    big.close()
+    for k in want:
+        ts[k].close()
+
+
 def test_config3_reduced_uneven(oracle_lib):
     p = W.config3(side=24, n_steps=3)
     o = _oracle(oracle_lib, p, 3)
