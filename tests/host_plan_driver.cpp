@@ -1,0 +1,275 @@
+// Device-free paths of the host runtime under AddressSanitizer and
+// UndefinedBehaviorSanitizer: descriptor validation and the plan of a
+// tissue (lattice edges ranked by (colour, i), rings, face groups, leaf
+// classes, the device layout), the chi launch plans of every mode, regroup
+// setting and device size, and batch layouts, on random descriptors and on
+// descriptors broken one field at a time.  Built by the CPU test suite with
+// the sanitizers on the host side only; it includes the runtime's source so
+// that its internal functions can be called, and takes the kernels'
+// launchers and the network compiler from the library.  Besides running
+// clean it checks what a plan promises: every cell in exactly one work item
+// of every launch plan, items within their launch's cells per item, regroup
+// segments covering their class, required bytes equal to the layout.
+#include "../paper_1806_10889_amd/csrc/host.cpp"
+
+#include <cstdio>
+#include <random>
+
+namespace {
+
+struct Case {
+    tissue_desc_t d{};
+    std::vector<uint8_t> mw, mh, cm;
+    std::vector<int32_t> reactants, stoich, init;
+    std::vector<double> rates, diffusion;
+    std::vector<tissue_model_t> models;
+    std::vector<std::vector<int32_t>> m_reac, m_stoich;
+    std::vector<std::vector<double>> m_rates, m_diff;
+};
+
+int fails = 0;
+
+void check(bool ok, const char *what, int trial)
+{
+    if (!ok) {
+        std::fprintf(stderr, "trial %d: %s\n", trial, what);
+        ++fails;
+    }
+}
+
+// a random network over S species: R reactions of order 0..2 whose net
+// change never removes more than a reactant supplies
+void random_network(std::mt19937_64 &g, int S, int R, std::vector<int32_t> &reac,
+                    std::vector<int32_t> &st, std::vector<double> &rates, std::vector<double> &diff)
+{
+    std::uniform_int_distribution<int> sp(-1, S - 1), dl(-1, 2);
+    std::uniform_real_distribution<double> u(0.0, 2.0);
+    reac.assign(2 * R, -1);
+    st.assign((size_t)R * S, 0);
+    rates.assign(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+        reac[2 * r] = sp(g);
+        reac[2 * r + 1] = sp(g);
+        int changed = 0;
+        for (int s = 0; s < S && changed < 4; ++s) {
+            int v = dl(g);
+            const int supplied = (reac[2 * r] == s) + (reac[2 * r + 1] == s);
+            if (v < -supplied) v = -supplied;
+            st[(size_t)r * S + s] = v;
+            changed += v != 0;
+        }
+        rates[r] = u(g);
+    }
+    diff.assign(S, 0.0);
+    for (int s = 0; s < S; ++s) diff[s] = (g() & 1) ? u(g) : 0.0;
+}
+
+void random_case(std::mt19937_64 &g, Case &c)
+{
+    std::uniform_int_distribution<int> side(1, 40), mesh(1, 8), spn(1, 8), rn(0, 16), cnt(0, 60);
+    tissue_desc_t &d = c.d;
+    d = tissue_desc_t{};
+    d.abi_version = TISSUE_ABI_VERSION;
+    d.lattice = g() & 1;
+    d.nx = (uint32_t)side(g);
+    d.ny = (uint32_t)side(g);
+    const uint32_t n = d.nx * d.ny;
+    const bool uneven = g() & 1;
+    d.mesh_w0 = (uint32_t)mesh(g);
+    d.mesh_h0 = (uint32_t)mesh(g);
+    c.mw.assign(n, 0);
+    c.mh.assign(n, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        c.mw[i] = (uint8_t)(uneven ? mesh(g) : d.mesh_w0);
+        c.mh[i] = (uint8_t)(uneven ? mesh(g) : d.mesh_h0);
+    }
+    d.mesh_w = uneven ? c.mw.data() : nullptr;
+    d.mesh_h = uneven ? c.mh.data() : nullptr;
+    const int S = std::max(3, spn(g));
+    d.n_species = (uint32_t)S;
+    const int R = rn(g);
+    random_network(g, S, R, c.reactants, c.stoich, c.rates, c.diffusion);
+    d.n_reactions = (uint32_t)R;
+    d.reactants = c.reactants.data();
+    d.stoich = c.stoich.data();
+    d.rates = c.rates.data();
+    d.diffusion = c.diffusion.data();
+    const bool first = g() & 1;
+    d.flags = (first ? TISSUE_FLAG_SIGNAL_FIRST_ORDER : 0u) | ((g() & 1) ? TISSUE_FLAG_STRANG : 0u) |
+              ((g() & 3) == 0 ? TISSUE_FLAG_TRACE : 0u) | TISSUE_FLAG_NO_JIT;
+    d.trace_steps = 3;
+    d.trans_n = first ? -1 : 0;
+    d.trans_d = 1;
+    d.trans_i = 2;
+    d.trans_rate = 0.5;
+    if ((g() % 5) == 0) d.trans_n = -1, d.trans_d = -1;  // no S
+    size_t nvox = 0;
+    for (uint32_t i = 0; i < n; ++i) nvox += (size_t)c.mw[i] * c.mh[i];
+    c.init.resize(nvox * S);
+    for (auto &x : c.init) x = cnt(g);
+    d.init_counts = c.init.data();
+    d.seed = g();
+    d.sim_id = (uint32_t)(g() % 1000);
+    // per-cell networks on some tissues
+    const int nm = (g() % 3 == 0) ? (int)(g() % 4) : 0;
+    c.models.assign(nm, tissue_model_t{});
+    c.m_reac.assign(nm, {});
+    c.m_stoich.assign(nm, {});
+    c.m_rates.assign(nm, {});
+    c.m_diff.assign(nm, {});
+    for (int m = 0; m < nm; ++m) {
+        const int Rm = rn(g);
+        random_network(g, S, Rm, c.m_reac[m], c.m_stoich[m], c.m_rates[m], c.m_diff[m]);
+        c.models[m] = tissue_model_t{(uint32_t)Rm, c.m_reac[m].data(), c.m_stoich[m].data(),
+                                     c.m_rates[m].data(), c.m_diff[m].data(), first ? 0.25 : 0.5};
+    }
+    c.cm.assign(n, 0);
+    for (uint32_t i = 0; i < n; ++i) c.cm[i] = (uint8_t)(nm ? g() % (nm + 1) : 0);
+    d.n_models = (uint32_t)nm;
+    d.models = nm ? c.models.data() : nullptr;
+    d.cell_model = nm ? c.cm.data() : nullptr;
+}
+
+// every cell of the plan in exactly one item of one launch; items within
+// their launch's cells per item; regroup segments within a class
+void check_launches(const Plan &p, const std::vector<ChiItem> &items,
+                    const std::vector<ChiLaunch> &ls, int trial)
+{
+    std::vector<int> seen(p.ncell, 0);
+    for (const ChiLaunch &L : ls) {
+        const size_t off = reinterpret_cast<uintptr_t>(L.items);
+        check(off + L.n_items <= items.size(), "launch items out of range", trial);
+        if (off + L.n_items > items.size()) return;
+        for (uint32_t k = 0; k < L.n_items; ++k) {
+            const ChiItem &it = items[off + k];
+            check(it.tissue == 0 && it.count >= 1 && it.count <= (uint32_t)L.cells_per_item,
+                  "item size", trial);
+            check(it.first + it.count <= p.ncell, "item range", trial);
+            for (uint32_t q = 0; q < it.count && it.first + q < p.ncell; ++q) {
+                const int32_t cell = p.cell_list[it.first + q];
+                const int V = p.wh[2 * cell] * p.wh[2 * cell + 1];
+                check(pow2_at_least(V) == L.P, "cell of another leaf class", trial);
+                check((int)p.cell_model[cell] == (int)it.model, "cell of another network", trial);
+                seen[cell]++;
+            }
+        }
+        if (L.n_segs) {
+            const size_t so = reinterpret_cast<uintptr_t>(L.segs);
+            check(so + L.n_segs <= items.size(), "segments out of range", trial);
+            for (uint32_t k = 0; k < L.n_segs && so + k < items.size(); ++k)
+                check(items[so + k].count <= kRegroupChunk, "segment too long", trial);
+        }
+    }
+    for (uint32_t c = 0; c < p.ncell; ++c) check(seen[c] == 1, "cell not in exactly one item", trial);
+    check(items.size() <= p.n_chi_items, "items over the plan's room", trial);
+}
+
+}  // namespace
+
+int main()
+{
+    std::mt19937_64 g(20261203);
+    int planned = 0, rejected = 0;
+    std::vector<std::unique_ptr<tissue>> keep;
+    for (int trial = 0; trial < 300; ++trial) {
+        Case c;
+        random_case(g, c);
+        std::unique_ptr<tissue> t(new tissue());
+        const int rc = build_plan(&c.d, t->plan);
+        if (rc != TISSUE_OK) {
+            ++rejected;
+            check(tissue_required_bytes(&c.d) == 0, "required bytes of a rejected descriptor", trial);
+            continue;
+        }
+        ++planned;
+        const Plan &p = t->plan;
+        check(tissue_required_bytes(&c.d) == p.bytes, "required bytes", trial);
+        check(p.cell_list.size() == p.ncell, "cell list", trial);
+        for (int mode = kModeLane; mode <= kModeRowWide; ++mode)
+            for (int regroup = 0; regroup <= 2; ++regroup)
+                for (int simd : {4, 1024}) {
+                    std::vector<ChiItem> items;
+                    std::vector<ChiLaunch> ls;
+                    plan_chi({&p}, mode, regroup, simd, items, ls);
+                    check_launches(p, items, ls, trial);
+                }
+        if (keep.size() < 12) keep.push_back(std::move(t));
+    }
+    // batches of the kept tissues: layout, passes, members repeated
+    for (size_t n = 1; n <= keep.size(); ++n) {
+        std::vector<tissue *> ts;
+        for (size_t i = 0; i < n; ++i) ts.push_back(keep[i].get());
+        bool same_scheme = true;
+        for (tissue *t : ts) same_scheme &= t->plan.strang == ts[0]->plan.strang;
+        BatchLayout B;
+        const int rc = plan_batch(ts.data(), (int32_t)n, B);
+        check(rc == (same_scheme ? TISSUE_OK : TISSUE_EINVAL), "batch scheme rule", (int)n);
+        if (rc == TISSUE_OK) check(B.bytes > 0 && B.s_fix.size() == B.s_passes.size(), "batch layout", (int)n);
+        ts.push_back(ts[0]);
+        BatchLayout B2;
+        check(plan_batch(ts.data(), (int32_t)ts.size(), B2) == TISSUE_EINVAL, "duplicate member", (int)n);
+    }
+    // one field broken at a time: every one rejected before any device work
+    {
+        Case c;
+        for (;;) {
+            random_case(g, c);
+            Plan tmp;
+            if (c.d.n_reactions > 0 && c.d.trans_n >= 0 && c.d.mesh_w && c.d.n_models > 0 &&
+                build_plan(&c.d, tmp) == TISSUE_OK)
+                break;
+        }
+        const tissue_desc_t good = c.d;
+        int broken = 0;
+        auto bad = [&](const char *what, const tissue_desc_t &d) {
+            Plan tmp;
+            check(build_plan(&d, tmp) == TISSUE_EINVAL, what, -1);
+            check(tissue_required_bytes(&d) == 0, what, -1);
+            ++broken;
+        };
+        tissue_desc_t d;
+        d = good; d.abi_version = 0; bad("abi version", d);
+        d = good; d.lattice = 2; bad("lattice", d);
+        d = good; d.nx = 0; bad("empty lattice", d);
+        d = good; d.n_species = 0; bad("no species", d);
+        d = good; d.n_species = 9; bad("too many species", d);
+        d = good; d.sim_id = 1u << 30; bad("sim_id", d);
+        d = good; d.init_counts = nullptr; bad("null counts", d);
+        d = good; d.mesh_h = nullptr; bad("one mesh array", d);
+        d = good; d.flags |= 1u << 10; bad("unknown flag", d);
+        d = good; d.flags |= TISSUE_FLAG_TRACE; d.trace_steps = 0; bad("trace without steps", d);
+        d = good; d.n_models = 8; bad("too many models", d);
+        d = good; d.n_reactions = 17; bad("too many reactions", d);
+        d = good; d.cell_model = nullptr; d.models = nullptr; bad("models null", d);
+        std::vector<double> r2 = c.rates;
+        r2[0] = std::nan("");
+        d = good; d.rates = r2.data(); bad("nan rate", d);
+        std::vector<double> df = c.diffusion;
+        df[0] = -1.0;
+        d = good; d.diffusion = df.data(); bad("negative diffusion", d);
+        std::vector<int32_t> ic = c.init;
+        ic.back() = -1;
+        d = good; d.init_counts = ic.data(); bad("negative count", d);
+        ic.back() = 1 << 26;
+        d = good; d.init_counts = ic.data(); bad("count at the limit", d);
+        std::vector<uint8_t> mw = c.mw;
+        mw[mw.size() / 2] = 9;
+        d = good; d.mesh_w = mw.data(); bad("mesh side 9", d);
+        d = good; d.trans_d = d.trans_n; bad("signalling species not distinct", d);
+        std::vector<int32_t> re = c.reactants;
+        re[0] = (int32_t)good.n_species;
+        d = good; d.reactants = re.data(); bad("reactant out of range", d);
+        std::vector<int32_t> sto = c.stoich;
+        std::vector<int32_t> re2 = c.reactants;
+        re2[0] = -1;
+        re2[1] = -1;
+        sto[0] = -1;  // reaction 0 has no reactant now and removes species 0
+        d = good; d.reactants = re2.data(); d.stoich = sto.data(); bad("consumes what it lacks", d);
+        std::vector<uint8_t> cm = c.cm;
+        cm[0] = (uint8_t)(good.n_models + 1);
+        d = good; d.cell_model = cm.data(); bad("cell model out of range", d);
+        std::printf("broken descriptors rejected: %d\n", broken);
+    }
+    std::printf("planned %d, rejected %d, failures %d\n", planned, rejected, fails);
+    return fails ? 1 : 0;
+}
