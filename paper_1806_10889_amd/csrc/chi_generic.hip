@@ -22,11 +22,11 @@ __global__ __launch_bounds__(kWave) void chi_lane_kernel(const DevTissue *const 
                                                          uint32_t *queue, int persistent,
                                                          int cells_per_item, int log2p, double dt,
                                                          uint32_t kstep, uint32_t tag,
-                                                         uint32_t *n_items_dev)
+                                                         uint32_t *n_items_dev, int prio)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     chi_lane_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
-                                           cells_per_item, log2p, dt, kstep, tag, n_items_dev);
+                                           cells_per_item, log2p, dt, kstep, tag, n_items_dev, prio);
 }
 
 template <int SM, int RM, int NDM, int G>
@@ -35,23 +35,24 @@ __global__ __launch_bounds__(kWave) void chi_lane16_kernel(const DevTissue *cons
                                                            uint32_t *queue, int persistent,
                                                            int cells_per_item, double dt,
                                                            uint32_t kstep, uint32_t tag,
-                                                           ChiItem *retry_items, uint32_t *retry_count)
+                                                           ChiItem *retry_items, uint32_t *retry_count,
+                                                           int prio)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     chi_lane16_body<NetGeneric<SM, RM, NDM>, G>(lds, tbl, items, n_items, queue, persistent,
                                                 cells_per_item, dt, kstep, tag, retry_items,
-                                                retry_count);
+                                                retry_count, prio);
 }
 
 template <int SM, int RM, int NDM, int RW>
 __global__ __launch_bounds__(kWave) void chi_row_kernel(const DevTissue *const *tbl,
                                                         const ChiItem *items, uint32_t n_items,
                                                         uint32_t *queue, int persistent, double dt,
-                                                        uint32_t kstep, uint32_t tag)
+                                                        uint32_t kstep, uint32_t tag, int prio)
 {
     __shared__ RowShared sh;
     chi_row_body<NetGeneric<SM, RM, NDM>, RW>(sh, tbl, items, n_items, queue, persistent, dt,
-                                              kstep, tag);
+                                              kstep, tag, prio);
 }
 
 namespace {
@@ -68,31 +69,31 @@ hipError_t launch_variant(const ChiArgs &a)
 {
     if (a.mode == kChiRow && a.rw == 64) {
         hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 64>), dim3(a.grid), dim3(kWave), 0, a.stream,
-                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
+                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag, a.prio);
     } else if (a.mode == kChiRow && a.rw == 32) {
         hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 32>), dim3(a.grid), dim3(kWave), 0, a.stream,
-                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
+                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag, a.prio);
     } else if (a.mode == kChiRow) {
         hipLaunchKernelGGL((chi_row_kernel<SM, RM, NDM, 16>), dim3(a.grid), dim3(kWave), 0, a.stream,
-                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag);
+                           a.tbl, a.items, a.n_items, a.queue, a.persistent, a.dt, a.kstep, a.tag, a.prio);
     } else if (a.mode == kChiLane16 && a.P == 64) {
         hipLaunchKernelGGL((chi_lane16_kernel<SM, RM, NDM, 4>), dim3(a.grid), dim3(kWave), a.lds,
                            a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count);
+                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count, a.prio);
     } else if (a.mode == kChiLane16 && a.P == 32) {
         hipLaunchKernelGGL((chi_lane16_kernel<SM, RM, NDM, 2>), dim3(a.grid), dim3(kWave), a.lds,
                            a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count);
+                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count, a.prio);
     } else if (a.mode == kChiLane16 && a.P <= 16) {
         hipLaunchKernelGGL((chi_lane16_kernel<SM, RM, NDM, 1>), dim3(a.grid), dim3(kWave), a.lds,
                            a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count);
+                           a.cells_per_item, a.dt, a.kstep, a.tag, a.retry_items, a.retry_count, a.prio);
     } else if (a.mode == kChiLane16) {
         return hipErrorInvalidValue;
     } else {
         hipLaunchKernelGGL((chi_lane_kernel<SM, RM, NDM>), dim3(a.grid), dim3(kWave), a.lds,
                            a.stream, a.tbl, a.items, a.n_items, a.queue, a.persistent,
-                           a.cells_per_item, log2_exact(a.P), a.dt, a.kstep, a.tag, a.n_items_dev);
+                           a.cells_per_item, log2_exact(a.P), a.dt, a.kstep, a.tag, a.n_items_dev, a.prio);
     }
     return hipGetLastError();
 }

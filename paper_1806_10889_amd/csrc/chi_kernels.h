@@ -14,6 +14,9 @@
 // Work items (<= 64 cells of one tissue) come one per workgroup or, in
 // persistent mode, from a device queue every workgroup pulls from until it is
 // empty; the last workgroup to leave clears the queue for the next launch.
+// A launch may ask for a raised issue priority of its wavefronts (`prio`):
+// where several classes' launches share the device, the arbiter then serves
+// its wavefronts first on a SIMD they share with another launch's.
 #pragma once
 
 #include "device_math.h"
@@ -407,10 +410,12 @@ template <class NET>
 __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissue *const *tbl,
                                               const ChiItem *items, uint32_t n_items, uint32_t *queue,
                                               int persistent, int cells_per_item, int log2p, double dt,
-                                              uint32_t kstep, uint32_t tag, uint32_t *n_items_dev)
+                                              uint32_t kstep, uint32_t tag, uint32_t *n_items_dev,
+                                              int prio)
 {
     constexpr int SM = NET::SM;
     __shared__ ChanEntry tab[kChanSlots];
+    if (prio) __builtin_amdgcn_s_setprio(2);
     if (n_items_dev) n_items = uni(*(volatile uint32_t *)n_items_dev);
     const int lane = threadIdx.x;
     const int stride = cells_per_item;
@@ -615,11 +620,26 @@ __device__ __forceinline__ uint32_t row_or(uint32_t x)
 }
 
 // The value of lane (lane ^ mask), mask 16 or 32: the tree levels and the
-// word broadcast of rows wider than one 16-lane DPP row.
+// word broadcast of rows wider than one 16-lane DPP row.  The gfx950 lane
+// swaps between row pairs and wave halves, without LDS: swapping a value
+// with itself leaves, in the first result, every even row's (lower half's)
+// own value and every odd row's (upper half's) partner's, in the second the
+// other way round.
+__device__ __forceinline__ uint32_t xlane_u32(uint32_t v, int mask)
+{
+    const int lane = (int)threadIdx.x;
+    if (mask == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return lane < 32 ? r[1] : r[0];
+    }
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) == 0 ? r[1] : r[0];
+}
+
 __device__ __forceinline__ double xlane_f64(double v, int mask)
 {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__shfl_xor(hi, mask, kWave), __shfl_xor(lo, mask, kWave));
+    const uint32_t lo = (uint32_t)__double2loint(v), hi = (uint32_t)__double2hiint(v);
+    return __hiloint2double((int)xlane_u32(hi, mask), (int)xlane_u32(lo, mask));
 }
 
 // One descent level from the children L (left) and R of the lane's ancestor.
@@ -657,9 +677,11 @@ struct RowShared {
 template <class NET, int RW>
 __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *const *tbl,
                                              const ChiItem *items, uint32_t n_items, uint32_t *queue,
-                                             int persistent, double dt, uint32_t kstep, uint32_t tag)
+                                             int persistent, double dt, uint32_t kstep, uint32_t tag,
+                                             int prio)
 {
     static_assert(RW == 16 || RW == 32 || RW == 64, "row width");
+    if (prio) __builtin_amdgcn_s_setprio(2);
     constexpr int SM = NET::SM;
     constexpr int LOG_RW = RW == 64 ? 6 : RW == 32 ? 5 : 4;
     ChanEntry *tab = sh.chan;
@@ -812,8 +834,8 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
             // zero outside the selected lane): OR over the 16-lane DPP row,
             // then across DPP rows for wider rows
             word = row_or(word);
-            if (RW >= 32) word |= (uint32_t)__shfl_xor((int)word, 16, kWave);
-            if (RW == 64) word |= (uint32_t)__shfl_xor((int)word, 32, kWave);
+            if (RW >= 32) word |= xlane_u32(word, 16);
+            if (RW == 64) word |= xlane_u32(word, 32);
             // (a word is set only in a row that takes its event)
             const bool recv = (word & 0xFFFFFF01u) == (((uint32_t)lvo << 8) | 1u);
             const uint64_t inc = (uint64_t)(recv ? 1u : 0u) << (word & 0x38u);
@@ -918,9 +940,10 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
                                                 const ChiItem *items, uint32_t n_items,
                                                 uint32_t *queue, int persistent, int cells_per_item,
                                                 double dt, uint32_t kstep, uint32_t tag,
-                                                ChiItem *retry_items, uint32_t *retry_count)
+                                                ChiItem *retry_items, uint32_t *retry_count, int prio)
 {
     static_assert(G == 1 || G == 2 || G == 4, "lanes per cell");
+    if (prio) __builtin_amdgcn_s_setprio(2);
     constexpr int SM = NET::SM;
     constexpr int LOG_G = G == 4 ? 2 : G == 2 ? 1 : 0;
     __shared__ ChanEntry tab[kChanSlots];

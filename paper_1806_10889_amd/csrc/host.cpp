@@ -209,7 +209,7 @@ struct Plan {
     std::vector<int32_t> cell_list;
     std::vector<uint8_t> cell_model;    // [ncell] each cell's network
     std::vector<EdgeRec> edges;
-    std::vector<uint32_t> class_start;  // [n_colours + 1] edge ranges per colour
+    std::vector<uint32_t> pass_start;   // [passes + 1] ranges of the edge records per S pass
     bool disjoint = true;               // every cell's face groups pairwise disjoint
     bool has_s = false;
     int face_kind = 0;                  // 2 or 1: every edge has face groups of 2 and 2 (1 and 1) voxels
@@ -429,7 +429,6 @@ int build_plan(const tissue_desc_t *d, Plan &p)
 
     // edges, face groups, S passes
     const int nd = p.lattice == TISSUE_LATTICE_SQUARE ? 4 : 6;
-    const int ncol = nd;
     if (p.has_s) {
         std::map<int, std::vector<std::vector<int>>> faces;  // (w*16+h) -> [nd] groups
         for (uint32_t c = 0; c < p.ncell; ++c) {
@@ -450,30 +449,62 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         const std::vector<Edge> E = lattice_edges((int)p.lattice, (int)p.nx, (int)p.ny);
         p.nedge = (uint32_t)E.size();
         p.edges.resize(E.size());
-        p.class_start.assign(ncol + 1, 0);
-        // processing order of the records: with disjoint face groups S is one
-        // pass, and the edges go in the order of their first cell (then
-        // direction), so that the edges around a cell are processed close
-        // together and its counts are fetched into a cache once; otherwise
-        // the colour classes in rank order
-        std::vector<uint32_t> pos(E.size());
-        for (size_t e = 0; e < E.size(); ++e) pos[e] = (uint32_t)e;
-        if (p.disjoint) {
-            std::vector<uint32_t> ord(E.size());
-            for (size_t e = 0; e < E.size(); ++e) ord[e] = (uint32_t)e;
-            std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
-                return E[a].i != E[b].i ? E[a].i < E[b].i : E[a].d < E[b].d;
-            });
-            for (size_t k = 0; k < ord.size(); ++k) pos[ord[k]] = (uint32_t)k;
+        auto group_i = [&](const Edge &ed) -> const std::vector<int> & {
+            return faces[p.wh[2 * ed.i] * 16 + p.wh[2 * ed.i + 1]][ed.d];
+        };
+        auto group_j = [&](const Edge &ed) -> const std::vector<int> & {
+            return faces[p.wh[2 * ed.j] * 16 + p.wh[2 * ed.j + 1]][(ed.d + nd / 2) % nd];
+        };
+        // S passes.  The colour classes run in order, each over the whole
+        // interval; an edge's SSA reads and writes only its two face groups,
+        // so two edges of different classes commute unless they share a
+        // voxel, and any order that keeps every such pair in class order
+        // gives the same bits.  Pass (level) of an edge: 0 if no edge of an
+        // earlier class touched its voxels, else one more than the highest
+        // pass of those that did.  With disjoint face groups every edge is in
+        // pass 0 (one launch); with overlapping ones (meshes of fewer than
+        // six membrane voxels on the hexagonal lattice) usually two passes
+        // instead of one per class.
+        std::vector<uint8_t> level(E.size(), 0);
+        if (!p.disjoint) {
+            std::vector<uint8_t> last(p.nvox, 0);  // highest pass + 1 that touched a voxel
+            std::vector<size_t> by_class(E.size());
+            for (size_t e = 0; e < E.size(); ++e) by_class[e] = e;  // already in (colour, i) order
+            for (size_t e : by_class) {
+                const Edge &ed = E[e];
+                int lv = 0;
+                for (int v : group_i(ed)) lv = std::max(lv, (int)last[p.vox_off[ed.i] + v]);
+                for (int v : group_j(ed)) lv = std::max(lv, (int)last[p.vox_off[ed.j] + v]);
+                if (lv >= 255) return fail(TISSUE_EINVAL, "too many signalling passes");
+                level[e] = (uint8_t)lv;
+                // edges of one class share no cell, so marking at once is safe
+                for (int v : group_i(ed)) last[p.vox_off[ed.i] + v] = (uint8_t)(lv + 1);
+                for (int v : group_j(ed)) last[p.vox_off[ed.j] + v] = (uint8_t)(lv + 1);
+            }
         }
-        for (size_t e = 0; e < E.size(); ++e) {
+        // record order: by pass, then by first cell and direction, so that the
+        // edges around a cell are processed close together and its counts
+        // are fetched into a cache once
+        std::vector<uint32_t> ord(E.size());
+        for (size_t e = 0; e < E.size(); ++e) ord[e] = (uint32_t)e;
+        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+            if (level[a] != level[b]) return level[a] < level[b];
+            return E[a].i != E[b].i ? E[a].i < E[b].i : E[a].d < E[b].d;
+        });
+        int n_levels = 0;
+        for (size_t e = 0; e < E.size(); ++e) n_levels = std::max(n_levels, (int)level[e] + 1);
+        p.pass_start.assign(n_levels + 1, 0);
+        for (size_t e = 0; e < E.size(); ++e) p.pass_start[level[e] + 1]++;
+        for (int l = 0; l < n_levels; ++l) p.pass_start[l + 1] += p.pass_start[l];
+        for (size_t k = 0; k < ord.size(); ++k) {
+            const uint32_t e = ord[k];
             const Edge &ed = E[e];
             EdgeRec r{};
-            r.id = (uint32_t)e;
+            r.id = e;
             r.vox_i = p.vox_off[ed.i];
             r.vox_j = p.vox_off[ed.j];
-            const auto &gi = faces[p.wh[2 * ed.i] * 16 + p.wh[2 * ed.i + 1]][ed.d];
-            const auto &gj = faces[p.wh[2 * ed.j] * 16 + p.wh[2 * ed.j + 1]][(ed.d + nd / 2) % nd];
+            const auto &gi = group_i(ed);
+            const auto &gj = group_j(ed);
             if (gi.size() > (size_t)kMaxFace || gj.size() > (size_t)kMaxFace)
                 return fail(TISSUE_EINVAL, "face group larger than supported");
             r.m_a = (uint8_t)gi.size();
@@ -482,30 +513,19 @@ int build_plan(const tissue_desc_t *d, Plan &p)
             r.model_j = p.cell_model[ed.j];
             for (size_t q = 0; q < gi.size(); ++q) r.A[q] = (uint8_t)gi[q];
             for (size_t q = 0; q < gj.size(); ++q) r.B[q] = (uint8_t)gj[q];
-            p.edges[pos[e]] = r;
-            p.class_start[ed.colour + 1]++;
+            p.edges[k] = r;
         }
-        for (int c = 0; c < ncol; ++c) p.class_start[c + 1] += p.class_start[c];
         p.face_kind = -1;
         for (const EdgeRec &r : p.edges) {
             const int k = (r.m_a == 2 && r.m_b == 2) ? 2 : (r.m_a == 1 && r.m_b == 1) ? 1 : 0;
             p.face_kind = p.face_kind < 0 || p.face_kind == k ? k : 0;
         }
         if (p.face_kind < 0) p.face_kind = 0;
-        auto cut = [](uint32_t lo, uint32_t hi, std::vector<SItem> &out) {
-            for (uint32_t o = lo; o < hi; o += kWave)
-                out.push_back(SItem{0, o, std::min<uint32_t>(kWave, hi - o), 0});
-        };
-        if (p.disjoint) {
+        for (int l = 0; l < n_levels; ++l) {
             std::vector<SItem> pass;
-            cut(0, p.nedge, pass);
-            if (!pass.empty()) p.s_passes.push_back(std::move(pass));
-        } else {
-            for (int c = 0; c < ncol; ++c) {
-                std::vector<SItem> pass;
-                cut(p.class_start[c], p.class_start[c + 1], pass);
-                if (!pass.empty()) p.s_passes.push_back(std::move(pass));
-            }
+            for (uint32_t o = p.pass_start[l]; o < p.pass_start[l + 1]; o += kWave)
+                pass.push_back(SItem{0, o, std::min<uint32_t>(kWave, p.pass_start[l + 1] - o), 0});
+            p.s_passes.push_back(std::move(pass));
         }
         for (auto &ps : p.s_passes) p.n_s_items += ps.size();
     }
@@ -556,6 +576,7 @@ struct ChiLaunch {
     uint32_t retry_off;      // compact layout: this launch's part of the redo list
     const ChiItem *segs;     // regroup segments (a class's cells of one member), or none
     uint32_t n_segs;
+    int prio;                // nonzero: wavefronts at a raised issue priority
 };
 
 // chi mode request: lane, row, automatic, compact (lane16), or wide rows.
@@ -591,17 +612,39 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
         std::vector<std::pair<uint32_t, const ChiGroupHost *>> cells;
     };
     std::map<Key, Group> groups;
+    // the network key of a class (compiled network, or generic table sizes)
+    auto net_of = [](const Plan &p, const ChiGroupHost &g, int &SM, int &RM, int &NDM) {
+        const DevModel &M = p.models[(size_t)g.model];
+        chi_variant((int)p.S, M.n_reactions, M.n_diff, SM, RM, NDM);
+        return p.jits[(size_t)g.model] ? "J" + p.net_keys[(size_t)g.model]
+                                       : "G" + std::to_string(SM) + "," + std::to_string(RM) + "," +
+                                             std::to_string(NDM);
+    };
+    // automatic: where the cells of 3 to 16 voxels of a network hold the
+    // compact layout's 16 lanes of work per SIMD, the classes of 4 and 8
+    // leaves join the 16-leaf class's compact launch (its tree over 16
+    // leaves gives a smaller cell the same bits: padding leaves add 0), one
+    // launch instead of a lane-layout launch per small class; cells of one
+    // or two voxels keep the lane layout, whose trees are shorter still
+    std::map<std::string, uint64_t> small_cells;
+    if (mode_req == kModeAuto)
+        for (const Plan *pp : members)
+            for (const ChiGroupHost &g : pp->chi)
+                if (g.P >= 4 && g.P <= 16) {
+                    int a, b, c;
+                    small_cells[net_of(*pp, g, a, b, c)] += g.count;
+                }
     for (size_t i = 0; i < members.size(); ++i) {
         const Plan &p = *members[i];
         for (const ChiGroupHost &g : p.chi) {
-            const DevModel &M = p.models[(size_t)g.model];
             const JitKernels *jit = p.jits[(size_t)g.model];
             int SM, RM, NDM;
-            chi_variant((int)p.S, M.n_reactions, M.n_diff, SM, RM, NDM);
-            const std::string net = jit ? "J" + p.net_keys[(size_t)g.model]
-                                        : "G" + std::to_string(SM) + "," + std::to_string(RM) + "," +
-                                              std::to_string(NDM);
-            Group &G = groups[Key{g.P, net}];
+            const std::string net = net_of(p, g, SM, RM, NDM);
+            int P = g.P;
+            if (P >= 4 && P < 16 && mode_req == kModeAuto &&
+                small_cells[net] >= 16ull * (uint64_t)std::max(n_simd, 1))
+                P = 16;
+            Group &G = groups[Key{P, net}];
             G.jit = jit;
             G.SM = SM;
             G.RM = RM;
@@ -654,6 +697,7 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
         if (mode == kChiLane16) retry_cells += cells;
         L.segs = nullptr;
         L.n_segs = 0;
+        L.prio = 0;
         // regroup of a compact class: on request, or automatically when the
         // launch spans at least two wavefronts (grouping cells of similar
         // load shortens each wavefront's wait for its busiest cell and, with
@@ -707,6 +751,16 @@ void plan_chi(const std::vector<const Plan *> &members, int mode_req, int regrou
         }
         launches.push_back(L);
     }
+    // several classes' launches share the device (as parallel branches of a
+    // step graph): the compact launches -- many wavefronts, the step's
+    // longest event chains (the largest cells), issue-bound -- get a raised
+    // issue priority over the rows, whose one-cell wavefronts fill the
+    // SIMDs' remaining issue slots (the uneven 256x256 tissue: 9.3e9 ->
+    // 1.16e10 events/s; the same bits, only the order of issue changes)
+    int with_items = 0;
+    for (const ChiLaunch &L : launches) with_items += L.n_items > 0;
+    if (with_items > 1)
+        for (ChiLaunch &L : launches) L.prio = L.mode == kChiLane16 ? 1 : 0;
     // every launch's regroup segments after all items, contiguous, so that
     // a step graph can regroup every class in one launch before it forks
     const size_t seg_base = items_out.size();
@@ -826,12 +880,13 @@ struct LaunchPlan {
         a.tag = tag;
         a.retry_items = retry_items + L.retry_off;
         a.retry_count = q + kQRetry;
+        a.prio = L.prio;
         hipError_t e = hipSuccess;
         if (!L.jit) {
             e = launch_chi(L.SM, L.RM, L.NDM, a);
         } else if (L.mode == kChiRow) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.dt, &a.kstep,
-                            &a.tag};
+                            &a.tag, &a.prio};
             hipFunction_t f = L.rw == 64 ? L.jit->row64 : L.rw == 32 ? L.jit->row32 : L.jit->row;
             e = hipModuleLaunchKernel(f, grid, 1, 1, kWave, 1, 1, 0, st, args, nullptr);
         } else if (refills(L)) {
@@ -842,13 +897,13 @@ struct LaunchPlan {
                                       args, nullptr);
         } else if (L.mode == kChiLane16) {
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
-                            &a.dt, &a.kstep, &a.tag, &a.retry_items, &a.retry_count};
+                            &a.dt, &a.kstep, &a.tag, &a.retry_items, &a.retry_count, &a.prio};
             hipFunction_t f = L.P == 64 ? L.jit->lane16x4 : L.P == 32 ? L.jit->lane16x2 : L.jit->lane16;
             e = hipModuleLaunchKernel(f, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st, args, nullptr);
         } else {
             uint32_t *none = nullptr;
             void *args[] = {&a.tbl, &a.items, &a.n_items, &a.queue, &a.persistent, &a.cells_per_item,
-                            &log2p, &a.dt, &a.kstep, &a.tag, &none};
+                            &log2p, &a.dt, &a.kstep, &a.tag, &none, &a.prio};
             e = hipModuleLaunchKernel(L.jit->lane, grid, 1, 1, kWave, 1, 1, (unsigned)L.lds, st,
                                       args, nullptr);
         }
@@ -866,7 +921,7 @@ struct LaunchPlan {
         r.n_items_dev = q + kQRetry;
         if (!L.jit) return launch_chi(L.SM, L.RM, L.NDM, r);
         void *args[] = {&r.tbl, &r.items, &r.n_items, &r.queue, &r.persistent, &r.cells_per_item,
-                        &log2p, &r.dt, &r.kstep, &r.tag, &r.n_items_dev};
+                        &log2p, &r.dt, &r.kstep, &r.tag, &r.n_items_dev, &r.prio};
         return hipModuleLaunchKernel(L.jit->lane, r.grid, 1, 1, kWave, 1, 1, (unsigned)r.lds, st,
                                      args, nullptr);
     }
@@ -1544,30 +1599,23 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
             return fail(TISSUE_EINVAL, "batch members must share the splitting scheme");
     // chi items: room for the largest cut of every member's classes
     for (int32_t i = 0; i < n; ++i) B.chi_cap += ts[i]->plan.n_chi_items;
-    // S: pass 0 holds all edges of members with disjoint faces and class 0
-    // of the others; pass c > 0 holds class c of the others
+    // S: pass c holds every member's pass c (a member with disjoint face
+    // groups has one pass)
     int max_pass = 0;
     for (int32_t i = 0; i < n; ++i) {
         const Plan &p = ts[i]->plan;
         if (!p.has_s || p.nedge == 0) continue;
-        max_pass = std::max(max_pass, p.disjoint ? 1 : (int)p.class_start.size() - 1);
+        max_pass = std::max(max_pass, (int)p.pass_start.size() - 1);
     }
     B.s_passes.assign(max_pass, {});
     B.s_fix.assign(max_pass, -1);
     for (int32_t i = 0; i < n; ++i) {
         const Plan &p = ts[i]->plan;
         if (!p.has_s || p.nedge == 0) continue;
-        for (int c = 0; c < (p.disjoint ? 1 : (int)p.class_start.size() - 1); ++c)
+        for (size_t c = 0; c + 1 < p.pass_start.size(); ++c) {
             B.s_fix[c] = B.s_fix[c] < 0 || B.s_fix[c] == p.face_kind ? p.face_kind : 0;
-        auto cut = [&](uint32_t lo, uint32_t hi, std::vector<SItem> &out) {
-            for (uint32_t o = lo; o < hi; o += kWave)
-                out.push_back(SItem{(uint32_t)i, o, std::min<uint32_t>(kWave, hi - o), 0});
-        };
-        if (p.disjoint) {
-            cut(0, p.nedge, B.s_passes[0]);
-        } else {
-            for (size_t c = 0; c + 1 < p.class_start.size(); ++c)
-                cut(p.class_start[c], p.class_start[c + 1], B.s_passes[c]);
+            for (uint32_t o = p.pass_start[c]; o < p.pass_start[c + 1]; o += kWave)
+                B.s_passes[c].push_back(SItem{(uint32_t)i, o, std::min<uint32_t>(kWave, p.pass_start[c + 1] - o), 0});
         }
     }
     for (int &f : B.s_fix) f = std::max(f, 0);

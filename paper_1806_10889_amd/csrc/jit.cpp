@@ -97,11 +97,11 @@ std::string network_source(const DevModel &M)
       << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane(\n"
       << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
       << "    int persistent, int cells_per_item, int log2p, double dt, uint32_t kstep,\n"
-      << "    uint32_t tag, uint32_t *n_items_dev)\n"
+      << "    uint32_t tag, uint32_t *n_items_dev, int prio)\n"
       << "{\n"
       << "    extern __shared__ __align__(16) unsigned char lds[];\n"
       << "    tissue_impl::chi_lane_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
-      << "        persistent, cells_per_item, log2p, dt, kstep, tag, n_items_dev);\n"
+      << "        persistent, cells_per_item, log2p, dt, kstep, tag, n_items_dev, prio);\n"
       << "}\n"
       ;
     for (int gl : {1, 2, 4}) {
@@ -109,12 +109,12 @@ std::string network_source(const DevModel &M)
           << (gl == 1 ? std::string() : "x" + std::to_string(gl)) << "(\n"
           << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
           << "    int persistent, int cells_per_item, double dt, uint32_t kstep, uint32_t tag,\n"
-          << "    ChiItem *retry_items, uint32_t *retry_count)\n"
+          << "    ChiItem *retry_items, uint32_t *retry_count, int prio)\n"
           << "{\n"
           << "    extern __shared__ __align__(16) unsigned char lds[];\n"
           << "    tissue_impl::chi_lane16_body<tissue_impl::NetCompiled, " << gl
           << ">(lds, tbl, items, n_items,\n"
-          << "        queue, persistent, cells_per_item, dt, kstep, tag, retry_items, retry_count);\n"
+          << "        queue, persistent, cells_per_item, dt, kstep, tag, retry_items, retry_count, prio);\n"
           << "}\n";
     }
     o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_lane16r(\n"
@@ -130,12 +130,12 @@ std::string network_source(const DevModel &M)
         o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row"
           << (rw == 16 ? std::string() : std::to_string(rw)) << "(\n"
           << "    const DevTissue *const *tbl, const ChiItem *items, uint32_t n_items, uint32_t *queue,\n"
-          << "    int persistent, double dt, uint32_t kstep, uint32_t tag)\n"
+          << "    int persistent, double dt, uint32_t kstep, uint32_t tag, int prio)\n"
           << "{\n"
           << "    __shared__ tissue_impl::RowShared sh;\n"
           << "    tissue_impl::chi_row_body<tissue_impl::NetCompiled, " << rw
           << ">(sh, tbl, items, n_items, queue,\n"
-          << "        persistent, dt, kstep, tag);\n"
+          << "        persistent, dt, kstep, tag, prio);\n"
           << "}\n";
     }
     return o.str();

@@ -34,6 +34,7 @@ struct ChiArgs {
     uint32_t *n_items_dev;   // lane mode: item count in device memory, or null
     ChiItem *retry_items;    // lane16: cells to redo at full width
     uint32_t *retry_count;
+    int prio;                // nonzero: the launch's wavefronts issue at a raised priority
 };
 // Table sizes (species slots, reaction slots, diffusion slots) the kernels
 // are instantiated for, for a network of S species, R reactions and ND

@@ -148,7 +148,8 @@ void check_launches(const Plan &p, const std::vector<ChiItem> &items,
             for (uint32_t q = 0; q < it.count && it.first + q < p.ncell; ++q) {
                 const int32_t cell = p.cell_list[it.first + q];
                 const int V = p.wh[2 * cell] * p.wh[2 * cell + 1];
-                check(pow2_at_least(V) == L.P, "cell of another leaf class", trial);
+                check(pow2_at_least(V) <= L.P && (L.P == pow2_at_least(V) || L.P == 16),
+                      "cell of another leaf class", trial);
                 check((int)p.cell_model[cell] == (int)it.model, "cell of another network", trial);
                 seen[cell]++;
             }
@@ -164,12 +165,46 @@ void check_launches(const Plan &p, const std::vector<ChiItem> &items,
     check(items.size() <= p.n_chi_items, "items over the plan's room", trial);
 }
 
+// The S passes keep every pair of edges that share a voxel in colour-class
+// order (an earlier class's edge in an earlier pass), every edge is in one
+// pass, and the records' ranks are a permutation of the edge ranks.
+void check_passes(const Plan &p, int trial)
+{
+    if (!p.has_s || p.nedge == 0) return;
+    const std::vector<Edge> E = lattice_edges((int)p.lattice, (int)p.nx, (int)p.ny);
+    check(E.size() == p.nedge && p.pass_start.back() == p.nedge, "pass ranges", trial);
+    std::vector<int> pass_of(p.nedge, -1), seen(p.nedge, 0);
+    for (size_t l = 0; l + 1 < p.pass_start.size(); ++l)
+        for (uint32_t k = p.pass_start[l]; k < p.pass_start[l + 1]; ++k) pass_of[k] = (int)l;
+    // per voxel: (colour, pass) of the edges touching it
+    std::vector<std::vector<std::pair<int, int>>> at(p.nvox);
+    for (uint32_t k = 0; k < p.nedge; ++k) {
+        const EdgeRec &r = p.edges[k];
+        if (r.id >= p.nedge) {
+            check(false, "edge rank out of range", trial);
+            return;
+        }
+        seen[r.id]++;
+        const int colour = E[r.id].colour;
+        for (int q = 0; q < r.m_a; ++q) at[r.vox_i + r.A[q]].push_back({colour, pass_of[k]});
+        for (int q = 0; q < r.m_b; ++q) at[r.vox_j + r.B[q]].push_back({colour, pass_of[k]});
+    }
+    for (uint32_t e = 0; e < p.nedge; ++e) check(seen[e] == 1, "edge ranks not a permutation", trial);
+    for (const auto &v : at)
+        for (size_t a = 0; a < v.size(); ++a)
+            for (size_t b = 0; b < v.size(); ++b)
+                if (v[a].first < v[b].first)
+                    check(v[a].second < v[b].second, "shared voxel out of class order", trial);
+                else if (a != b && v[a].first == v[b].first)
+                    check(false, "two edges of one class share a voxel", trial);
+}
+
 }  // namespace
 
 int main()
 {
     std::mt19937_64 g(20261203);
-    int planned = 0, rejected = 0;
+    int planned = 0, rejected = 0, overlapping = 0;
     std::vector<std::unique_ptr<tissue>> keep;
     for (int trial = 0; trial < 300; ++trial) {
         Case c;
@@ -184,6 +219,8 @@ int main()
         ++planned;
         const Plan &p = t->plan;
         check(tissue_required_bytes(&c.d) == p.bytes, "required bytes", trial);
+        check_passes(p, trial);
+        if (!p.disjoint) ++overlapping;
         check(p.cell_list.size() == p.ncell, "cell list", trial);
         for (int mode = kModeLane; mode <= kModeRowWide; ++mode)
             for (int regroup = 0; regroup <= 2; ++regroup)
@@ -270,6 +307,8 @@ int main()
         d = good; d.cell_model = cm.data(); bad("cell model out of range", d);
         std::printf("broken descriptors rejected: %d\n", broken);
     }
-    std::printf("planned %d, rejected %d, failures %d\n", planned, rejected, fails);
+    check(overlapping > 10, "few tissues with overlapping face groups", -1);
+    std::printf("planned %d (%d with overlapping face groups), rejected %d, failures %d\n", planned,
+                overlapping, rejected, fails);
     return fails ? 1 : 0;
 }
