@@ -87,7 +87,78 @@ PEAK_HBM = 8.0e12
 # again.
 FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
-COUNTERS = {}
+COUNTERS = {
+    "plain": {
+        "digest": "27bab57622db1bbdfe3954f1add34582a4431e94",
+        "profile": "profiles/chi_row_plain_hex64x64_4x4.md",
+        "chi_events_per_step": 744850.5,
+        "kernels": {
+            "tissue_chi_row": {
+                "dispatches_per_step": 1.0,
+                "avg_us": 170.494,
+                "sq_insts_valu": 46678900.0,
+                "fetch_kib": 930.676,
+                "write_kib": 1376.0
+            }
+        }
+    },
+    "batched": {
+        "digest": "27bab57622db1bbdfe3954f1add34582a4431e94",
+        "profile": "profiles/chi_lane16_batched_512_tissues.md",
+        "chi_events_per_step": 1298376166.0,
+        "kernels": {
+            "tissue_chi_lane16": {
+                "dispatches_per_step": 1.0,
+                "avg_us": 19831.102,
+                "sq_insts_valu": 10691200000.0,
+                "fetch_kib": 652427.0,
+                "write_kib": 1058600.0
+            }
+        }
+    },
+    "uneven": {
+        "digest": "27bab57622db1bbdfe3954f1add34582a4431e94",
+        "profile": "profiles/chi_classes_uneven_hex256x256.md",
+        "chi_events_per_step": 22521846.2,
+        "kernels": {
+            "tissue_chi_row64": {
+                "dispatches_per_step": 1.0,
+                "avg_us": 1228.179,
+                "sq_insts_valu": 327004000.0,
+                "fetch_kib": 883.967,
+                "write_kib": 1222.38
+            },
+            "tissue_chi_lane16x4": {
+                "dispatches_per_step": 1.0,
+                "avg_us": 1516.126,
+                "sq_insts_valu": 91581300.0,
+                "fetch_kib": 2411.35,
+                "write_kib": 3341.4
+            },
+            "tissue_chi_lane16x2": {
+                "dispatches_per_step": 1.0,
+                "avg_us": 1040.597,
+                "sq_insts_valu": 141728000.0,
+                "fetch_kib": 7338.27,
+                "write_kib": 10512.2
+            },
+            "tissue_chi_lane16": {
+                "dispatches_per_step": 1.0,
+                "avg_us": 538.694,
+                "sq_insts_valu": 74518900.0,
+                "fetch_kib": 8812.66,
+                "write_kib": 11674.2
+            },
+            "tissue_chi_lane": {
+                "dispatches_per_step": 3.0,
+                "avg_us": 8.928,
+                "sq_insts_valu": 27655.0,
+                "fetch_kib": 22.7724,
+                "write_kib": 16.0938
+            }
+        }
+    }
+}
 
 
 def kernel_source_digest() -> str:
@@ -104,12 +175,14 @@ def kernel_source_digest() -> str:
 
 def counter_figures(leg: str, kernels=None, live_s_per_step=None):
     """VALU busy, issued lane-slots per event and HBM bytes of the leg's chi
-    kernels (one dispatch of each per step) from the committed counter
-    figures, or None when they were taken on other sources.  VALU busy =
+    kernels (per step: dispatches_per_step of each, default one) from the
+    committed counter figures, or None when they were taken on other
+    sources.  VALU busy =
     SQ_INSTS_VALU x 4 cycles / (SIMDs x the dispatch's own duration in that
     run x clock); lane-slots per event = SQ_INSTS_VALU x 64 / chi events
     per step; HBM fraction = the scaled FETCH + WRITE bytes over the live
-    time per step (or the counter run's duration) / 8 TB/s."""
+    time per step (or the counter run's duration) / 8 TB/s; valu_busy_live =
+    the same instructions over the live time per step."""
     rec = COUNTERS.get(leg)
     if not rec or rec["digest"] != kernel_source_digest():
         return None
@@ -117,11 +190,14 @@ def counter_figures(leg: str, kernels=None, live_s_per_step=None):
     ks = [rec["kernels"][k] for k in kernels if k in rec["kernels"]]
     if not kernels or len(ks) != len(kernels):
         return None
-    valu = sum(k["sq_insts_valu"] for k in ks)
-    dur = sum(k["avg_us"] for k in ks) * 1e-6
-    traffic = 1024.0 * sum(k["fetch_kib"] * FETCH_SCALE + k["write_kib"] * WRITE_SCALE for k in ks)
+    per = [k.get("dispatches_per_step", 1) for k in ks]
+    valu = sum(n * k["sq_insts_valu"] for n, k in zip(per, ks))
+    dur = sum(n * k["avg_us"] for n, k in zip(per, ks)) * 1e-6
+    traffic = 1024.0 * sum(n * (k["fetch_kib"] * FETCH_SCALE + k["write_kib"] * WRITE_SCALE)
+                           for n, k in zip(per, ks))
     t = live_s_per_step or dur
     return {"kernels": list(kernels), "valu_busy": valu * 4.0 / (N_SIMD * dur * CLOCK_HZ),
+            "valu_busy_live": valu * 4.0 / (N_SIMD * t * CLOCK_HZ),
             "issued_lane_slots_per_event": valu * 64.0 / rec["chi_events_per_step"],
             "counter_run_us_per_step": dur * 1e6, "traffic": traffic,
             "hbm_frac": traffic / t / PEAK_HBM, "profile": rec["profile"]}
