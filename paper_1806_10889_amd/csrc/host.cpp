@@ -52,10 +52,11 @@ int hip_fail(hipError_t e, const char *what)
 constexpr size_t kAlign = 256;
 constexpr size_t kChiLdsBudget = 40 * 1024;  // per workgroup: >= 4 resident per CU
 // chi launches of one plan (leaf classes x networks) and their queue words:
-// each launch owns a block of 8 words (item queue, exit count, redo count,
-// redo queue) so that launches of different classes can run concurrently
+// each launch owns a block of kQueueBlockWords words (its per-XCD item
+// queue and exit count, its redo count, its redo launch's queue) so that
+// launches of different classes can run concurrently
 constexpr int kMaxChiLaunches = 64;
-constexpr size_t kLaunchQueueBytes = (size_t)kMaxChiLaunches * 8 * sizeof(uint32_t);
+constexpr size_t kLaunchQueueBytes = (size_t)kMaxChiLaunches * kQueueBlockWords * sizeof(uint32_t);
 constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kChiStaticLds = 512;  // the chi kernels' static LDS (channel table), rounded up
 constexpr int kDefaultRefillMin = 0;
@@ -550,7 +551,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     p.off_models = take(p.models.size() * sizeof(DevModel));
     p.off_chi = take(p.n_chi_items * sizeof(ChiItem));
     p.off_s = take(p.n_s_items * sizeof(SItem));
-    p.off_ctl = take(64);  // stats[3] u64, flags[2] u32, queue words u32[8]
+    p.off_ctl = take(64);  // stats[3] u64, flags[2] u32
     p.off_lq = take(kLaunchQueueBytes);  // per-launch queue words of the chi launches
     p.off_load = take((size_t)p.ncell * 4);  // per-cell load: the regroup pass's key
     p.off_retry = take((size_t)p.ncell * sizeof(ChiItem));  // lane16 cells to redo
@@ -791,12 +792,11 @@ struct LaunchPlan {
     ChiItem *chi_items = nullptr;  // device region for chi work items
     size_t chi_items_cap = 0;
     ChiItem *retry_items = nullptr;  // device region: compact-layout cells to redo (one per cell)
-    uint32_t *lq = nullptr;     // device: 8 queue words per chi launch
+    uint32_t *lq = nullptr;     // device: kQueueBlockWords queue words per chi launch
     int chi_mode = kModeAuto;
     int regroup = 2;            // regroup pass before compact launches: 0 off, 1 on, 2 automatic
     std::vector<ChiLaunch> chi;
     std::vector<SLaunch> s;
-    uint32_t *queue = nullptr;  // device: [0] next item, [1] workgroups done
     hipStream_t stream = nullptr;
     int persistent = 1;
     bool strang = false;        // chi over dt/2 (tag 0), S over dt, chi over dt/2 (tag 2)
@@ -855,7 +855,7 @@ struct LaunchPlan {
     hipError_t launch_chi_any(const ChiLaunch &L, uint32_t grid, hipStream_t st, double dt,
                               uint32_t kstep, uint32_t tag, bool regrouped = false)
     {
-        uint32_t *const q = lq + 8 * (size_t)(&L - chi.data());
+        uint32_t *const q = lq + kQueueBlockWords * (size_t)(&L - chi.data());
         if (L.n_segs && !regrouped) {  // regroup the class's cells by load first (same stream)
             const hipError_t er = launch_regroup(st, tbl, L.segs, L.n_segs);
             if (er != hipSuccess) return er;
@@ -1013,7 +1013,7 @@ struct LaunchPlan {
                 // the chi launch shape (its face-count gathers wait on memory,
                 // and many resident workgroups hide that better than a
                 // persistent grid: 2 % on the batched sweep)
-                HIP_TRY(launch_s(L.n_items, st, tbl, L.items, L.n_items, queue, 0, dt, (uint32_t)k, L.fix));
+                HIP_TRY(launch_s(st, tbl, L.items, L.n_items, dt, (uint32_t)k, L.fix));
                 if (ev) {
                     HIP_TRY(hipEventRecord((*ev)[e++], st));
                     kind->push_back(-1);
@@ -1333,7 +1333,6 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     LaunchPlan &L = t->lp;
     L.tbl = reinterpret_cast<DevTissue **>(base + p.off_tbl);
     L.n_tissues = 1;
-    L.queue = reinterpret_cast<uint32_t *>(base + p.off_ctl + 32);
     L.lq = reinterpret_cast<uint32_t *>(base + p.off_lq);
     L.stream = st;
     L.cus = cus;
@@ -1576,7 +1575,7 @@ int tissue_destroy(tissue_t *t)
 namespace {
 
 struct BatchLayout {
-    size_t off_tbl = 0, off_queue = 0, off_lq = 0, off_chi = 0, off_s = 0, off_retry = 0, bytes = 0;
+    size_t off_tbl = 0, off_lq = 0, off_chi = 0, off_s = 0, off_retry = 0, bytes = 0;
     size_t chi_cap = 0;
     std::vector<std::vector<SItem>> s_passes;
     std::vector<int> s_fix;  // per pass: the face-group kind shared by every member in it, or 0
@@ -1628,7 +1627,6 @@ int plan_batch(tissue_t *const *ts, int32_t n, BatchLayout &B)
         return at;
     };
     B.off_tbl = take((size_t)n * sizeof(DevTissue *));
-    B.off_queue = take(64);
     B.off_lq = take(kLaunchQueueBytes);
     B.off_chi = take(B.chi_cap * sizeof(ChiItem));
     B.off_s = take(n_s * sizeof(SItem));
@@ -1678,7 +1676,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
         const size_t up = B.off_s + s_all.size() * sizeof(SItem);
         HIP_TRY(staging_acquire(lk, up, &h));
         std::memcpy(h + B.off_tbl, tbl.data(), tbl.size() * sizeof(DevTissue *));
-        std::memset(h + B.off_queue, 0, B.off_chi - B.off_queue);
+        std::memset(h + B.off_lq, 0, B.off_chi - B.off_lq);
         if (!s_all.empty()) std::memcpy(h + B.off_s, s_all.data(), s_all.size() * sizeof(SItem));
         HIP_TRY(hipMemcpyAsync(b->dev, h, up, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -1686,7 +1684,6 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     LaunchPlan &L = b->lp;
     L.tbl = reinterpret_cast<DevTissue **>(b->dev + B.off_tbl);
     L.n_tissues = (uint32_t)n;
-    L.queue = reinterpret_cast<uint32_t *>(b->dev + B.off_queue);
     L.lq = reinterpret_cast<uint32_t *>(b->dev + B.off_lq);
     L.stream = st;
     L.cus = cus;
@@ -1752,7 +1749,7 @@ int tissue_batch_set_members(tissue_batch_t *b, tissue_t *const *ts, int32_t n)
             DevTissue *rec = ts[i]->d_rec();
             std::memcpy(h + B.off_tbl + (size_t)i * sizeof(DevTissue *), &rec, sizeof(rec));
         }
-        std::memset(h + B.off_queue, 0, B.off_chi - B.off_queue);
+        std::memset(h + B.off_lq, 0, B.off_chi - B.off_lq);
         if (!items.empty()) std::memcpy(h + B.off_chi, items.data(), items.size() * sizeof(ChiItem));
         if (!s_all.empty()) std::memcpy(h + B.off_s, s_all.data(), s_all.size() * sizeof(SItem));
         // members on other streams: the batch's stream waits for their work so far
@@ -1769,7 +1766,6 @@ int tissue_batch_set_members(tissue_batch_t *b, tissue_t *const *ts, int32_t n)
     L.clear_graphs();
     L.tbl = reinterpret_cast<DevTissue **>(b->dev + B.off_tbl);
     L.n_tissues = (uint32_t)n;
-    L.queue = reinterpret_cast<uint32_t *>(b->dev + B.off_queue);
     L.lq = reinterpret_cast<uint32_t *>(b->dev + B.off_lq);
     L.members = plans;
     L.strang = n > 0 ? ts[0]->plan.strang : L.strang;
@@ -1955,7 +1951,6 @@ int tissue_batch_step_static(tissue_t *const *ts, int32_t n, double dt, int32_t 
         return at;
     };
     const size_t off_tbl = take((size_t)n * sizeof(DevTissue *));
-    const size_t off_queue = take(64);
     const size_t off_lq = take(kLaunchQueueBytes);
     const size_t off_chi = take(items.size() * sizeof(ChiItem));
     const size_t off_s = take(s_all.size() * sizeof(SItem));
@@ -1984,7 +1979,6 @@ int tissue_batch_step_static(tissue_t *const *ts, int32_t n, double dt, int32_t 
 
     L.tbl = reinterpret_cast<DevTissue **>(ws + off_tbl);
     L.n_tissues = (uint32_t)n;
-    L.queue = reinterpret_cast<uint32_t *>(ws + off_queue);
     L.lq = reinterpret_cast<uint32_t *>(ws + off_lq);
     L.stream = st;
     L.cus = cus;

@@ -96,10 +96,20 @@ struct ChiItem {
 // outgrow 16 bits
 enum ChiMode { kChiLane = 0, kChiRow = 1, kChiLane16 = 2 };
 
-// device control words of a launch plan (uint32 each): the persistent queue
-// of the main launches, the retry count of lane16 launches, and the queue of
-// the follow-up (retry) launches
-enum { kQNext = 0, kQDone = 1, kQRetry = 2, kQRetryNext = 4, kQRetryDone = 5 };
+// XCDs of the device: workgroups are dealt to them in turn (workgroup b to
+// XCD b mod 8), each with its own L2
+constexpr uint32_t kXcds = 8;
+
+// device control words of one chi launch (uint32 each): the persistent
+// queue of the main launch (one counter per XCD, then the count of
+// workgroups that left), the redo count of a compact launch, and the queue
+// of its redo launch (laid out as the main queue)
+enum {
+    kQNext = 0,
+    kQRetry = kXcds + 1,
+    kQRetryNext = 16,
+    kQueueBlockWords = 32
+};
 
 // up to 64 consecutive edges [first, first + count) of one tissue
 struct SItem {

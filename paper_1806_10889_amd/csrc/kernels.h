@@ -49,11 +49,11 @@ hipError_t launch_chi_part1(int RM, const ChiArgs &a);
 hipError_t launch_chi_part2(int RM, const ChiArgs &a);
 hipError_t launch_chi_part3(int RM, const ChiArgs &a);
 hipError_t launch_chi_part4(int RM, const ChiArgs &a);
-// fix = 2 or 1: every edge of the launch has face groups of 2 and 2 (1 and 1)
-// voxels, the kernel specialised for them; 0: any face groups.
-hipError_t launch_s(uint32_t grid, hipStream_t stream, const DevTissue *const *tbl,
-                    const SItem *items, uint32_t n_items, uint32_t *queue, int persistent,
-                    double dt, uint32_t kstep, int fix);
+// One workgroup per item of up to 64 edges.  fix = 2 or 1: every edge of
+// the launch has face groups of 2 and 2 (1 and 1) voxels, the kernel
+// specialised for them; 0: any face groups.
+hipError_t launch_s(hipStream_t stream, const DevTissue *const *tbl, const SItem *items,
+                    uint32_t n_items, double dt, uint32_t kstep, int fix);
 hipError_t launch_advance(hipStream_t stream, DevTissue *const *tbl, uint32_t n_tissues,
                           uint32_t n);
 // Cells per regroup segment: a class's cells of one tissue are regrouped in

@@ -26,7 +26,6 @@ namespace {
 // of the items (a bijection on 0..n-1).
 __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n)
 {
-    constexpr uint32_t kXcds = 8;
     const uint32_t x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
     return x * q + min(x, r) + k;
 }
@@ -184,8 +183,7 @@ __device__ __forceinline__ void s_edge_fixed(int32_t *counts, long long gi, long
 // wavefronts); FIX = 0: any sizes, the general path in LDS for the others.
 template <int FIX>
 __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, const SItem *items,
-                                                  uint32_t n_items, uint32_t *queue,
-                                                  int persistent, double dt, uint32_t kstep)
+                                                  uint32_t n_items, double dt, uint32_t kstep)
 {
     // per lane: N, D, I of face A (cell i) then of face B (cell j)
     __shared__ int32_t fa[3][kMaxFace][kWave];
@@ -194,96 +192,144 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
     // one workgroup per item: consecutive items on one XCD (workgroups are
     // dealt to the XCDs in turn), so that the edges around a cell share that
     // XCD's L2
-    uint32_t cursor = persistent ? blockIdx.x : xcd_contiguous(blockIdx.x, gridDim.x);
-    for (;;) {
-        const uint32_t it = next_item(queue, persistent != 0, cursor);
-        if (it >= n_items) break;
-        const SItem item = items[it];
-        const DevTissue *T = tbl[uni(item.tissue)];
-        const int S = uni(T->model.n_species);
-        const int sp0 = uni(T->model.trans_n), sp1 = uni(T->model.trans_d), sp2 = uni(T->model.trans_i);
-        // first order: D_i -> I_j into the facing voxel, N unused (slot 0 idle)
-        const bool first_order = uni(T->model.signal_order) == 1;
-        const double c = uni(T->model.trans_rate);
-        const uint32_t first = uni(item.first), count = uni(item.count);
-        const uint32_t step = uni(T->step_base) + kstep;
-        const uint64_t seed = uni((uint64_t)T->seed);
-        const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
-        const uint32_t tagword = (uni(T->sim_id) << 2) | 1u;
-        const uint32_t cap = uni(T->event_cap);
-        int32_t *counts = T->counts;
-        const bool active = lane < (int)count;
-        double t = 0.0;
-        uint32_t j = 0, ev = 0, e = 0;
-        bool overflow = false, capped = false;
-        if (active) {
-            const EdgeRec *er = T->edges + (first + lane);
-            e = er->id;  // the edge's rank: its counters and trace slot
-            const int mA = er->m_a, mB = er->m_b;
-            // first order: each side's molecules signal at their own
-            // cell's network's rate (the tissue's rate without per-cell models)
-            const double ci = T->models[er->model_i].trans_rate;
-            const double cj = T->models[er->model_j].trans_rate;
-            const long long gi = (long long)er->vox_i, gj = (long long)er->vox_j;
-            uint8_t A[kMaxFace], B[kMaxFace];
+    const uint32_t it = xcd_contiguous(blockIdx.x, gridDim.x);
+    if (it >= n_items) return;
+    const SItem item = items[it];
+    const DevTissue *T = tbl[uni(item.tissue)];
+    const int S = uni(T->model.n_species);
+    const int sp0 = uni(T->model.trans_n), sp1 = uni(T->model.trans_d), sp2 = uni(T->model.trans_i);
+    // first order: D_i -> I_j into the facing voxel, N unused (slot 0 idle)
+    const bool first_order = uni(T->model.signal_order) == 1;
+    const double c = uni(T->model.trans_rate);
+    const uint32_t first = uni(item.first), count = uni(item.count);
+    const uint32_t step = uni(T->step_base) + kstep;
+    const uint64_t seed = uni((uint64_t)T->seed);
+    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+    const uint32_t tagword = (uni(T->sim_id) << 2) | 1u;
+    const uint32_t cap = uni(T->event_cap);
+    int32_t *counts = T->counts;
+    const bool active = lane < (int)count;
+    double t = 0.0;
+    uint32_t j = 0, ev = 0, e = 0;
+    bool overflow = false, capped = false;
+    if (active) {
+        const EdgeRec *er = T->edges + (first + lane);
+        e = er->id;  // the edge's rank: its counters and trace slot
+        const int mA = er->m_a, mB = er->m_b;
+        // first order: each side's molecules signal at their own
+        // cell's network's rate (the tissue's rate without per-cell models)
+        const double ci = T->models[er->model_i].trans_rate;
+        const double cj = T->models[er->model_j].trans_rate;
+        const long long gi = (long long)er->vox_i, gj = (long long)er->vox_j;
+        uint8_t A[kMaxFace], B[kMaxFace];
 #pragma unroll
-            for (int a = 0; a < kMaxFace; ++a) {
-                A[a] = er->A[a];
-                B[a] = er->B[a];
+        for (int a = 0; a < kMaxFace; ++a) {
+            A[a] = er->A[a];
+            B[a] = er->B[a];
+        }
+        // face groups of 2 and 2 voxels (4x4 cells on the hexagonal
+        // lattice) and of 1 and 1 (well-mixed cells): counts in registers
+        const int fixed = FIX ? FIX : (mA == 2 && mB == 2) ? 2 : (mA == 1 && mB == 1) ? 1 : 0;
+        if (fixed == 2)
+            s_edge_fixed<2, 2>(counts, gi, gj, A, B, S, sp0, sp1, sp2, first_order, c, ci, cj, dt,
+                               step, e, tagword, key0, key1, cap, t, j, ev, overflow, capped);
+        else if (fixed == 1)
+            s_edge_fixed<1, 1>(counts, gi, gj, A, B, S, sp0, sp1, sp2, first_order, c, ci, cj, dt,
+                               step, e, tagword, key0, key1, cap, t, j, ev, overflow, capped);
+#pragma unroll
+        for (int a = 0; a < kMaxFace; ++a)
+            if (fixed == 0 && a < mA) {
+                const long long g = (gi + A[a]) * S;
+                if (!first_order) fa[0][a][lane] = counts[g + sp0];
+                fa[1][a][lane] = counts[g + sp1];
+                fa[2][a][lane] = counts[g + sp2];
             }
-            // face groups of 2 and 2 voxels (4x4 cells on the hexagonal
-            // lattice) and of 1 and 1 (well-mixed cells): counts in registers
-            const int fixed = FIX ? FIX : (mA == 2 && mB == 2) ? 2 : (mA == 1 && mB == 1) ? 1 : 0;
-            if (fixed == 2)
-                s_edge_fixed<2, 2>(counts, gi, gj, A, B, S, sp0, sp1, sp2, first_order, c, ci, cj, dt,
-                                   step, e, tagword, key0, key1, cap, t, j, ev, overflow, capped);
-            else if (fixed == 1)
-                s_edge_fixed<1, 1>(counts, gi, gj, A, B, S, sp0, sp1, sp2, first_order, c, ci, cj, dt,
-                                   step, e, tagword, key0, key1, cap, t, j, ev, overflow, capped);
 #pragma unroll
-            for (int a = 0; a < kMaxFace; ++a)
-                if (fixed == 0 && a < mA) {
-                    const long long g = (gi + A[a]) * S;
-                    if (!first_order) fa[0][a][lane] = counts[g + sp0];
-                    fa[1][a][lane] = counts[g + sp1];
-                    fa[2][a][lane] = counts[g + sp2];
+        for (int b = 0; b < kMaxFace; ++b)
+            if (fixed == 0 && b < mB) {
+                const long long g = (gj + B[b]) * S;
+                if (!first_order) fb[0][b][lane] = counts[g + sp0];
+                fb[1][b][lane] = counts[g + sp1];
+                fb[2][b][lane] = counts[g + sp2];
+            }
+        const int half = mA * mB;
+        // first order: channels ci D_i(a) for a in A, then cj D_j(b) for
+        // b in B; a Delta of face voxel k of one group becomes an NICD in
+        // voxel m' - 1 - floor(k m' / m) of the other (they run in
+        // opposite directions along the shared face)
+        while (fixed == 0 && first_order) {
+            double a0 = 0.0;
+            for (int a = 0; a < mA; ++a) a0 = a0 + ci * (double)fa[1][a][lane];
+            for (int b = 0; b < mB; ++b) a0 = a0 + cj * (double)fb[1][b][lane];
+            if (a0 == 0.0) break;
+            if (ev >= cap) {
+                capped = true;
+                break;
+            }
+            const tdev::Words4 wds = tdev::philox4x32_10(j, step, e, tagword, key0, key1);
+            ++j;
+            double u1, u2;
+            tdev::two_uniforms(wds, u1, u2);
+            const double tau = (-tdev::plog<true>(u1)) / a0;
+            const double tn = t + tau;
+            if (tn >= dt) break;
+            t = tn;
+            const double r = u2 * a0;
+            double prefix = 0.0;
+            int sel = -1, last = -1;
+            for (int k = 0; k < mA + mB; ++k) {
+                const double p = k < mA ? ci * (double)fa[1][k][lane]
+                                        : cj * (double)fb[1][k - mA][lane];
+                const double next = prefix + p;
+                if (p > 0.0) {
+                    if (sel < 0 && r < next) sel = k;
+                    last = k;
                 }
-#pragma unroll
-            for (int b = 0; b < kMaxFace; ++b)
-                if (fixed == 0 && b < mB) {
-                    const long long g = (gj + B[b]) * S;
-                    if (!first_order) fb[0][b][lane] = counts[g + sp0];
-                    fb[1][b][lane] = counts[g + sp1];
-                    fb[2][b][lane] = counts[g + sp2];
-                }
-            const int half = mA * mB;
-            // first order: channels ci D_i(a) for a in A, then cj D_j(b) for
-            // b in B; a Delta of face voxel k of one group becomes an NICD in
-            // voxel m' - 1 - floor(k m' / m) of the other (they run in
-            // opposite directions along the shared face)
-            while (fixed == 0 && first_order) {
-                double a0 = 0.0;
-                for (int a = 0; a < mA; ++a) a0 = a0 + ci * (double)fa[1][a][lane];
-                for (int b = 0; b < mB; ++b) a0 = a0 + cj * (double)fb[1][b][lane];
-                if (a0 == 0.0) break;
-                if (ev >= cap) {
-                    capped = true;
-                    break;
-                }
-                const tdev::Words4 wds = tdev::philox4x32_10(j, step, e, tagword, key0, key1);
-                ++j;
-                double u1, u2;
-                tdev::two_uniforms(wds, u1, u2);
-                const double tau = (-tdev::plog<true>(u1)) / a0;
-                const double tn = t + tau;
-                if (tn >= dt) break;
-                t = tn;
-                const double r = u2 * a0;
-                double prefix = 0.0;
-                int sel = -1, last = -1;
-                for (int k = 0; k < mA + mB; ++k) {
-                    const double p = k < mA ? ci * (double)fa[1][k][lane]
-                                            : cj * (double)fb[1][k - mA][lane];
+                prefix = next;
+            }
+            if (sel < 0) sel = last;
+            int32_t nD, nI;
+            if (sel < mA) {
+                nD = --fa[1][sel][lane];
+                nI = ++fb[2][mB - 1 - (sel * mB) / mA][lane];
+            } else {
+                const int kk = sel - mA;
+                nD = --fb[1][kk][lane];
+                nI = ++fa[2][mA - 1 - (kk * mA) / mB][lane];
+            }
+            overflow |= (nD < 0) | (nI >= kCountLimit);
+            ++ev;
+        }
+        for (;;) {
+            if (fixed != 0 || first_order) break;
+            // channels: N_i(a) D_j(b) for a, b; then N_j(b) D_i(a) for b, a
+            double a0 = 0.0;
+            for (int a = 0; a < mA; ++a)
+                for (int b = 0; b < mB; ++b)
+                    a0 = a0 + c * (double)((long long)fa[0][a][lane] * fb[1][b][lane]);
+            for (int b = 0; b < mB; ++b)
+                for (int a = 0; a < mA; ++a)
+                    a0 = a0 + c * (double)((long long)fb[0][b][lane] * fa[1][a][lane]);
+            if (a0 == 0.0) break;
+            if (ev >= cap) {
+                capped = true;
+                break;
+            }
+            const tdev::Words4 wds = tdev::philox4x32_10(j, step, e, tagword, key0, key1);
+            ++j;
+            double u1, u2;
+            tdev::two_uniforms(wds, u1, u2);
+            const double tau = (-tdev::plog<true>(u1)) / a0;
+            const double tn = t + tau;
+            if (tn >= dt) break;
+            t = tn;
+            const double r = u2 * a0;
+            double prefix = 0.0;
+            int sel = -1, last = -1;
+            int k = 0;
+            for (int a = 0; a < mA; ++a)
+                for (int b = 0; b < mB; ++b, ++k) {
+                    const double p = c * (double)((long long)fa[0][a][lane] * fb[1][b][lane]);
                     const double next = prefix + p;
                     if (p > 0.0) {
                         if (sel < 0 && r < next) sel = k;
@@ -291,118 +337,66 @@ __global__ __launch_bounds__(kWave) void s_kernel(const DevTissue *const *tbl, c
                     }
                     prefix = next;
                 }
-                if (sel < 0) sel = last;
-                int32_t nD, nI;
-                if (sel < mA) {
-                    nD = --fa[1][sel][lane];
-                    nI = ++fb[2][mB - 1 - (sel * mB) / mA][lane];
-                } else {
-                    const int kk = sel - mA;
-                    nD = --fb[1][kk][lane];
-                    nI = ++fa[2][mA - 1 - (kk * mA) / mB][lane];
-                }
-                overflow |= (nD < 0) | (nI >= kCountLimit);
-                ++ev;
-            }
-            for (;;) {
-                if (fixed != 0 || first_order) break;
-                // channels: N_i(a) D_j(b) for a, b; then N_j(b) D_i(a) for b, a
-                double a0 = 0.0;
-                for (int a = 0; a < mA; ++a)
-                    for (int b = 0; b < mB; ++b)
-                        a0 = a0 + c * (double)((long long)fa[0][a][lane] * fb[1][b][lane]);
-                for (int b = 0; b < mB; ++b)
-                    for (int a = 0; a < mA; ++a)
-                        a0 = a0 + c * (double)((long long)fb[0][b][lane] * fa[1][a][lane]);
-                if (a0 == 0.0) break;
-                if (ev >= cap) {
-                    capped = true;
-                    break;
-                }
-                const tdev::Words4 wds = tdev::philox4x32_10(j, step, e, tagword, key0, key1);
-                ++j;
-                double u1, u2;
-                tdev::two_uniforms(wds, u1, u2);
-                const double tau = (-tdev::plog<true>(u1)) / a0;
-                const double tn = t + tau;
-                if (tn >= dt) break;
-                t = tn;
-                const double r = u2 * a0;
-                double prefix = 0.0;
-                int sel = -1, last = -1;
-                int k = 0;
-                for (int a = 0; a < mA; ++a)
-                    for (int b = 0; b < mB; ++b, ++k) {
-                        const double p = c * (double)((long long)fa[0][a][lane] * fb[1][b][lane]);
-                        const double next = prefix + p;
-                        if (p > 0.0) {
-                            if (sel < 0 && r < next) sel = k;
-                            last = k;
-                        }
-                        prefix = next;
+            for (int b = 0; b < mB; ++b)
+                for (int a = 0; a < mA; ++a, ++k) {
+                    const double p = c * (double)((long long)fb[0][b][lane] * fa[1][a][lane]);
+                    const double next = prefix + p;
+                    if (p > 0.0) {
+                        if (sel < 0 && r < next) sel = k;
+                        last = k;
                     }
-                for (int b = 0; b < mB; ++b)
-                    for (int a = 0; a < mA; ++a, ++k) {
-                        const double p = c * (double)((long long)fb[0][b][lane] * fa[1][a][lane]);
-                        const double next = prefix + p;
-                        if (p > 0.0) {
-                            if (sel < 0 && r < next) sel = k;
-                            last = k;
-                        }
-                        prefix = next;
-                    }
-                if (sel < 0) sel = last;
-                int32_t nN, nD, nI;
-                if (sel < half) {
-                    const int a = sel / mB, b = sel - (sel / mB) * mB;
-                    nN = --fa[0][a][lane];
-                    nD = --fb[1][b][lane];
-                    nI = ++fa[2][a][lane];
-                } else {
-                    const int kk = sel - half;
-                    const int b = kk / mA, a = kk - (kk / mA) * mA;
-                    nN = --fb[0][b][lane];
-                    nD = --fa[1][a][lane];
-                    nI = ++fb[2][b][lane];
+                    prefix = next;
                 }
-                overflow |= (nN < 0) | (nD < 0) | (nI >= kCountLimit);
-                ++ev;
+            if (sel < 0) sel = last;
+            int32_t nN, nD, nI;
+            if (sel < half) {
+                const int a = sel / mB, b = sel - (sel / mB) * mB;
+                nN = --fa[0][a][lane];
+                nD = --fb[1][b][lane];
+                nI = ++fa[2][a][lane];
+            } else {
+                const int kk = sel - half;
+                const int b = kk / mA, a = kk - (kk / mA) * mA;
+                nN = --fb[0][b][lane];
+                nD = --fa[1][a][lane];
+                nI = ++fb[2][b][lane];
             }
-#pragma unroll
-            for (int a = 0; a < kMaxFace; ++a)
-                if (fixed == 0 && a < mA) {
-                    const long long g = (gi + A[a]) * S;
-                    if (!first_order) counts[g + sp0] = fa[0][a][lane];
-                    counts[g + sp1] = fa[1][a][lane];
-                    counts[g + sp2] = fa[2][a][lane];
-                }
-#pragma unroll
-            for (int b = 0; b < kMaxFace; ++b)
-                if (fixed == 0 && b < mB) {
-                    const long long g = (gj + B[b]) * S;
-                    if (!first_order) counts[g + sp0] = fb[0][b][lane];
-                    counts[g + sp1] = fb[1][b][lane];
-                    counts[g + sp2] = fb[2][b][lane];
-                }
-            if (T->tr_s_ev) {
-                const uint32_t ts = uni(T->trace_steps), ne = uni(T->n_edges);
-                const size_t slot = (size_t)(step % ts) * ne + e;
-                T->tr_s_ev[slot] = ev;
-                T->tr_s_t[slot] = (unsigned long long)__double_as_longlong(t);
-            }
+            overflow |= (nN < 0) | (nD < 0) | (nI >= kCountLimit);
+            ++ev;
         }
-        const uint32_t ev_sum = wave_sum_u32(ev);
-        const uint32_t dr_sum = wave_sum_u32(j);
-        const bool any_over = __any(overflow);
-        const bool any_cap = __any(capped);
-        if (lane == 0) {
-            if (ev_sum) atomicAdd(T->stats + 1, (unsigned long long)ev_sum);
-            if (dr_sum) atomicAdd(T->stats + 2, (unsigned long long)dr_sum);
-            if (any_over) atomicOr(T->flags + 0, 1u);
-            if (any_cap) atomicOr(T->flags + 1, 1u);
+#pragma unroll
+        for (int a = 0; a < kMaxFace; ++a)
+            if (fixed == 0 && a < mA) {
+                const long long g = (gi + A[a]) * S;
+                if (!first_order) counts[g + sp0] = fa[0][a][lane];
+                counts[g + sp1] = fa[1][a][lane];
+                counts[g + sp2] = fa[2][a][lane];
+            }
+#pragma unroll
+        for (int b = 0; b < kMaxFace; ++b)
+            if (fixed == 0 && b < mB) {
+                const long long g = (gj + B[b]) * S;
+                if (!first_order) counts[g + sp0] = fb[0][b][lane];
+                counts[g + sp1] = fb[1][b][lane];
+                counts[g + sp2] = fb[2][b][lane];
+            }
+        if (T->tr_s_ev) {
+            const uint32_t ts = uni(T->trace_steps), ne = uni(T->n_edges);
+            const size_t slot = (size_t)(step % ts) * ne + e;
+            T->tr_s_ev[slot] = ev;
+            T->tr_s_t[slot] = (unsigned long long)__double_as_longlong(t);
         }
     }
-    leave_queue(queue, persistent != 0);
+    const uint32_t ev_sum = wave_sum_u32(ev);
+    const uint32_t dr_sum = wave_sum_u32(j);
+    const bool any_over = __any(overflow);
+    const bool any_cap = __any(capped);
+    if (lane == 0) {
+        if (ev_sum) atomicAdd(T->stats + 1, (unsigned long long)ev_sum);
+        if (dr_sum) atomicAdd(T->stats + 2, (unsigned long long)dr_sum);
+        if (any_over) atomicOr(T->flags + 0, 1u);
+        if (any_cap) atomicOr(T->flags + 1, 1u);
+    }
 }
 
 // step_base += n for every tissue of the table
@@ -530,19 +524,18 @@ hipError_t launch_chi(int SM, int RM, int NDM, const ChiArgs &a)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_s(uint32_t grid, hipStream_t stream, const DevTissue *const *tbl,
-                    const SItem *items, uint32_t n_items, uint32_t *queue, int persistent,
-                    double dt, uint32_t kstep, int fix)
+hipError_t launch_s(hipStream_t stream, const DevTissue *const *tbl, const SItem *items,
+                    uint32_t n_items, double dt, uint32_t kstep, int fix)
 {
     if (fix == 2)
-        hipLaunchKernelGGL(s_kernel<2>, dim3(grid), dim3(kWave), 0, stream, tbl, items, n_items,
-                           queue, persistent, dt, kstep);
+        hipLaunchKernelGGL(s_kernel<2>, dim3(n_items), dim3(kWave), 0, stream, tbl, items, n_items,
+                           dt, kstep);
     else if (fix == 1)
-        hipLaunchKernelGGL(s_kernel<1>, dim3(grid), dim3(kWave), 0, stream, tbl, items, n_items,
-                           queue, persistent, dt, kstep);
+        hipLaunchKernelGGL(s_kernel<1>, dim3(n_items), dim3(kWave), 0, stream, tbl, items, n_items,
+                           dt, kstep);
     else
-        hipLaunchKernelGGL(s_kernel<0>, dim3(grid), dim3(kWave), 0, stream, tbl, items, n_items,
-                           queue, persistent, dt, kstep);
+        hipLaunchKernelGGL(s_kernel<0>, dim3(n_items), dim3(kWave), 0, stream, tbl, items, n_items,
+                           dt, kstep);
     return hipGetLastError();
 }
 
