@@ -452,31 +452,41 @@ def run_batched(args, torch, T, W):
 def run_tiny(args, torch, T, W):
     """The plain tiny workload: 16 well-mixed cells on a 4x4 square lattice,
     the 4-species network, dt 0.1, T 10 (100 steps) -- a latency case: each
-    simulation is 100 steps of a handful of events per cell, replayed from
-    captured graphs; events/s and the latency per simulation and per step."""
+    simulation is 100 steps of a handful of events per cell.  By default the
+    library runs such a tissue's whole call in one kernel launch; the same
+    simulations step by step (one graph of 100 steps) are reported beside
+    it.  Events/s and the latency per simulation and per step, the restart
+    and the synchronising read of the totals included."""
     p = W.config1()
-    t = T.Tissue(p, device="cuda:0", stream=torch.cuda.current_stream())
-    t.set_launch(False, 0)
-    t.set_graph_chunk(p["n_steps"])
     n = p["n_steps"]
-    t.step(p["dt"], n)  # warm-up: the graph capture
-    t.stats()
-    lat, ev = [], 0
-    for k in range(args.tiny_sims):
-        a = time.perf_counter()
-        t.restart(sim_id=k, start_step=0)
-        t.step(p["dt"], n)
-        st = t.stats()
-        lat.append(time.perf_counter() - a)
-        ev += st["chi_events"] + st["s_events"]
-    t.close()
-    return {"workload": "square 4x4 tissue, 16 well-mixed cells, 4 species, 7+1 reactions, "
-                        "dt=0.1, T=10 (100 splitting steps)",
-            "sims": len(lat), "events_per_s": ev / sum(lat),
-            "sim_latency_ms_p50": pct(lat, 50) * 1e3, "sim_latency_ms_p99": pct(lat, 99) * 1e3,
-            "step_latency_us_p50": pct(lat, 50) * 1e6 / n,
-            "launch": "one workgroup per item, one graph of 100 steps; latency includes the "
-                      "restart and the synchronising read of the totals"}
+
+    def sims(whole):
+        t = T.Tissue(p, device="cuda:0", stream=torch.cuda.current_stream())
+        t.set_launch(False, 0)
+        t.set_graph_chunk(n)
+        t.set_whole_run(whole)
+        assert t.runs_whole() == whole
+        t.step(p["dt"], n)  # warm-up (the graph capture when step by step)
+        t.stats()
+        lat, ev = [], 0
+        for k in range(args.tiny_sims):
+            a = time.perf_counter()
+            t.restart(sim_id=k, start_step=0)
+            t.step(p["dt"], n)
+            st = t.stats()
+            lat.append(time.perf_counter() - a)
+            ev += st["chi_events"] + st["s_events"]
+        t.close()
+        return {"sims": len(lat), "events_per_s": ev / sum(lat),
+                "sim_latency_ms_p50": pct(lat, 50) * 1e3, "sim_latency_ms_p99": pct(lat, 99) * 1e3,
+                "step_latency_us_p50": pct(lat, 50) * 1e6 / n}
+
+    out = {"workload": "square 4x4 tissue, 16 well-mixed cells, 4 species, 7+1 reactions, "
+                       "dt=0.1, T=10 (100 splitting steps)"}
+    out.update(sims(True))
+    out["launch"] = "the whole call in one launch of the whole-run kernel (one workgroup)"
+    out["step_by_step"] = dict(sims(False), launch="one workgroup per item, one graph of 100 steps")
+    return out
 
 
 def run_serving(args, torch, budget_bytes=None, n_requests=None):

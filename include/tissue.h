@@ -271,6 +271,28 @@ int tissue_set_chi_mode(tissue_t *t, int32_t mode);
 /* Steps captured per HIP graph launch (0 disables graphs). */
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph);
 
+/* Small tissues in one launch per call (Algorithm section and Results >
+ * Scaling: at small splitting intervals the scheduling of the per-step tasks
+ * outweighs the tasks themselves).  enable = 1 (the default): when the
+ * tissue's chi operator is one work item of the one-lane-per-cell layout
+ * (at most 64 cells of one leaf class of at most 8 voxels) with a compiled
+ * network, it has at most 8 S passes of at most 2 work items (128 edges)
+ * each, and its state fits 48 KiB, tissue_step runs all its steps in one
+ * workgroup of one kernel (up to 100 steps per launch) with the state
+ * copied into LDS for the call: the chi item, then the S passes in order,
+ * step after step, with the same operations per cell and edge as the
+ * step-by-step launches, so the same bits.  (With more items the one
+ * wavefront would run in sequence what the step-by-step launches run side
+ * by side.)  0: always the step-by-step launches (graphs or eager).
+ * tissue_step_timed always launches step by step.  Other values:
+ * TISSUE_EINVAL.  Synchronises the stream. */
+int tissue_set_whole_run(tissue_t *t, int32_t enable);
+
+/* 1 when tissue_step runs this tissue's steps in the whole-run kernel (it
+ * is enabled and the current plan fits it), 0 when step by step;
+ * TISSUE_EINVAL for a null handle. */
+int tissue_runs_whole(tissue_t *t);
+
 /* Lane refill of compact-layout launches of cells of at most 16 voxels
  * (compiled networks, persistent launches): a wavefront does not wait for
  * the busiest cell of its work item; once min_idle_lanes of its 64 lanes
@@ -337,6 +359,8 @@ int tissue_batch_set_chi_mode(tissue_batch_t *b, int32_t mode);
 int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph);
 int tissue_batch_set_regroup(tissue_batch_t *b, int32_t mode);
 int tissue_batch_set_refill(tissue_batch_t *b, int32_t min_idle_lanes);
+int tissue_batch_set_whole_run(tissue_batch_t *b, int32_t enable);
+int tissue_batch_runs_whole(tissue_batch_t *b);
 int tissue_batch_sync(tissue_batch_t *b);
 /* Replace the batch's members in place (continuous batching: admit and
  * retire tissues between steps) without creating a new batch: the work

@@ -26,7 +26,8 @@ __global__ __launch_bounds__(kWave) void chi_lane_kernel(const DevTissue *const 
 {
     extern __shared__ __align__(16) unsigned char lds[];
     chi_lane_body<NetGeneric<SM, RM, NDM>>(lds, tbl, items, n_items, queue, persistent,
-                                           cells_per_item, log2p, dt, kstep, tag, n_items_dev, prio);
+                                           cells_per_item, log2p, dt, kstep, tag, n_items_dev, prio,
+                                           blockIdx.x);
 }
 
 template <int SM, int RM, int NDM, int G>

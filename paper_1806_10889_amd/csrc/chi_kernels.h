@@ -425,13 +425,14 @@ __device__ __forceinline__ void item_stats(const ItemCtx &c, uint32_t ev, uint32
 // ---------------------------------------------------------------------------
 // n_items_dev: when not null the item count is read from device memory
 // (the retry list of a lane16 launch) and *n_items_dev is cleared by the
-// last workgroup.
+// last workgroup.  first: the item of a workgroup that is not persistent
+// (its index in the grid, or the item a whole-run kernel asks for).
 template <class NET>
 __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissue *const *tbl,
                                               const ChiItem *items, uint32_t n_items, uint32_t *queue,
                                               int persistent, int cells_per_item, int log2p, double dt,
                                               uint32_t kstep, uint32_t tag, uint32_t *n_items_dev,
-                                              int prio)
+                                              int prio, uint32_t first)
 {
     constexpr int SM = NET::SM;
     __shared__ ChanEntry tab[kChanSlots];
@@ -440,7 +441,7 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
     const int lane = threadIdx.x;
     const int stride = cells_per_item;
     const int P = 1 << log2p;
-    uint32_t cursor = blockIdx.x, spent = 0u;
+    uint32_t cursor = first, spent = 0u;
     for (;;) {
         const uint32_t it = next_item(queue, persistent != 0, cursor, n_items, spent);
         if (it >= n_items) break;

@@ -56,6 +56,7 @@ constexpr size_t kChiLdsBudget = 40 * 1024;  // per workgroup: >= 4 resident per
 // queue and exit count, its redo count, its redo launch's queue) so that
 // launches of different classes can run concurrently
 constexpr int kMaxChiLaunches = 64;
+constexpr int32_t kWholeRunSteps = 100;  // steps per launch of the whole-run kernel
 constexpr size_t kLaunchQueueBytes = (size_t)kMaxChiLaunches * kQueueBlockWords * sizeof(uint32_t);
 constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kChiStaticLds = 512;  // the chi kernels' static LDS (channel table), rounded up
@@ -788,6 +789,7 @@ struct GraphKey {
 struct LaunchPlan {
     DevTissue **tbl = nullptr;  // device table of DevTissue pointers
     uint32_t n_tissues = 0;
+    DevTissue *rec0 = nullptr;  // device record of the first member
     std::vector<const Plan *> members;
     ChiItem *chi_items = nullptr;  // device region for chi work items
     size_t chi_items_cap = 0;
@@ -807,6 +809,9 @@ struct LaunchPlan {
     // and a persistent grid: a wavefront refills its idle lanes with new
     // cells once this many are idle (0: never; lanes wait for their item)
     int refill_min = kDefaultRefillMin;
+    // small tissues: every step of a call in one launch of the network's
+    // whole-run kernel (when the plan fits it; 0: never)
+    int whole_run = 1;
     hipStream_t capture_stream = nullptr;
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     // side streams and fork/join events for running the leaf-count classes'
@@ -1064,8 +1069,81 @@ struct LaunchPlan {
         return c;
     }
 
+    // The whole-run kernel's description of this plan: one tissue whose
+    // chi operator is one work item of the one-lane-per-cell layout with a
+    // compiled network, at most kSmallPasses S passes of at most
+    // kSmallItems items, and copies that fit the kernel's LDS (lds: its
+    // dynamic LDS, the chi item's area then the copies, 16-byte aligned).
+    bool small_run(SmallRun &r, const JitKernels *&jk, size_t &lds) const
+    {
+        r = SmallRun{};
+        jk = nullptr;
+        lds = 0;
+        if (n_tissues != 1 || members.size() != 1 || !rec0) return false;
+        const ChiLaunch *one = nullptr;
+        for (const ChiLaunch &L : chi) {
+            if (L.n_items == 0) continue;
+            if (one || L.n_items != 1 || L.mode != kChiLane || !L.jit || !L.jit->run_small) return false;
+            one = &L;
+        }
+        if (!one) return false;
+        jk = one->jit;
+        int log2p = 0;
+        while ((1 << log2p) < one->P) ++log2p;
+        r.chi_item = one->items;
+        r.chi_cells_per_item = one->cells_per_item;
+        r.chi_log2p = log2p;
+        for (const SLaunch &L : s) {
+            if (L.n_items == 0) continue;
+            if (r.n_s == kSmallPasses || L.n_items > (uint32_t)kSmallItems) return false;
+            r.s_items[r.n_s] = L.items;
+            r.s_n[r.n_s] = L.n_items;
+            ++r.n_s;
+        }
+        // the copies in LDS, after the chi item's area
+        size_t o = one->lds;
+        auto take = [&](size_t bytes) {
+            const size_t at = (o + 15) & ~(size_t)15;
+            o = at + bytes;
+            return (uint32_t)at;
+        };
+        const Plan &p = *members[0];
+        r.n_counts = p.nvox * p.S;
+        r.n_models = (uint32_t)p.models.size();
+        r.rec = take(sizeof(DevTissue));
+        r.counts = take((size_t)r.n_counts * 4);
+        r.vox_off = take((size_t)p.ncell * 4);
+        r.wh = take((size_t)p.ncell * 2);
+        r.cell_list = take((size_t)p.ncell * 4);
+        r.edges = take((size_t)p.nedge * sizeof(EdgeRec));
+        r.models = take((size_t)r.n_models * sizeof(DevModel));
+        r.tbl = take(sizeof(DevTissue *));
+        r.chi_item_lds = take(sizeof(ChiItem));
+        for (int c = 0; c < r.n_s; ++c) r.s_items_lds[c] = take(r.s_n[c] * sizeof(SItem));
+        if (o > kSmallLds) return false;
+        lds = o;
+        r.strang = strang ? 1 : 0;
+        return true;
+    }
+
     int run(double dt, int32_t n)
     {
+        SmallRun sr;
+        const JitKernels *jk = nullptr;
+        size_t lds = 0;
+        if (whole_run && n > 0 && small_run(sr, jk, lds)) {
+            // one workgroup runs every step; launches of at most
+            // kWholeRunSteps steps keep each kernel short
+            for (int32_t left = n; left > 0;) {
+                uint32_t m = (uint32_t)std::min<int32_t>(left, kWholeRunSteps);
+                DevTissue *rec = rec0;
+                void *args[] = {&rec, &sr, &dt, &m};
+                HIP_TRY(hipModuleLaunchKernel(jk->run_small, 1, 1, 1, kWave, 1, 1, (unsigned)lds,
+                                              stream, args, nullptr));
+                left -= (int32_t)m;
+            }
+            return TISSUE_OK;
+        }
         int32_t left = n;
         if (graph_chunk > 0 && n >= graph_chunk) {
             uint64_t bits;
@@ -1338,6 +1416,7 @@ int tissue_create(const tissue_desc_t *d, void *dev_buf, size_t dev_bytes, void 
     L.cus = cus;
     L.strang = p.strang;
     L.members = {&t->plan};
+    L.rec0 = t->d_rec();
     L.retry_items = reinterpret_cast<ChiItem *>(base + p.off_retry);
     L.chi_items = reinterpret_cast<ChiItem *>(base + p.off_chi);
     L.chi_items_cap = p.n_chi_items;
@@ -1547,6 +1626,23 @@ int tissue_set_refill(tissue_t *t, int32_t min_idle_lanes)
     return TISSUE_OK;
 }
 
+int tissue_set_whole_run(tissue_t *t, int32_t enable)
+{
+    if (!t || enable < 0 || enable > 1) return fail(TISSUE_EINVAL, "whole run must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(t->stream));
+    t->lp.whole_run = enable;
+    return TISSUE_OK;
+}
+
+int tissue_runs_whole(tissue_t *t)
+{
+    if (!t) return fail(TISSUE_EINVAL, "null tissue");
+    SmallRun r;
+    const JitKernels *jk = nullptr;
+    size_t lds = 0;
+    return t->lp.whole_run && t->lp.small_run(r, jk, lds) ? 1 : 0;
+}
+
 int tissue_set_graph_chunk(tissue_t *t, int32_t steps_per_graph)
 {
     if (!t || steps_per_graph < 0 || steps_per_graph > 100000) return fail(TISSUE_EINVAL, "bad graph chunk");
@@ -1689,6 +1785,7 @@ int tissue_batch_create(tissue_t *const *ts, int32_t n, void *dev_buf, size_t de
     L.cus = cus;
     L.strang = ts[0]->plan.strang;
     for (int32_t i = 0; i < n; ++i) L.members.push_back(&ts[i]->plan);
+    L.rec0 = ts[0]->d_rec();
     L.retry_items = reinterpret_cast<ChiItem *>(b->dev + B.off_retry);
     L.chi_items = reinterpret_cast<ChiItem *>(b->dev + B.off_chi);
     L.chi_items_cap = B.chi_cap;
@@ -1768,6 +1865,7 @@ int tissue_batch_set_members(tissue_batch_t *b, tissue_t *const *ts, int32_t n)
     L.n_tissues = (uint32_t)n;
     L.lq = reinterpret_cast<uint32_t *>(b->dev + B.off_lq);
     L.members = plans;
+    L.rec0 = n > 0 ? ts[0]->d_rec() : nullptr;
     L.strang = n > 0 ? ts[0]->plan.strang : L.strang;
     L.retry_items = reinterpret_cast<ChiItem *>(b->dev + B.off_retry);
     L.chi_items = reinterpret_cast<ChiItem *>(b->dev + B.off_chi);
@@ -1861,6 +1959,23 @@ int tissue_batch_set_refill(tissue_batch_t *b, int32_t min_idle_lanes)
     return TISSUE_OK;
 }
 
+int tissue_batch_set_whole_run(tissue_batch_t *b, int32_t enable)
+{
+    if (!b || enable < 0 || enable > 1) return fail(TISSUE_EINVAL, "whole run must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(b->lp.stream));
+    b->lp.whole_run = enable;
+    return TISSUE_OK;
+}
+
+int tissue_batch_runs_whole(tissue_batch_t *b)
+{
+    if (!b) return fail(TISSUE_EINVAL, "null batch");
+    SmallRun r;
+    const JitKernels *jk = nullptr;
+    size_t lds = 0;
+    return b->lp.whole_run && b->lp.small_run(r, jk, lds) ? 1 : 0;
+}
+
 int tissue_batch_set_graph_chunk(tissue_batch_t *b, int32_t steps_per_graph)
 {
     if (!b || steps_per_graph < 0 || steps_per_graph > 100000) return fail(TISSUE_EINVAL, "bad graph chunk");
@@ -1936,6 +2051,7 @@ int tissue_batch_step_static(tissue_t *const *ts, int32_t n, double dt, int32_t 
     // persistent chi launches, steps launched eagerly (no graph)
     LaunchPlan L;
     for (int32_t i = 0; i < n; ++i) L.members.push_back(&ts[i]->plan);
+    L.rec0 = n > 0 ? ts[0]->d_rec() : nullptr;
     std::vector<ChiItem> items;
     std::vector<ChiLaunch> launches;
     plan_chi(L.members, kModeAuto, L.regroup, cus * 4, items, launches);

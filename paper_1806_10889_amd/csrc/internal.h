@@ -63,7 +63,7 @@ struct DevTissue {
     const uint8_t *wh;            // [n_cells][2] mesh (w, h)
     int32_t *cell_list;           // [n_cells] cells grouped by leaf-count class (each
                                   // class's order may be regrouped between steps)
-    const EdgeRec *edges;         // [n_edges], ranked by (colour, i)
+    const EdgeRec *edges;         // [n_edges] in the order S processes them
     unsigned long long *stats;    // [3] chi events, S events, draws
     uint32_t *flags;              // [2] overflow, capped
     uint32_t *tr_chi_ev;          // trace ring [trace_steps][n_cells] or null
@@ -117,6 +117,38 @@ struct SItem {
     uint32_t first;
     uint32_t count;
     uint32_t pad;
+};
+
+// The whole run of a small tissue in one launch (one workgroup): its one
+// chi work item (one lane per cell, at most 64 cells of one leaf class),
+// then its S passes, for every step of the call, with the tissue's state
+// copied into LDS for the run.  The bounds keep the one wavefront's
+// sequence of items no longer than the step-by-step launches' critical
+// path, and the copies within its LDS.
+constexpr int kSmallPasses = 8;   // S passes (conflict levels)
+constexpr int kSmallItems = 2;    // items per S pass
+constexpr uint32_t kSmallLds = 48 * 1024;  // dynamic LDS of the whole-run kernel
+
+// (copied into LDS a 4-byte word at a time)
+static_assert(sizeof(DevTissue) % 8 == 0 && sizeof(DevModel) % 4 == 0, "record sizes");
+static_assert(sizeof(ChiItem) % 4 == 0 && sizeof(SItem) % 4 == 0, "item sizes");
+
+struct SmallRun {
+    // LDS byte offsets of the copies: the tissue's record, counts, cell
+    // tables, edge records and networks, its table of one record pointer,
+    // and the work items
+    uint32_t rec, counts, vox_off, wh, cell_list, edges, models, tbl;
+    uint32_t n_counts;  // int32 counts (voxels x species)
+    uint32_t n_models;
+    const ChiItem *chi_item;
+    uint32_t chi_item_lds;
+    int32_t chi_cells_per_item;
+    int32_t chi_log2p;
+    const SItem *s_items[kSmallPasses];
+    uint32_t s_n[kSmallPasses];
+    uint32_t s_items_lds[kSmallPasses];
+    int32_t n_s;
+    int32_t strang;
 };
 
 }  // namespace tissue_impl

@@ -3,7 +3,8 @@
 // The chi kernels are templates over a network policy (chi_kernels.h).  For
 // each distinct reaction network (species count, reactants, stoichiometry,
 // diffusing species) this file writes a policy whose structure is a set of
-// compile-time constants, compiles the two chi kernels for gfx950 with the
+// compile-time constants, compiles the chi kernels (and the whole-run
+// kernel of small tissues, which runs S as well) for gfx950 with the
 // same floating-point rules as the ahead-of-time library (no contraction,
 // no fast-math, no packed FP32), and caches the module for the process.
 // Rate constants stay runtime values read per tissue, so one compiled network
@@ -24,7 +25,7 @@
 namespace tissue_impl {
 namespace {
 
-#include "jit_sources.inc"  // kSrcDeviceMath, kSrcInternal, kSrcChiKernels
+#include "jit_sources.inc"  // kSrcDeviceMath, kSrcInternal, kSrcChiKernels, kSrcSDevice
 
 std::mutex g_mu;
 std::map<std::string, std::unique_ptr<JitKernels>> g_cache;
@@ -67,7 +68,7 @@ std::string network_source(const DevModel &M)
     }
     for (int q = 0; q < ND; ++q) dsp[q] = M.diff_species[q];
     std::ostringstream o;
-    o << "#include \"chi_kernels.h\"\n"
+    o << "#include \"s_device.h\"\n"
       << "namespace tissue_impl {\n"
       << "struct NetCompiled {\n"
       << "    static constexpr int SM = " << S << ", RM = " << R << ", NDM = " << ND << ";\n"
@@ -101,7 +102,7 @@ std::string network_source(const DevModel &M)
       << "{\n"
       << "    extern __shared__ __align__(16) unsigned char lds[];\n"
       << "    tissue_impl::chi_lane_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
-      << "        persistent, cells_per_item, log2p, dt, kstep, tag, n_items_dev, prio);\n"
+      << "        persistent, cells_per_item, log2p, dt, kstep, tag, n_items_dev, prio, blockIdx.x);\n"
       << "}\n"
       ;
     for (int gl : {1, 2, 4}) {
@@ -126,6 +127,13 @@ std::string network_source(const DevModel &M)
       << "    tissue_impl::chi_refill_body<tissue_impl::NetCompiled>(lds, tbl, items, n_items, queue,\n"
       << "        persistent, dt, kstep, tag, retry_items, retry_count, refill_min);\n"
       << "}\n";
+    o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_run_small(\n"
+      << "    DevTissue *T, tissue_impl::SmallRun run, double dt, uint32_t n_steps)\n"
+      << "{\n"
+      << "    extern __shared__ __align__(16) unsigned char lds[];\n"
+      << "    __shared__ tissue_impl::SShared sh;\n"
+      << "    tissue_impl::run_small<tissue_impl::NetCompiled>(lds, sh, T, run, dt, n_steps);\n"
+      << "}\n";
     for (int rw : {16, 32, 64}) {
         o << "extern \"C\" __global__ __launch_bounds__(64) void tissue_chi_row"
           << (rw == 16 ? std::string() : std::to_string(rw)) << "(\n"
@@ -147,10 +155,10 @@ namespace {
 int compile_network(const DevModel &M, std::vector<char> &code, std::string &err)
 {
     const std::string src = network_source(M);
-    const char *hdr_src[] = {kSrcDeviceMath, kSrcInternal, kSrcChiKernels};
-    const char *hdr_name[] = {"device_math.h", "internal.h", "chi_kernels.h"};
+    const char *hdr_src[] = {kSrcDeviceMath, kSrcInternal, kSrcChiKernels, kSrcSDevice};
+    const char *hdr_name[] = {"device_math.h", "internal.h", "chi_kernels.h", "s_device.h"};
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "tissue_network.hip", 3, hdr_src, hdr_name) !=
+    if (hiprtcCreateProgram(&prog, src.c_str(), "tissue_network.hip", 4, hdr_src, hdr_name) !=
         HIPRTC_SUCCESS) {
         err = "hiprtcCreateProgram failed";
         return -1;
@@ -206,6 +214,7 @@ int jit_kernels(const DevModel &M, const JitKernels **out, std::string &err)
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16x2, k->module, "tissue_chi_lane16x2");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16x4, k->module, "tissue_chi_lane16x4");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->lane16r, k->module, "tissue_chi_lane16r");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->run_small, k->module, "tissue_run_small");
     if (e != hipSuccess) {
         err = std::string("loading the compiled network: ") + hipGetErrorString(e);
         return -1;

@@ -19,6 +19,7 @@ struct JitKernels {
     hipFunction_t lane16x2 = nullptr; // compact, 2 lanes per cell (17..32 voxels)
     hipFunction_t lane16x4 = nullptr; // compact, 4 lanes per cell (33..64 voxels)
     hipFunction_t lane16r = nullptr;  // compact, one lane per cell, lanes refilled (persistent)
+    hipFunction_t run_small = nullptr;  // every step of a call of a small tissue, chi and S
 };
 
 // Cache key of a network's structure (not its rates).

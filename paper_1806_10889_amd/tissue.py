@@ -88,7 +88,8 @@ EXPORTS = [
     "tissue_batch_step_timed", "tissue_batch_set_launch", "tissue_batch_sync",
     "tissue_batch_destroy", "tissue_strerror", "tissue_last_error", "tissue_device_cus",
     "tissue_batch_step_static", "tissue_set_refill", "tissue_batch_set_refill",
-    "tissue_batch_set_members",
+    "tissue_batch_set_members", "tissue_set_whole_run", "tissue_batch_set_whole_run",
+    "tissue_runs_whole", "tissue_batch_runs_whole",
 ]
 
 
@@ -134,6 +135,10 @@ def _load():
         "tissue_batch_step_static": (C.c_int, [C.POINTER(vp), i32, dbl, i32, vp]),
         "tissue_set_refill": (C.c_int, [vp, i32]),
         "tissue_batch_set_refill": (C.c_int, [vp, i32]),
+        "tissue_set_whole_run": (C.c_int, [vp, i32]),
+        "tissue_batch_set_whole_run": (C.c_int, [vp, i32]),
+        "tissue_runs_whole": (C.c_int, [vp]),
+        "tissue_batch_runs_whole": (C.c_int, [vp]),
         "tissue_batch_set_members": (C.c_int, [vp, C.POINTER(vp), i32]),
     }
     for name, (res, args) in sig.items():
@@ -337,6 +342,17 @@ class Tissue:
         """Lane refill of compact launches (0 off, 1..64 idle lanes; results unchanged)."""
         _check(lib.tissue_set_refill(self.handle, int(min_idle_lanes)), "tissue_set_refill")
 
+    def set_whole_run(self, enable: bool):
+        """Small tissues: every step of a call in one kernel launch (the
+        default; results unchanged)."""
+        _check(lib.tissue_set_whole_run(self.handle, int(bool(enable))), "tissue_set_whole_run")
+
+    def runs_whole(self) -> bool:
+        """Whether step() runs this tissue in the whole-run kernel."""
+        rc = lib.tissue_runs_whole(self.handle)
+        _check(min(rc, 0), "tissue_runs_whole")
+        return rc == 1
+
     def set_regroup(self, mode: int):
         """0 off, 1 on, 2 automatic: the load-ordered regroup pass before
         compact-layout chi launches (results are unchanged)."""
@@ -417,6 +433,14 @@ class Batch:
 
     def set_refill(self, min_idle_lanes: int):
         _check(lib.tissue_batch_set_refill(self.handle, int(min_idle_lanes)), "tissue_batch_set_refill")
+
+    def set_whole_run(self, enable: bool):
+        _check(lib.tissue_batch_set_whole_run(self.handle, int(bool(enable))), "tissue_batch_set_whole_run")
+
+    def runs_whole(self) -> bool:
+        rc = lib.tissue_batch_runs_whole(self.handle)
+        _check(min(rc, 0), "tissue_batch_runs_whole")
+        return rc == 1
 
     def set_regroup(self, mode: int):
         _check(lib.tissue_batch_set_regroup(self.handle, int(mode)), "tissue_batch_set_regroup")

@@ -6,10 +6,14 @@ from paper_1806_10889_amd import workloads as W
 
 
 def gpu_run(problem, n_steps, trace=False, persistent=None, wpc=0, graph_chunk=None, chunks=None,
-            allow_flags=False, chi_mode=None, jit=True, regroup=None):
+            allow_flags=False, chi_mode=None, jit=True, regroup=None, whole_run=False):
+    """The tissue stepped through the library.  whole_run=False (the
+    default here) keeps the step-by-step launches these tests exercise; the
+    whole-run kernel of small tissues has tests of its own."""
     from paper_1806_10889_amd import tissue as T
     t = T.Tissue(problem, trace_steps=n_steps if trace else 0, jit=jit)
     assert t.stats()["jit"] == int(jit), "network kernels not compiled"
+    t.set_whole_run(whole_run)
     if chi_mode is not None:
         t.set_chi_mode(chi_mode)
     if regroup is not None:
