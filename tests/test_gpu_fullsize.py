@@ -6,9 +6,10 @@ per-(cell, step) and per-(edge, step) event counts and last-event-time bits.
 
 * the 64x64 headline tissue over its first 50 splitting steps (persistent and
   one-workgroup-per-item launches, graphs);
-* the uneven 256x256 tissue in the automatic layout with forked graph
-  branches: compact classes of 35 975 and 20 217 cells regrouped by load in
-  segments of at most 16 384 cells, and the row head of its 64-leaf class;
+* the uneven 256x256 tissue over its first 20 steps in the automatic layout
+  with forked graph branches: compact classes of 35 975 and 20 217 cells
+  regrouped by load in segments of at most 16 384 cells, and the row head of
+  its 64-leaf class;
 * a forced-compact class of 22 500 cells (two regroup segments) and a 64-leaf
   class of 18 496 cells whose row head is cut from a segmented class;
 * the full 512-tissue batch exactly as the batched leg builds it, with 16
@@ -47,21 +48,22 @@ def test_config3_full_auto_forked_graphs(oracle_lib):
     one workgroup per item, regroup automatic): the 16- and 32-leaf classes
     compact and regrouped in 3 and 2 segments, the 64-leaf class's heaviest
     1024 cells in rows, every class a parallel branch of the step graph;
-    12 steps (two graphs of 5 and an eager tail) on every cell and edge."""
+    its first 20 steps (three graphs of 6 and an eager tail) on every cell
+    and edge."""
     from paper_1806_10889_amd import tissue as T
-    p = W.config3(n_steps=12)
+    p = W.config3(n_steps=20)
     P = [1 << int(np.ceil(np.log2(w * h))) for w, h in zip(p["mesh_w"], p["mesh_h"])]
     classes = {k: P.count(k) for k in set(P)}
     assert classes[16] > 2 * 16384 and 16384 < classes[32] <= 2 * 16384 and classes[64] > 4096
-    print("oracle: hex 256x256 uneven, 12 steps", flush=True)
-    o = oracle_lib.run(p, p["dt"], 12, trace=True)
-    t = T.Tissue(p, trace_steps=12)
+    print("oracle: hex 256x256 uneven, 20 steps", flush=True)
+    o = oracle_lib.run(p, p["dt"], 20, trace=True)
+    t = T.Tissue(p, trace_steps=20)
     t.set_chi_mode(2)
     t.set_regroup(2)
     t.set_launch(False, 0)
-    t.set_graph_chunk(5)
-    t.step(p["dt"], 12)
-    g = dict(counts=t.read_counts(), stats=t.stats(), trace=t.trace(0, 12))
+    t.set_graph_chunk(6)
+    t.step(p["dt"], 20)
+    g = dict(counts=t.read_counts(), stats=t.stats(), trace=t.trace(0, 20))
     t.close()
     assert_same(g, o)
 
