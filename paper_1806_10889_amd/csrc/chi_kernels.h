@@ -39,8 +39,11 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 // on the front of the list (the heaviest items, after a regroup by load).
 // A workgroup takes the next item of its own XCD's stream and, once that
 // is drained, of the other streams in turn (`spent`, kept by lane 0, marks
-// the streams it found drained).  A counter passes the end of its stream
-// by at most one per workgroup.
+// the streams it found drained).  Another XCD's stream is looked at with a
+// plain load first, so that the workgroups leaving at the end of a launch
+// do not queue up on the counters of drained streams; a counter passes the
+// end of its stream by at most one per workgroup.  An empty launch (a redo
+// list with nothing in it) touches no counter.
 __device__ __forceinline__ uint32_t next_item(uint32_t *queue, bool persistent, uint32_t &cursor,
                                               uint32_t n_items, uint32_t &spent)
 {
@@ -50,11 +53,19 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *queue, bool persistent, 
         return it;
     }
     uint32_t it = n_items;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && n_items > 0) {
         const uint32_t home = blockIdx.x % kXcds;
         for (uint32_t s = 0; s < kXcds; ++s) {
             const uint32_t x = (home + s) % kXcds;
             if ((spent >> x) & 1u) continue;
+            if (s > 0) {
+                const uint32_t taken = __hip_atomic_load(queue + x, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                if (x + (uint64_t)kXcds * taken >= n_items) {
+                    spent |= 1u << x;
+                    continue;
+                }
+            }
             const uint64_t cand = x + (uint64_t)kXcds * atomicAdd(queue + x, 1u);
             if (cand < n_items) {
                 it = (uint32_t)cand;
