@@ -89,72 +89,72 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 COUNTERS = {
     "plain": {
-        "digest": "27bab57622db1bbdfe3954f1add34582a4431e94",
+        "digest": "eade0e3f17f00b0028220392e3b136636c7d0bf6",
         "profile": "profiles/chi_row_plain_hex64x64_4x4.md",
         "chi_events_per_step": 744850.5,
         "kernels": {
             "tissue_chi_row": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 170.494,
-                "sq_insts_valu": 46678900.0,
-                "fetch_kib": 930.676,
+                "avg_us": 167.031,
+                "sq_insts_valu": 46705500.0,
+                "fetch_kib": 941.183,
                 "write_kib": 1376.0
             }
         }
     },
     "batched": {
-        "digest": "27bab57622db1bbdfe3954f1add34582a4431e94",
+        "digest": "eade0e3f17f00b0028220392e3b136636c7d0bf6",
         "profile": "profiles/chi_lane16_batched_512_tissues.md",
         "chi_events_per_step": 1298376166.0,
         "kernels": {
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 19831.102,
-                "sq_insts_valu": 10691200000.0,
-                "fetch_kib": 652427.0,
-                "write_kib": 1058600.0
+                "avg_us": 20047.416,
+                "sq_insts_valu": 10692500000.0,
+                "fetch_kib": 656154.0,
+                "write_kib": 1061300.0
             }
         }
     },
     "uneven": {
-        "digest": "27bab57622db1bbdfe3954f1add34582a4431e94",
+        "digest": "eade0e3f17f00b0028220392e3b136636c7d0bf6",
         "profile": "profiles/chi_classes_uneven_hex256x256.md",
         "chi_events_per_step": 22521846.2,
         "kernels": {
             "tissue_chi_row64": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1228.179,
-                "sq_insts_valu": 327004000.0,
-                "fetch_kib": 883.967,
-                "write_kib": 1222.38
+                "avg_us": 1222.515,
+                "sq_insts_valu": 327033000.0,
+                "fetch_kib": 898.976,
+                "write_kib": 1222.39
             },
             "tissue_chi_lane16x4": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1516.126,
-                "sq_insts_valu": 91581300.0,
-                "fetch_kib": 2411.35,
-                "write_kib": 3341.4
+                "avg_us": 1520.736,
+                "sq_insts_valu": 91582500.0,
+                "fetch_kib": 2427.53,
+                "write_kib": 3341.37
             },
             "tissue_chi_lane16x2": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1040.597,
-                "sq_insts_valu": 141728000.0,
-                "fetch_kib": 7338.27,
-                "write_kib": 10512.2
+                "avg_us": 1046.659,
+                "sq_insts_valu": 141753000.0,
+                "fetch_kib": 7354.95,
+                "write_kib": 10512.0
             },
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 538.694,
-                "sq_insts_valu": 74518900.0,
-                "fetch_kib": 8812.66,
-                "write_kib": 11674.2
+                "avg_us": 549.671,
+                "sq_insts_valu": 74551800.0,
+                "fetch_kib": 8821.45,
+                "write_kib": 11673.6
             },
             "tissue_chi_lane": {
                 "dispatches_per_step": 3.0,
-                "avg_us": 8.928,
-                "sq_insts_valu": 27655.0,
-                "fetch_kib": 22.7724,
-                "write_kib": 16.0938
+                "avg_us": 8.651,
+                "sq_insts_valu": 35335.0,
+                "fetch_kib": 39.2437,
+                "write_kib": 8.3125
             }
         }
     }
