@@ -37,4 +37,5 @@ def test_host_plans_clean_under_asan_and_ubsan():
                    UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
         r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env, cwd=d)
         assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
+        print(r.stdout)
         assert "failures 0" in r.stdout and "broken descriptors rejected: 22" in r.stdout
