@@ -5,7 +5,9 @@ element by element: counts, event and draw totals, and, where traced, the
 per-(cell, step) and per-(edge, step) event counts and last-event-time bits.
 
 * the 64x64 headline tissue over its first 50 splitting steps (persistent and
-  one-workgroup-per-item launches, graphs);
+  one-workgroup-per-item launches, graphs), and over its whole horizon of
+  2000 steps in the benchmark's launch configuration (final counts and
+  totals);
 * the uneven 256x256 tissue over its first 20 steps in the automatic layout
   with forked graph branches: compact classes of 35 975 and 20 217 cells
   regrouped by load in segments of at most 16 384 cells, and the row head of
@@ -13,7 +15,8 @@ per-(cell, step) and per-(edge, step) event counts and last-event-time bits.
 * a forced-compact class of 22 500 cells (two regroup segments) and a 64-leaf
   class of 18 496 cells whose row head is cut from a segmented class;
 * the full 512-tissue batch exactly as the batched leg builds it, with 16
-  sampled tissues (the 8 smallest and 8 at random) against the oracle;
+  sampled tissues (the 8 smallest and 8 at random) against the oracle over
+  the first 5 steps (graphs of 2) and over the whole horizon of 200 steps;
 * the serving loop at four lanes on the serving workload's own requests:
   32 sampled results equal the same requests run alone, 8 equal the oracle.
 """
@@ -97,6 +100,47 @@ def test_row_head_cut_from_a_segmented_class(oracle_lib):
     o = oracle_lib.run(p, p["dt"], 3, trace=True)
     g = gpu_run(p, 3, trace=True, persistent=False, graph_chunk=2, chi_mode=2, regroup=2)
     assert_same(g, o)
+
+
+def test_config2_full_horizon(oracle_lib):
+    """The headline workload over its whole horizon (2000 steps, about
+    1.5e9 events) in the benchmark's launch configuration (rows of 16
+    lanes, one workgroup per item, graphs of 25 steps): the final counts
+    of every voxel and the event and draw totals equal the oracle's."""
+    p = W.config2()
+    print("oracle: hex 64x64, 4x4 cells, 2000 steps", flush=True)
+    o = oracle_lib.run(p, p["dt"], 2000)
+    g = gpu_run(p, 2000, persistent=0, graph_chunk=25, chi_mode=1)
+    assert_same(g, o, trace=False)
+
+
+def test_config4_full_horizon_sampled(oracle_lib):
+    """The 512-tissue sweep over its whole horizon (200 steps) as the
+    batched leg runs it (one Batch, automatic layout and regroup, the
+    default persistent launch and graphs); the same 16 sampled tissues (the
+    8 smallest and 8 at random) against the oracle."""
+    from paper_1806_10889_amd import tissue as T
+    probs = W.config4()
+    n = probs[0]["n_steps"]
+    ts = [T.Tissue(p) for p in probs]
+    b = T.Batch(ts)
+    b.set_regroup(2)
+    b.step(probs[0]["dt"], n)
+    b.sync()
+    sizes = np.array([p["nx"] * p["ny"] for p in probs])
+    rng = np.random.default_rng(404)
+    small = list(np.argsort(sizes, kind="stable")[:8])
+    rest = [i for i in range(len(probs)) if i not in small]
+    sample = small + list(rng.choice(rest, size=8, replace=False))
+    for i in sample:
+        print(f"oracle: batch member {i} ({probs[i]['nx']}x{probs[i]['ny']}), {n} steps", flush=True)
+        o = oracle_lib.run(probs[i], probs[i]["dt"], n)
+        st = ts[i].stats()
+        assert np.array_equal(ts[i].read_counts(), o.counts), i
+        assert (st["chi_events"], st["s_events"], st["draws"]) == (o.chi_events, o.s_events, o.draws)
+    b.close()
+    for t in ts:
+        t.close()
 
 
 def test_config4_full_batch_sampled(oracle_lib):
