@@ -392,13 +392,15 @@ __device__ __forceinline__ void s_item(const DevTissue *const *tbl, const SItem 
 // The whole run of a small tissue in one workgroup (one wavefront).  The
 // tissue's record, counts, cell tables, edge records and networks, and the
 // work items, are copied into LDS, and the record's copy points at the
-// copies (its statistics, flags and trace rings stay in device memory), so
-// that every read and write of the run's steps is an LDS access.  Then,
+// copies and at event and draw totals and flags of the run kept in LDS
+// (only trace rings stay in device memory), so that every read and write
+// of the run's steps is an LDS access.  Then,
 // step after step, the chi item (one lane per cell, the same code as the
 // chi lane kernel) and the S items of every pass in order run on the
 // copies, each phase closed by a workgroup barrier so that the next one
-// reads the counts this one wrote; at the end the counts go back and the
-// step counter advances by n_steps.  The operations and their order per
+// reads the counts this one wrote; at the end the counts go back, the
+// run's totals and flags are added to the tissue's, and the step counter
+// advances by n_steps.  The operations and their order per
 // cell and per edge are those of the step-by-step launches, so the bits
 // are the same.  A small tissue spends most of a launched step on launch
 // overhead (paper: at small splitting intervals the scheduling of the
@@ -426,10 +428,17 @@ __device__ __forceinline__ void run_small(unsigned char *lds, SShared &sh, DevTi
     copy_words(lds + run.chi_item_lds, run.chi_item, sizeof(ChiItem) / 4);
     for (int p = 0; p < run.n_s; ++p)
         copy_words(lds + run.s_items_lds[p], run.s_items[p], run.s_n[p] * (sizeof(SItem) / 4));
+    // the run's event and draw totals and flags, added to the tissue's at the end
+    __shared__ unsigned long long run_stats[3];
+    __shared__ uint32_t run_flags[2];
+    if (threadIdx.x < 3) run_stats[threadIdx.x] = 0ull;
+    if (threadIdx.x < 2) run_flags[threadIdx.x] = 0u;
     __syncthreads();  // the record's copy is whole before its pointers change
     DevTissue *L = reinterpret_cast<DevTissue *>(lds + run.rec);
     DevTissue **tbl = reinterpret_cast<DevTissue **>(lds + run.tbl);
     if (threadIdx.x == 0) {
+        L->stats = run_stats;
+        L->flags = run_flags;
         L->counts = reinterpret_cast<int32_t *>(lds + run.counts);
         L->vox_off = reinterpret_cast<const int32_t *>(lds + run.vox_off);
         L->wh = lds + run.wh;
@@ -460,6 +469,8 @@ __device__ __forceinline__ void run_small(unsigned char *lds, SShared &sh, DevTi
     }
 
     copy_words(T->counts, lds + run.counts, run.n_counts);
+    if (threadIdx.x < 3 && run_stats[threadIdx.x]) atomicAdd(T->stats + threadIdx.x, run_stats[threadIdx.x]);
+    if (threadIdx.x < 2 && run_flags[threadIdx.x]) atomicOr(T->flags + threadIdx.x, 1u);
     if (threadIdx.x == 0) T->step_base += n_steps;
 }
 
