@@ -89,71 +89,71 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 COUNTERS = {
     "plain": {
-        "digest": "eade0e3f17f00b0028220392e3b136636c7d0bf6",
+        "digest": "f85cd7e5300cdeffa66a992ced63861957d2e92c",
         "profile": "profiles/chi_row_plain_hex64x64_4x4.md",
         "chi_events_per_step": 744850.5,
         "kernels": {
             "tissue_chi_row": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 167.031,
+                "avg_us": 167.671,
                 "sq_insts_valu": 46705500.0,
-                "fetch_kib": 941.183,
+                "fetch_kib": 945.226,
                 "write_kib": 1376.0
             }
         }
     },
     "batched": {
-        "digest": "eade0e3f17f00b0028220392e3b136636c7d0bf6",
+        "digest": "f85cd7e5300cdeffa66a992ced63861957d2e92c",
         "profile": "profiles/chi_lane16_batched_512_tissues.md",
         "chi_events_per_step": 1298376166.0,
         "kernels": {
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 20047.416,
+                "avg_us": 20006.037,
                 "sq_insts_valu": 10692500000.0,
-                "fetch_kib": 656154.0,
+                "fetch_kib": 656164.0,
                 "write_kib": 1061300.0
             }
         }
     },
     "uneven": {
-        "digest": "eade0e3f17f00b0028220392e3b136636c7d0bf6",
+        "digest": "f85cd7e5300cdeffa66a992ced63861957d2e92c",
         "profile": "profiles/chi_classes_uneven_hex256x256.md",
         "chi_events_per_step": 22521846.2,
         "kernels": {
             "tissue_chi_row64": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1222.515,
-                "sq_insts_valu": 327033000.0,
-                "fetch_kib": 898.976,
-                "write_kib": 1222.39
+                "avg_us": 1223.988,
+                "sq_insts_valu": 327032000.0,
+                "fetch_kib": 897.518,
+                "write_kib": 1222.38
             },
             "tissue_chi_lane16x4": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1520.736,
-                "sq_insts_valu": 91582500.0,
-                "fetch_kib": 2427.53,
+                "avg_us": 1523.578,
+                "sq_insts_valu": 91584500.0,
+                "fetch_kib": 2427.27,
                 "write_kib": 3341.37
             },
             "tissue_chi_lane16x2": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1046.659,
-                "sq_insts_valu": 141753000.0,
-                "fetch_kib": 7354.95,
+                "avg_us": 1041.2,
+                "sq_insts_valu": 141755000.0,
+                "fetch_kib": 7354.72,
                 "write_kib": 10512.0
             },
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 549.671,
+                "avg_us": 549.812,
                 "sq_insts_valu": 74551800.0,
-                "fetch_kib": 8821.45,
-                "write_kib": 11673.6
+                "fetch_kib": 8821.54,
+                "write_kib": 11673.8
             },
             "tissue_chi_lane": {
                 "dispatches_per_step": 3.0,
-                "avg_us": 8.651,
+                "avg_us": 8.548,
                 "sq_insts_valu": 35335.0,
-                "fetch_kib": 39.2437,
+                "fetch_kib": 39.2545,
                 "write_kib": 8.3125
             }
         }
