@@ -245,10 +245,8 @@ int tissue_write_counts(tissue_t *t, const int32_t *host_in, size_t n_in);
 
 /* Launch shape of the chi operator: 0 = one workgroup per work item,
  * 1 = persistent workgroups pulling items from a device queue (the
- * default: one stream of items per XCD, each workgroup draining its own
- * XCD's stream and then stealing from the others), with workgroups_per_cu
- * resident workgroups per CU (0 = auto).  Results are bit-identical for
- * every choice. */
+ * default), with workgroups_per_cu resident workgroups per CU (0 = auto).
+ * Results are bit-identical for every choice. */
 int tissue_set_launch(tissue_t *t, int32_t persistent, int32_t workgroups_per_cu);
 
 /* Kernel of the chi operator.  0 = one lane per cell with the full sum tree

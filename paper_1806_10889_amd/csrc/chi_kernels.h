@@ -12,9 +12,8 @@
 //     fastest, so 64 lanes touching "their" element hit 64 distinct banks;
 //   - one 16-lane row per cell (at most 16 voxels): lane l holds voxel l.
 // Work items (<= 64 cells of one tissue) come one per workgroup or, in
-// persistent mode, from a device queue with one stream of items per XCD: a
-// workgroup drains its own XCD's stream and then steals from the others in
-// turn; the last workgroup to leave clears the queue for the next launch.
+// persistent mode, from a device queue every workgroup pulls from until it is
+// empty; the last workgroup to leave clears the queue for the next launch.
 // A launch may ask for a raised issue priority of its wavefronts (`prio`):
 // where several classes' launches share the device, the arbiter then serves
 // its wavefronts first on a SIMD they share with another launch's.
@@ -34,62 +33,33 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 }
 
 // Next work item for this workgroup (one wavefront); n_items or more when
-// none is left.  Persistent queue: stream x (one per XCD, counter queue[x])
-// holds the items x, x + 8, x + 16, ... in order, so that every XCD starts
-// on the front of the list (the heaviest items, after a regroup by load).
-// A workgroup takes the next item of its own XCD's stream and, once that
-// is drained, of the other streams in turn (`spent`, kept by lane 0, marks
-// the streams it found drained).  Another XCD's stream is looked at with a
-// plain load first, so that the workgroups leaving at the end of a launch
-// do not queue up on the counters of drained streams; a counter passes the
-// end of its stream by at most one per workgroup.  An empty launch (a redo
-// list with nothing in it) touches no counter.
-__device__ __forceinline__ uint32_t next_item(uint32_t *queue, bool persistent, uint32_t &cursor,
-                                              uint32_t n_items, uint32_t &spent)
+// none is left.  Persistent queue: one counter shared by the launch.
+__device__ __forceinline__ uint32_t next_item(uint32_t *queue, bool persistent, uint32_t &cursor)
 {
     if (!persistent) {
         uint32_t it = cursor;
         cursor = 0xFFFFFFFFu;
         return it;
     }
-    uint32_t it = n_items;
-    if (threadIdx.x == 0 && n_items > 0) {
-        const uint32_t home = blockIdx.x % kXcds;
-        for (uint32_t s = 0; s < kXcds; ++s) {
-            const uint32_t x = (home + s) % kXcds;
-            if ((spent >> x) & 1u) continue;
-            if (s > 0) {
-                const uint32_t taken = __hip_atomic_load(queue + x, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                if (x + (uint64_t)kXcds * taken >= n_items) {
-                    spent |= 1u << x;
-                    continue;
-                }
-            }
-            const uint64_t cand = x + (uint64_t)kXcds * atomicAdd(queue + x, 1u);
-            if (cand < n_items) {
-                it = (uint32_t)cand;
-                break;
-            }
-            spent |= 1u << x;
-        }
-    }
+    uint32_t it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(queue, 1u);
     it = __shfl(it, 0, kWave);
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)it);
 }
 
 // Called by every workgroup when it has no more items: the last one out
-// resets the stream counters and the exit count (queue[0..8]) and, if
-// given, one more counter (the retry count consumed by a follow-up launch).
+// resets the queue and the exit count (queue[0], queue[1]) and, if given,
+// one more counter (the retry count consumed by a follow-up launch).
 __device__ __forceinline__ void leave_queue(uint32_t *queue, bool persistent,
                                             uint32_t *also_reset = nullptr)
 {
     if (!persistent) return;
     if (threadIdx.x == 0) {
         __threadfence();
-        const uint32_t done = atomicAdd(queue + kXcds, 1u);
+        const uint32_t done = atomicAdd(queue + kQDone, 1u);
         if (done == gridDim.x - 1) {
-            for (uint32_t x = 0; x <= kXcds; ++x) atomicExch(queue + x, 0u);
+            atomicExch(queue, 0u);
+            atomicExch(queue + kQDone, 0u);
             if (also_reset) atomicExch(also_reset, 0u);
         }
     }
@@ -452,9 +422,9 @@ __device__ __forceinline__ void chi_lane_body(unsigned char *lds, const DevTissu
     const int lane = threadIdx.x;
     const int stride = cells_per_item;
     const int P = 1 << log2p;
-    uint32_t cursor = first, spent = 0u;
+    uint32_t cursor = first;
     for (;;) {
-        const uint32_t it = next_item(queue, persistent != 0, cursor, n_items, spent);
+        const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const ChiItem item = items[it];
         const ItemCtx c = item_ctx(tbl, item, kstep, tag);
@@ -720,9 +690,9 @@ __device__ __forceinline__ void chi_row_body(RowShared &sh, const DevTissue *con
     double *rng_e = sh.rng_e;
     double *rng_u = sh.rng_u;
     const int lane = threadIdx.x, row = lane >> LOG_RW, lv = lane & (RW - 1);
-    uint32_t cursor = blockIdx.x, spent = 0u;
+    uint32_t cursor = blockIdx.x;
     for (;;) {
-        const uint32_t it = next_item(queue, persistent != 0, cursor, n_items, spent);
+        const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const ChiItem item = items[it];
         const ItemCtx c = item_ctx(tbl, item, kstep, tag);
@@ -984,9 +954,9 @@ __device__ __forceinline__ void chi_lane16_body(unsigned char *lds, const DevTis
     const int sub = lane & (G - 1);   // which 16 voxels of the cell it holds
     const int v0 = kLane16Leaves * sub;
     const int stride = cells_per_item * G;
-    uint32_t cursor = blockIdx.x, spent = 0u;
+    uint32_t cursor = blockIdx.x;
     for (;;) {
-        const uint32_t it = next_item(queue, persistent != 0, cursor, n_items, spent);
+        const uint32_t it = next_item(queue, persistent != 0, cursor);
         if (it >= n_items) break;
         const ChiItem item = items[it];
         const ItemCtx c = item_ctx(tbl, item, kstep, tag);
@@ -1336,7 +1306,7 @@ __device__ __forceinline__ void chi_refill_body(unsigned char *lds, const DevTis
     uint16_t *cnt = reinterpret_cast<uint16_t *>(lds + (size_t)stride * kLane16Leaves * 8) + lane;
 
     // the wavefront's item being handed out (wave-uniform)
-    uint32_t cursor = blockIdx.x, spent = 0u;
+    uint32_t cursor = blockIdx.x;
     uint32_t pend_next = 0, pend_count = 0, pend_tissue = 0, pend_first = 0, pend_model = 0;
     bool drained = false;
 
@@ -1399,7 +1369,7 @@ __device__ __forceinline__ void chi_refill_body(unsigned char *lds, const DevTis
                 const uint64_t free = __ballot(!has);
                 if (free == 0) break;
                 if (pend_next >= pend_count) {
-                    const uint32_t it = next_item(queue, persistent != 0, cursor, n_items, spent);
+                    const uint32_t it = next_item(queue, persistent != 0, cursor);
                     if (it >= n_items) {
                         drained = true;
                         break;

@@ -52,9 +52,9 @@ int hip_fail(hipError_t e, const char *what)
 constexpr size_t kAlign = 256;
 constexpr size_t kChiLdsBudget = 40 * 1024;  // per workgroup: >= 4 resident per CU
 // chi launches of one plan (leaf classes x networks) and their queue words:
-// each launch owns a block of kQueueBlockWords words (its per-XCD item
-// queue and exit count, its redo count, its redo launch's queue) so that
-// launches of different classes can run concurrently
+// each launch owns a block of kQueueBlockWords words (its item queue and
+// exit count, its redo count, its redo launch's queue) so that launches of
+// different classes can run concurrently
 constexpr int kMaxChiLaunches = 64;
 constexpr int32_t kWholeRunSteps = 100;  // steps per launch of the whole-run kernel
 constexpr size_t kLaunchQueueBytes = (size_t)kMaxChiLaunches * kQueueBlockWords * sizeof(uint32_t);

@@ -101,14 +101,15 @@ enum ChiMode { kChiLane = 0, kChiRow = 1, kChiLane16 = 2 };
 constexpr uint32_t kXcds = 8;
 
 // device control words of one chi launch (uint32 each): the persistent
-// queue of the main launch (one counter per XCD, then the count of
-// workgroups that left), the redo count of a compact launch, and the queue
-// of its redo launch (laid out as the main queue)
+// queue of the main launch (next item, workgroups that left), the redo
+// count of a compact launch, and the queue of its redo launch (laid out as
+// the main queue)
 enum {
     kQNext = 0,
-    kQRetry = kXcds + 1,
-    kQRetryNext = 16,
-    kQueueBlockWords = 32
+    kQDone = 1,  // relative to a queue's first word
+    kQRetry = 2,
+    kQRetryNext = 4,
+    kQueueBlockWords = 8
 };
 
 // up to 64 consecutive edges [first, first + count) of one tissue
