@@ -89,72 +89,72 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 COUNTERS = {
     "plain": {
-        "digest": "f85cd7e5300cdeffa66a992ced63861957d2e92c",
+        "digest": "8666236603afc6cedeac02cb2440e57ef5f426ca",
         "profile": "profiles/chi_row_plain_hex64x64_4x4.md",
         "chi_events_per_step": 744850.5,
         "kernels": {
             "tissue_chi_row": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 167.671,
-                "sq_insts_valu": 46705500.0,
-                "fetch_kib": 945.226,
+                "avg_us": 170.666,
+                "sq_insts_valu": 46678900.0,
+                "fetch_kib": 934.205,
                 "write_kib": 1376.0
             }
         }
     },
     "batched": {
-        "digest": "f85cd7e5300cdeffa66a992ced63861957d2e92c",
+        "digest": "8666236603afc6cedeac02cb2440e57ef5f426ca",
         "profile": "profiles/chi_lane16_batched_512_tissues.md",
         "chi_events_per_step": 1298376166.0,
         "kernels": {
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 20006.037,
-                "sq_insts_valu": 10692500000.0,
-                "fetch_kib": 656164.0,
-                "write_kib": 1061300.0
+                "avg_us": 19858.718,
+                "sq_insts_valu": 10691100000.0,
+                "fetch_kib": 652397.0,
+                "write_kib": 1058580.0
             }
         }
     },
     "uneven": {
-        "digest": "f85cd7e5300cdeffa66a992ced63861957d2e92c",
+        "digest": "8666236603afc6cedeac02cb2440e57ef5f426ca",
         "profile": "profiles/chi_classes_uneven_hex256x256.md",
         "chi_events_per_step": 22521846.2,
         "kernels": {
             "tissue_chi_row64": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1223.988,
-                "sq_insts_valu": 327032000.0,
-                "fetch_kib": 897.518,
-                "write_kib": 1222.38
+                "avg_us": 1230.533,
+                "sq_insts_valu": 327009000.0,
+                "fetch_kib": 878.953,
+                "write_kib": 1222.37
             },
             "tissue_chi_lane16x4": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1523.578,
-                "sq_insts_valu": 91584500.0,
-                "fetch_kib": 2427.27,
+                "avg_us": 1511.355,
+                "sq_insts_valu": 91576800.0,
+                "fetch_kib": 2410.8,
                 "write_kib": 3341.37
             },
             "tissue_chi_lane16x2": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1041.2,
-                "sq_insts_valu": 141755000.0,
-                "fetch_kib": 7354.72,
-                "write_kib": 10512.0
+                "avg_us": 1037.068,
+                "sq_insts_valu": 141732000.0,
+                "fetch_kib": 7337.58,
+                "write_kib": 10512.1
             },
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 549.812,
-                "sq_insts_valu": 74551800.0,
-                "fetch_kib": 8821.54,
-                "write_kib": 11673.8
+                "avg_us": 536.812,
+                "sq_insts_valu": 74517400.0,
+                "fetch_kib": 8808.46,
+                "write_kib": 11674.2
             },
             "tissue_chi_lane": {
                 "dispatches_per_step": 3.0,
-                "avg_us": 8.548,
-                "sq_insts_valu": 35335.0,
-                "fetch_kib": 39.2545,
-                "write_kib": 8.3125
+                "avg_us": 9.015,
+                "sq_insts_valu": 27655.0,
+                "fetch_kib": 29.7541,
+                "write_kib": 16.0938
             }
         }
     }
