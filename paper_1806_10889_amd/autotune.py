@@ -104,22 +104,25 @@ def tune(problems, dt: float, steps: int = 50, reps: int = 2, device="cuda:0", t
     results = []
     for cfg in candidates(vmax, ncells):
         apply(runner, cfg)
+        # at least one whole graph chunk, so that a candidate's steps run
+        # from its graph and not eagerly
+        n = max(steps, cfg["graph_chunk"])
         times = []
         for _ in range(reps + 1):  # the first run captures the graph
             for t in clones:
                 t.restart(t.problem["sim_id"], 0)
             a = time.perf_counter()
-            runner.step(dt, steps)
+            runner.step(dt, n)
             runner.sync()
             times.append(time.perf_counter() - a)
-        ms = 1e3 * min(times[1:])
-        results.append((ms, cfg))
+        ms_per_step = 1e3 * min(times[1:]) / n
+        results.append((ms_per_step, cfg))
         if log:
-            log(f"autotune {cfg}: {ms:.2f} ms / {steps} steps")
+            log(f"autotune {cfg}: {ms_per_step * n:.2f} ms / {n} steps")
     results.sort(key=lambda x: x[0])
     best = results[0][1]
-    entry = {"config": best, "ms_per_step": results[0][0] / steps,
-             "worst_ms_per_step": results[-1][0] / steps, "candidates": len(results)}
+    entry = {"config": best, "ms_per_step": results[0][0],
+             "worst_ms_per_step": results[-1][0], "candidates": len(results)}
     cache[sig] = entry
     if use_cache:
         _save_cache(cache)
