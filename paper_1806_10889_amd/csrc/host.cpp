@@ -152,20 +152,27 @@ struct Edge {
 
 std::vector<Edge> lattice_edges(int lattice, int nx, int ny)
 {
+    // edges in (colour class, first cell) order, generated in that order:
+    // class 2d + parity holds the edges of forward direction d whose first
+    // cell has that parity of x (d = 0) or of y (d > 0)
     const int nfwd = lattice == TISSUE_LATTICE_SQUARE ? 2 : 3;
     std::vector<Edge> out;
-    for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x)
-            for (int d = 0; d < nfwd; ++d) {
-                const int *off = lattice == TISSUE_LATTICE_SQUARE ? kSquareDir[d] : kHexDir[d];
-                const int X = x + off[0], Y = y + off[1];
-                if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
-                const int parity = (d == 0 ? x : y) & 1;
-                out.push_back(Edge{2 * d + parity, y * nx + x, Y * nx + X, d});
+    out.reserve((size_t)nx * ny * nfwd);
+    for (int d = 0; d < nfwd; ++d) {
+        const int *off = lattice == TISSUE_LATTICE_SQUARE ? kSquareDir[d] : kHexDir[d];
+        for (int parity = 0; parity < 2; ++parity)
+            for (int y = 0; y < ny; ++y) {
+                if (d != 0 && (y & 1) != parity) continue;
+                const int Y = y + off[1];
+                if (Y < 0 || Y >= ny) continue;
+                const int x0 = d == 0 ? parity : 0, dx = d == 0 ? 2 : 1;
+                for (int x = x0; x < nx; x += dx) {
+                    const int X = x + off[0];
+                    if (X < 0 || X >= nx) continue;
+                    out.push_back(Edge{2 * d + parity, y * nx + x, Y * nx + X, d});
+                }
             }
-    std::sort(out.begin(), out.end(), [](const Edge &a, const Edge &b) {
-        return a.colour != b.colour ? a.colour < b.colour : a.i < b.i;
-    });
+    }
     return out;
 }
 
@@ -398,26 +405,44 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     }
     if (nvox * (uint64_t)S >= (1ull << 31)) return fail(TISSUE_EINVAL, "too many voxels");
     p.nvox = (uint32_t)nvox;
-    for (uint64_t i = 0; i < nvox * S; ++i)
-        if (d->init_counts[i] < 0 || d->init_counts[i] >= TISSUE_COUNT_LIMIT)
-            return fail(TISSUE_EINVAL, "init_counts must be in [0, 2^26)");
+    {
+        // (a negative count, taken unsigned, is at or past the limit too)
+        uint32_t out_of_range = 0;
+        for (uint64_t i = 0; i < nvox * S; ++i)
+            out_of_range |= (uint32_t)((uint32_t)d->init_counts[i] >= (uint32_t)TISSUE_COUNT_LIMIT);
+        if (out_of_range) return fail(TISSUE_EINVAL, "init_counts must be in [0, 2^26)");
+    }
 
     // chi: cells grouped by leaf count P (largest cells first); work items
     // are cut per launch mode when a launch plan is made
-    std::map<std::pair<int, int>, std::vector<int32_t>> by_p;  // (P, network) -> cells
+    // classes (P, network) in order of decreasing P, then increasing
+    // network; each class's cells in increasing order (a counting sort)
+    constexpr int kLogP = 7;  // P = 1, 2, ..., 64
+    const int nm = 1 + (int)d->n_models;
+    std::vector<uint32_t> cls(p.ncell), n_in((size_t)kLogP * nm, 0);
     for (uint32_t c = 0; c < p.ncell; ++c) {
         const int m = d->cell_model ? d->cell_model[c] : 0;
         if (m > (int)d->n_models) return fail(TISSUE_EINVAL, "cell_model entries must be <= n_models");
         p.cell_model[c] = (uint8_t)m;
-        by_p[{pow2_at_least(p.wh[2 * c] * p.wh[2 * c + 1]), -m}].push_back((int32_t)c);
+        int lp = 0;
+        while ((1 << lp) < p.wh[2 * c] * p.wh[2 * c + 1]) ++lp;
+        cls[c] = (uint32_t)((kLogP - 1 - lp) * nm + m);
+        n_in[cls[c]]++;
     }
-    for (auto it = by_p.rbegin(); it != by_p.rend(); ++it) {
+    std::vector<uint32_t> at(n_in.size() + 1, 0);
+    for (size_t k = 0; k < n_in.size(); ++k) at[k + 1] = at[k] + n_in[k];
+    p.cell_list.resize(p.ncell);
+    {
+        std::vector<uint32_t> put(at.begin(), at.end() - 1);
+        for (uint32_t c = 0; c < p.ncell; ++c) p.cell_list[put[cls[c]]++] = (int32_t)c;
+    }
+    for (size_t k = 0; k < n_in.size(); ++k) {
+        if (!n_in[k]) continue;
         ChiGroupHost g;
-        g.P = it->first.first;
-        g.model = -it->first.second;
-        g.first = (uint32_t)p.cell_list.size();
-        g.count = (uint32_t)it->second.size();
-        p.cell_list.insert(p.cell_list.end(), it->second.begin(), it->second.end());
+        g.P = 1 << (kLogP - 1 - (int)(k / (size_t)nm));
+        g.model = (int)(k % (size_t)nm);
+        g.first = at[k];
+        g.count = n_in[k];
         p.chi.push_back(g);
         // room for the largest cut of the class, whichever the launch plan
         // picks: lane layout, rows of max(16, P) or max(32, P) lanes, or the
@@ -432,10 +457,11 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     // edges, face groups, S passes
     const int nd = p.lattice == TISSUE_LATTICE_SQUARE ? 4 : 6;
     if (p.has_s) {
-        std::map<int, std::vector<std::vector<int>>> faces;  // (w*16+h) -> [nd] groups
+        // per mesh (key w*16+h) its [nd] face groups (empty: mesh not present)
+        std::vector<std::vector<std::vector<int>>> faces(16 * 16);
         for (uint32_t c = 0; c < p.ncell; ++c) {
             const int key = p.wh[2 * c] * 16 + p.wh[2 * c + 1];
-            if (faces.count(key)) continue;
+            if (!faces[key].empty()) continue;
             const std::vector<int> ring = membrane_ring(p.wh[2 * c], p.wh[2 * c + 1]);
             std::vector<std::vector<int>> g(nd);
             for (int dd = 0; dd < nd; ++dd) g[dd] = face_voxels(ring, nd, dd);
@@ -470,9 +496,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
         std::vector<uint8_t> level(E.size(), 0);
         if (!p.disjoint) {
             std::vector<uint8_t> last(p.nvox, 0);  // highest pass + 1 that touched a voxel
-            std::vector<size_t> by_class(E.size());
-            for (size_t e = 0; e < E.size(); ++e) by_class[e] = e;  // already in (colour, i) order
-            for (size_t e : by_class) {
+            for (size_t e = 0; e < E.size(); ++e) {  // E is in (colour, i) order
                 const Edge &ed = E[e];
                 int lv = 0;
                 for (int v : group_i(ed)) lv = std::max(lv, (int)last[p.vox_off[ed.i] + v]);
@@ -484,20 +508,24 @@ int build_plan(const tissue_desc_t *d, Plan &p)
                 for (int v : group_j(ed)) last[p.vox_off[ed.j] + v] = (uint8_t)(lv + 1);
             }
         }
-        // record order: by pass, then by first cell and direction, so that the
-        // edges around a cell are processed close together and its counts
-        // are fetched into a cache once
-        std::vector<uint32_t> ord(E.size());
-        for (size_t e = 0; e < E.size(); ++e) ord[e] = (uint32_t)e;
-        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
-            if (level[a] != level[b]) return level[a] < level[b];
-            return E[a].i != E[b].i ? E[a].i < E[b].i : E[a].d < E[b].d;
-        });
         int n_levels = 0;
         for (size_t e = 0; e < E.size(); ++e) n_levels = std::max(n_levels, (int)level[e] + 1);
         p.pass_start.assign(n_levels + 1, 0);
         for (size_t e = 0; e < E.size(); ++e) p.pass_start[level[e] + 1]++;
         for (int l = 0; l < n_levels; ++l) p.pass_start[l + 1] += p.pass_start[l];
+        // record order: by pass, then by first cell and direction, so that the
+        // edges around a cell are processed close together and its counts
+        // are fetched into a cache once (a counting sort by pass of the
+        // edges taken in (first cell, direction) order)
+        const int nfwd = p.lattice == TISSUE_LATTICE_SQUARE ? 2 : 3;
+        std::vector<int32_t> by_cell((size_t)p.ncell * nfwd, -1);
+        for (size_t e = 0; e < E.size(); ++e) by_cell[(size_t)E[e].i * nfwd + E[e].d] = (int32_t)e;
+        std::vector<uint32_t> ord(E.size());
+        {
+            std::vector<uint32_t> at(p.pass_start.begin(), p.pass_start.end() - 1);
+            for (const int32_t e : by_cell)
+                if (e >= 0) ord[at[level[e]]++] = (uint32_t)e;
+        }
         for (size_t k = 0; k < ord.size(); ++k) {
             const uint32_t e = ord[k];
             const Edge &ed = E[e];
