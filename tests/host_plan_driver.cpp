@@ -9,7 +9,8 @@
 // launchers and the network compiler from the library.  Besides running
 // clean it checks what a plan promises: every cell in exactly one work item
 // of every launch plan, items within their launch's cells per item, regroup
-// segments covering their class, required bytes equal to the layout.
+// segments covering their class, required bytes equal to the layout, the
+// lattice's edges and the records, cells and classes in their stated orders.
 #include "../paper_1806_10889_amd/csrc/host.cpp"
 
 #include <cstdio>
@@ -165,6 +166,54 @@ void check_launches(const Plan &p, const std::vector<ChiItem> &items,
     check(items.size() <= p.n_chi_items, "items over the plan's room", trial);
 }
 
+// The lattice's edges, listed by brute force over (cell, direction) and
+// sorted by (colour class, first cell), against lattice_edges, which makes
+// them in that order directly.
+void check_edges(int lattice, int nx, int ny, int trial)
+{
+    const int nfwd = lattice == TISSUE_LATTICE_SQUARE ? 2 : 3;
+    std::vector<Edge> want;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int d = 0; d < nfwd; ++d) {
+                const int *off = lattice == TISSUE_LATTICE_SQUARE ? kSquareDir[d] : kHexDir[d];
+                const int X = x + off[0], Y = y + off[1];
+                if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
+                want.push_back(Edge{2 * d + ((d == 0 ? x : y) & 1), y * nx + x, Y * nx + X, d});
+            }
+    std::sort(want.begin(), want.end(), [](const Edge &a, const Edge &b) {
+        return a.colour != b.colour ? a.colour < b.colour : a.i < b.i;
+    });
+    const std::vector<Edge> got = lattice_edges(lattice, nx, ny);
+    bool same = got.size() == want.size();
+    for (size_t k = 0; same && k < got.size(); ++k)
+        same = got[k].colour == want[k].colour && got[k].i == want[k].i && got[k].j == want[k].j &&
+               got[k].d == want[k].d;
+    check(same, "lattice edges not the sorted brute-force list", trial);
+}
+
+// Records within a pass in (first cell, direction) order; cells of a leaf
+// class in increasing order, classes by decreasing P, then network.
+void check_orders(const Plan &p, int trial)
+{
+    if (p.has_s && p.nedge) {
+        const std::vector<Edge> E = lattice_edges((int)p.lattice, (int)p.nx, (int)p.ny);
+        for (size_t l = 0; l + 1 < p.pass_start.size(); ++l)
+            for (uint32_t k = p.pass_start[l] + 1; k < p.pass_start[l + 1]; ++k) {
+                const Edge &a = E[p.edges[k - 1].id], &b = E[p.edges[k].id];
+                check(a.i < b.i || (a.i == b.i && a.d < b.d), "records out of (cell, direction) order", trial);
+            }
+    }
+    for (size_t k = 0; k < p.chi.size(); ++k) {
+        const ChiGroupHost &g = p.chi[k];
+        for (uint32_t q = g.first + 1; q < g.first + g.count; ++q)
+            check(p.cell_list[q - 1] < p.cell_list[q], "class cells out of order", trial);
+        if (k)
+            check(p.chi[k - 1].P > g.P || (p.chi[k - 1].P == g.P && p.chi[k - 1].model < g.model),
+                  "classes out of order", trial);
+    }
+}
+
 // The S passes keep every pair of edges that share a voxel in colour-class
 // order (an earlier class's edge in an earlier pass), every edge is in one
 // pass, and the records' ranks are a permutation of the edge ranks.
@@ -220,6 +269,9 @@ int main()
         const Plan &p = t->plan;
         check(tissue_required_bytes(&c.d) == p.bytes, "required bytes", trial);
         check_passes(p, trial);
+        check_orders(p, trial);
+        check_edges(TISSUE_LATTICE_SQUARE, (int)p.nx, (int)p.ny, trial);
+        check_edges(TISSUE_LATTICE_HEX, (int)p.nx, (int)p.ny, trial);
         if (!p.disjoint) ++overlapping;
         check(p.cell_list.size() == p.ncell, "cell list", trial);
         for (int mode = kModeLane; mode <= kModeRowWide; ++mode)
