@@ -89,71 +89,71 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 COUNTERS = {
     "plain": {
-        "digest": "8666236603afc6cedeac02cb2440e57ef5f426ca",
+        "digest": "d083c3fba3ac4e63b14a34ad0e4cdd16a887c349",
         "profile": "profiles/chi_row_plain_hex64x64_4x4.md",
         "chi_events_per_step": 744850.5,
         "kernels": {
             "tissue_chi_row": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 170.666,
+                "avg_us": 169.151,
                 "sq_insts_valu": 46678900.0,
-                "fetch_kib": 934.205,
+                "fetch_kib": 934.19,
                 "write_kib": 1376.0
             }
         }
     },
     "batched": {
-        "digest": "8666236603afc6cedeac02cb2440e57ef5f426ca",
+        "digest": "d083c3fba3ac4e63b14a34ad0e4cdd16a887c349",
         "profile": "profiles/chi_lane16_batched_512_tissues.md",
         "chi_events_per_step": 1298376166.0,
         "kernels": {
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 19858.718,
-                "sq_insts_valu": 10691100000.0,
-                "fetch_kib": 652397.0,
-                "write_kib": 1058580.0
+                "avg_us": 19842.893,
+                "sq_insts_valu": 10691200000.0,
+                "fetch_kib": 652387.0,
+                "write_kib": 1058630.0
             }
         }
     },
     "uneven": {
-        "digest": "8666236603afc6cedeac02cb2440e57ef5f426ca",
+        "digest": "d083c3fba3ac4e63b14a34ad0e4cdd16a887c349",
         "profile": "profiles/chi_classes_uneven_hex256x256.md",
         "chi_events_per_step": 22521846.2,
         "kernels": {
             "tissue_chi_row64": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1230.533,
-                "sq_insts_valu": 327009000.0,
-                "fetch_kib": 878.953,
-                "write_kib": 1222.37
+                "avg_us": 1223.51,
+                "sq_insts_valu": 327006000.0,
+                "fetch_kib": 878.939,
+                "write_kib": 1222.39
             },
             "tissue_chi_lane16x4": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1511.355,
-                "sq_insts_valu": 91576800.0,
-                "fetch_kib": 2410.8,
-                "write_kib": 3341.37
+                "avg_us": 1508.983,
+                "sq_insts_valu": 91578500.0,
+                "fetch_kib": 2410.74,
+                "write_kib": 3341.36
             },
             "tissue_chi_lane16x2": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1037.068,
-                "sq_insts_valu": 141732000.0,
-                "fetch_kib": 7337.58,
+                "avg_us": 1032.034,
+                "sq_insts_valu": 141731000.0,
+                "fetch_kib": 7337.78,
                 "write_kib": 10512.1
             },
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 536.812,
-                "sq_insts_valu": 74517400.0,
-                "fetch_kib": 8808.46,
-                "write_kib": 11674.2
+                "avg_us": 535.505,
+                "sq_insts_valu": 74520400.0,
+                "fetch_kib": 8808.42,
+                "write_kib": 11674.4
             },
             "tissue_chi_lane": {
                 "dispatches_per_step": 3.0,
-                "avg_us": 9.015,
+                "avg_us": 9.175,
                 "sq_insts_valu": 27655.0,
-                "fetch_kib": 29.7541,
+                "fetch_kib": 29.7481,
                 "write_kib": 16.0938
             }
         }
