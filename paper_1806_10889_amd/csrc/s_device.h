@@ -146,6 +146,10 @@ __device__ __forceinline__ void s_edge_fixed(int32_t *counts, long long gi, long
         }
         ++ev;
     }
+    // an edge without events leaves its face counts as they were: nothing
+    // to write (most edges take no event in a step), so their lines stay
+    // clean in the cache
+    if (ev == 0) return;
 #pragma unroll
     for (int a = 0; a < MA; ++a) {
         const long long g = (gi + A[a]) * S;
@@ -355,7 +359,7 @@ __device__ __forceinline__ void s_item(const DevTissue *const *tbl, const SItem 
         }
 #pragma unroll
         for (int a = 0; a < kMaxFace; ++a)
-            if (fixed == 0 && a < mA) {
+            if (fixed == 0 && ev != 0 && a < mA) {  // (no events: nothing changed)
                 const long long g = (gi + A[a]) * S;
                 if (!first_order) counts[g + sp0] = fa[0][a][lane];
                 counts[g + sp1] = fa[1][a][lane];
@@ -363,7 +367,7 @@ __device__ __forceinline__ void s_item(const DevTissue *const *tbl, const SItem 
             }
 #pragma unroll
         for (int b = 0; b < kMaxFace; ++b)
-            if (fixed == 0 && b < mB) {
+            if (fixed == 0 && ev != 0 && b < mB) {
                 const long long g = (gj + B[b]) * S;
                 if (!first_order) counts[g + sp0] = fb[0][b][lane];
                 counts[g + sp1] = fb[1][b][lane];
