@@ -89,71 +89,71 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 COUNTERS = {
     "plain": {
-        "digest": "d083c3fba3ac4e63b14a34ad0e4cdd16a887c349",
+        "digest": "ace288db4a55ca299c5a9883877a0cd74d062832",
         "profile": "profiles/chi_row_plain_hex64x64_4x4.md",
         "chi_events_per_step": 744850.5,
         "kernels": {
             "tissue_chi_row": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 169.151,
+                "avg_us": 170.635,
                 "sq_insts_valu": 46678900.0,
-                "fetch_kib": 934.19,
+                "fetch_kib": 934.193,
                 "write_kib": 1376.0
             }
         }
     },
     "batched": {
-        "digest": "d083c3fba3ac4e63b14a34ad0e4cdd16a887c349",
+        "digest": "ace288db4a55ca299c5a9883877a0cd74d062832",
         "profile": "profiles/chi_lane16_batched_512_tissues.md",
         "chi_events_per_step": 1298376166.0,
         "kernels": {
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 19842.893,
+                "avg_us": 19838.114,
                 "sq_insts_valu": 10691200000.0,
-                "fetch_kib": 652387.0,
-                "write_kib": 1058630.0
+                "fetch_kib": 652401.0,
+                "write_kib": 1058670.0
             }
         }
     },
     "uneven": {
-        "digest": "d083c3fba3ac4e63b14a34ad0e4cdd16a887c349",
+        "digest": "ace288db4a55ca299c5a9883877a0cd74d062832",
         "profile": "profiles/chi_classes_uneven_hex256x256.md",
         "chi_events_per_step": 22521846.2,
         "kernels": {
             "tissue_chi_row64": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1223.51,
-                "sq_insts_valu": 327006000.0,
-                "fetch_kib": 878.939,
-                "write_kib": 1222.39
+                "avg_us": 1226.925,
+                "sq_insts_valu": 327001000.0,
+                "fetch_kib": 876.923,
+                "write_kib": 1222.38
             },
             "tissue_chi_lane16x4": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1508.983,
-                "sq_insts_valu": 91578500.0,
-                "fetch_kib": 2410.74,
-                "write_kib": 3341.36
+                "avg_us": 1510.274,
+                "sq_insts_valu": 91577500.0,
+                "fetch_kib": 2410.8,
+                "write_kib": 3341.35
             },
             "tissue_chi_lane16x2": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1032.034,
-                "sq_insts_valu": 141731000.0,
-                "fetch_kib": 7337.78,
+                "avg_us": 1038.28,
+                "sq_insts_valu": 141730000.0,
+                "fetch_kib": 7337.76,
                 "write_kib": 10512.1
             },
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 535.505,
-                "sq_insts_valu": 74520400.0,
-                "fetch_kib": 8808.42,
-                "write_kib": 11674.4
+                "avg_us": 534.544,
+                "sq_insts_valu": 74521200.0,
+                "fetch_kib": 8808.72,
+                "write_kib": 11674.3
             },
             "tissue_chi_lane": {
                 "dispatches_per_step": 3.0,
-                "avg_us": 9.175,
+                "avg_us": 9.239,
                 "sq_insts_valu": 27655.0,
-                "fetch_kib": 29.7481,
+                "fetch_kib": 29.7273,
                 "write_kib": 16.0938
             }
         }
