@@ -302,7 +302,28 @@ int build_model(int S, uint32_t n_reactions, const int32_t *reactants, const int
     return TISSUE_OK;
 }
 
-int build_plan(const tissue_desc_t *d, Plan &p)
+// The number of forward lattice edges of an nx x ny tissue (each counted
+// once): square +x and +y; hexagonal also the (-1, +1) diagonal.
+uint64_t lattice_edge_count(int lattice, uint64_t nx, uint64_t ny)
+{
+    const uint64_t n = (nx - 1) * ny + nx * (ny - 1);
+    return lattice == TISSUE_LATTICE_SQUARE ? n : n + (nx - 1) * (ny - 1);
+}
+
+// Room for the S work items: each pass's items are ceil(edges / 64), and
+// there are at most as many passes as colour classes (an edge of class k
+// is at most in pass k: edges of one class share no voxel), so the sum is
+// at most ceil(nedge / 64) + classes - 1.  Known before the passes are.
+size_t s_item_room(int lattice, uint64_t nedge)
+{
+    const int classes = lattice == TISSUE_LATTICE_SQUARE ? 4 : 6;
+    return nedge ? (size_t)((nedge + kWave - 1) / kWave) + (size_t)(classes - 1) : 0;
+}
+
+// with_edges false: everything but the edge records and the S passes (the
+// tissue's size in device memory needs only their counts, known in closed
+// form); tissue_required_bytes plans this way.
+int build_plan(const tissue_desc_t *d, Plan &p, bool with_edges = true)
 {
     if (!d) return fail(TISSUE_EINVAL, "null descriptor");
     if (d->abi_version != TISSUE_ABI_VERSION) return fail(TISSUE_EINVAL, "abi_version mismatch");
@@ -456,7 +477,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
 
     // edges, face groups, S passes
     const int nd = p.lattice == TISSUE_LATTICE_SQUARE ? 4 : 6;
-    if (p.has_s) {
+    if (p.has_s) p.nedge = (uint32_t)lattice_edge_count((int)p.lattice, p.nx, p.ny);
+    if (p.has_s && with_edges) {
         // per mesh (key w*16+h) its [nd] face groups (empty: mesh not present)
         std::vector<std::vector<std::vector<int>>> faces(16 * 16);
         for (uint32_t c = 0; c < p.ncell; ++c) {
@@ -475,7 +497,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
             faces[key] = std::move(g);
         }
         const std::vector<Edge> E = lattice_edges((int)p.lattice, (int)p.nx, (int)p.ny);
-        p.nedge = (uint32_t)E.size();
+        if (E.size() != p.nedge) return fail(TISSUE_EINVAL, "internal: lattice edge count");
         p.edges.resize(E.size());
         auto group_i = [&](const Edge &ed) -> const std::vector<int> & {
             return faces[p.wh[2 * ed.i] * 16 + p.wh[2 * ed.i + 1]][ed.d];
@@ -558,6 +580,8 @@ int build_plan(const tissue_desc_t *d, Plan &p)
             p.s_passes.push_back(std::move(pass));
         }
         for (auto &ps : p.s_passes) p.n_s_items += ps.size();
+        if (p.n_s_items > s_item_room((int)p.lattice, p.nedge))
+            return fail(TISSUE_EINVAL, "internal: S work items over their room");
     }
 
     // device layout
@@ -579,7 +603,7 @@ int build_plan(const tissue_desc_t *d, Plan &p)
     p.off_edges = take((size_t)p.nedge * sizeof(EdgeRec));
     p.off_models = take(p.models.size() * sizeof(DevModel));
     p.off_chi = take(p.n_chi_items * sizeof(ChiItem));
-    p.off_s = take(p.n_s_items * sizeof(SItem));
+    p.off_s = take(s_item_room((int)p.lattice, p.nedge) * sizeof(SItem));
     p.off_ctl = take(64);  // stats[3] u64, flags[2] u32
     p.off_lq = take(kLaunchQueueBytes);  // per-launch queue words of the chi launches
     p.off_load = take((size_t)p.ncell * 4);  // per-cell load: the regroup pass's key
@@ -1340,7 +1364,7 @@ int tissue_network_check(const tissue_desc_t *d)
 size_t tissue_required_bytes(const tissue_desc_t *d)
 {
     Plan p;
-    if (build_plan(d, p) != TISSUE_OK) return 0;
+    if (build_plan(d, p, false) != TISSUE_OK) return 0;
     return p.bytes;
 }
 
