@@ -108,7 +108,9 @@ def chain_estimate(problem: dict) -> float:
     at degree 3) times the largest cell's voxel count times dt."""
     p = problem
     S = int(p["n_species"])
-    x = np.asarray(p["init_counts"], np.float64).reshape(-1, S).mean(axis=0)
+    c = np.asarray(p["init_counts"]).reshape(-1, S)
+    # (per-species column sums: much faster than a strided reduction over axis 0)
+    x = np.array([float(c[:, s].sum(dtype=np.int64)) for s in range(S)]) / max(c.shape[0], 1)
     a = 0.0
     for r, (ra, rb) in enumerate(np.asarray(p["reactants"], np.int64).reshape(-1, 2)):
         if ra < 0 and rb < 0:

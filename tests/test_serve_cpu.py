@@ -115,14 +115,16 @@ def test_budget_from_free_memory_binds(oracle_lib):
 def test_ebusy_when_the_waiting_queue_is_full(oracle_lib):
     """submit answers EBUSY while the waiting queue is full (a request that
     cannot be admitted now: the budget holds one at a time); the replay
-    tries again later, and every request completes."""
+    tries again later, and every request completes.  Ticks take 50 ms on a
+    fake clock and requests arrive 10 ms apart, so the queue fills."""
+    clock = FakeClock()
     reqs = _requests(6)
-    be = OracleBackend(oracle_lib)
+    be = TickBackend(oracle_lib, clock, 0.05)
     one = max(be.required_bytes(r.problem) for r in reqs)
-    srv = serve.Server(be, max_bytes=one, quantum=2, max_waiting=1)
+    srv = serve.Server(be, max_bytes=one, quantum=2, max_waiting=1, clock=clock, sleep=clock.sleep)
     assert srv.submit(reqs[0]) == serve.OK
     assert srv.submit(reqs[1]) == serve.EBUSY
-    st, done = srv.run(reqs, real_time=False)
+    st, done = srv.run(reqs, real_time=True)
     assert st.completed == 6 and st.busy_retries > 0 and be.live == {}
     assert sorted(r.rid for r in done) == list(range(6))
 
@@ -161,6 +163,23 @@ class FakeClock:
 
     def sleep(self, s):
         self.t += s
+
+
+class TickBackend(OracleBackend):
+    """Every tick takes tick_s on a fake clock."""
+
+    def __init__(self, oracle_lib, clock, tick_s):
+        super().__init__(oracle_lib)
+        self.clock = clock
+        self.tick_s = tick_s
+        self.until = 0.0
+
+    def step(self, lane, handles, dt, n, finishing=()):
+        super().step(lane, handles, dt, n, finishing)
+        self.until = self.clock.t + self.tick_s
+
+    def busy(self, lane):
+        return self.clock.t < self.until
 
 
 def test_tick_deadline_fails_the_requests_and_goes_on(oracle_lib):
