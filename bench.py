@@ -89,71 +89,71 @@ FETCH_SCALE = 262144.0 / 131085.0
 WRITE_SCALE = 262144.0 / 262144.0
 COUNTERS = {
     "plain": {
-        "digest": "ace288db4a55ca299c5a9883877a0cd74d062832",
+        "digest": "5ae5c01a1874fef8f7ed5afd81ee266678ffe815",
         "profile": "profiles/chi_row_plain_hex64x64_4x4.md",
         "chi_events_per_step": 744850.5,
         "kernels": {
             "tissue_chi_row": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 170.635,
+                "avg_us": 168.637,
                 "sq_insts_valu": 46678900.0,
-                "fetch_kib": 934.193,
+                "fetch_kib": 934.241,
                 "write_kib": 1376.0
             }
         }
     },
     "batched": {
-        "digest": "ace288db4a55ca299c5a9883877a0cd74d062832",
+        "digest": "5ae5c01a1874fef8f7ed5afd81ee266678ffe815",
         "profile": "profiles/chi_lane16_batched_512_tissues.md",
         "chi_events_per_step": 1298376166.0,
         "kernels": {
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 19838.114,
-                "sq_insts_valu": 10691200000.0,
-                "fetch_kib": 652401.0,
-                "write_kib": 1058670.0
+                "avg_us": 19870.414,
+                "sq_insts_valu": 10691100000.0,
+                "fetch_kib": 652282.0,
+                "write_kib": 1058540.0
             }
         }
     },
     "uneven": {
-        "digest": "ace288db4a55ca299c5a9883877a0cd74d062832",
+        "digest": "5ae5c01a1874fef8f7ed5afd81ee266678ffe815",
         "profile": "profiles/chi_classes_uneven_hex256x256.md",
         "chi_events_per_step": 22521846.2,
         "kernels": {
             "tissue_chi_row64": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1226.925,
-                "sq_insts_valu": 327001000.0,
-                "fetch_kib": 876.923,
+                "avg_us": 1231.577,
+                "sq_insts_valu": 326999000.0,
+                "fetch_kib": 876.96,
                 "write_kib": 1222.38
             },
             "tissue_chi_lane16x4": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1510.274,
-                "sq_insts_valu": 91577500.0,
-                "fetch_kib": 2410.8,
-                "write_kib": 3341.35
+                "avg_us": 1513.735,
+                "sq_insts_valu": 91578300.0,
+                "fetch_kib": 2410.94,
+                "write_kib": 3341.36
             },
             "tissue_chi_lane16x2": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 1038.28,
+                "avg_us": 1036.49,
                 "sq_insts_valu": 141730000.0,
-                "fetch_kib": 7337.76,
+                "fetch_kib": 7338.0,
                 "write_kib": 10512.1
             },
             "tissue_chi_lane16": {
                 "dispatches_per_step": 1.0,
-                "avg_us": 534.544,
-                "sq_insts_valu": 74521200.0,
-                "fetch_kib": 8808.72,
-                "write_kib": 11674.3
+                "avg_us": 535.785,
+                "sq_insts_valu": 74519500.0,
+                "fetch_kib": 8808.59,
+                "write_kib": 11674.4
             },
             "tissue_chi_lane": {
                 "dispatches_per_step": 3.0,
-                "avg_us": 9.239,
+                "avg_us": 9.303,
                 "sq_insts_valu": 27655.0,
-                "fetch_kib": 29.7273,
+                "fetch_kib": 29.7576,
                 "write_kib": 16.0938
             }
         }
