@@ -333,9 +333,10 @@ def run_single(args, torch, T, p, leg, sims, warmup):
 def event_chains(args, T, p, cfg):
     """The latency side of the chi launch: each cell's events in a step form
     one dependent chain, and a launch lasts as long as its busiest cell's
-    chain.  A traced simulation over the first chain_steps steps (eager,
-    HIP events around every launch) gives, per step, the busiest cell's and
-    the mean cell's events, and the time per event along the busiest chain."""
+    chain.  A traced simulation over the first chain_steps steps (by default
+    the whole horizon; eager, HIP events around every launch) gives, per
+    step, the busiest cell's and the mean cell's events, and the time per
+    event along the busiest chain."""
     import numpy as np
     n = min(args.chain_steps, p["n_steps"])
     t = T.Tissue(p, device="cuda:0", trace_steps=n)
@@ -351,8 +352,9 @@ def event_chains(args, T, p, cfg):
     if tm["chi_launches"] != n:
         return None, basis  # several chi launches per step: no single chain per launch
     launch_ms = tm["chi_ms"] / n
+    mean = float(ce.mean())
     return {"steps": n, "busiest_cell_events_per_step": busiest,
-            "mean_cell_events_per_step": float(ce.mean()),
+            "mean_cell_events_per_step": mean, "busiest_over_mean": busiest / max(mean, 1e-12),
             "avg_launch_ms": launch_ms,
             "ns_per_event_on_busiest_chain": launch_ms * 1e6 / max(busiest, 1.0)}, basis
 
@@ -894,8 +896,9 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--roofline-steps", type=int, default=0,
                     help="steps of the eagerly timed roofline pass (0: the whole horizon)")
-    ap.add_argument("--chain-steps", type=int, default=200,
-                    help="steps of the traced pass that measures the busiest cell's event chain (0: skip)")
+    ap.add_argument("--chain-steps", type=int, default=1 << 30,
+                    help="steps of the traced pass that measures the busiest cell's event chain "
+                         "(at most the horizon, the default; 0: skip)")
     ap.add_argument("--dt-replicas", type=int, default=16384)
     ap.add_argument("--dt-T", type=float, default=20.0)
     ap.add_argument("--leg", choices=["all", "plain", "tiny", "uneven", "batched", "serving", "dt",
